@@ -1,0 +1,183 @@
+/*
+ * gfnc.h -- GF(2^n) random linear network coding on AMD Instinct MI355X (gfx950).
+ *
+ * A C ABI over hand-written HIP kernels.  The operations follow
+ * Guenther, Appel, Carle, "Galois Field Arithmetics for Linear Network Coding
+ * using AVX 512 Instruction Set Extensions" (arXiv 1909.02871):
+ *
+ *   - a packet of l bits is a sequence of M = l/n words of n bits, each an
+ *     element of GF(q), q = 2^n, n in {1, 2, 4, 8}                 (Sec. II)
+ *   - encoding: a coded packet is the sum over the generation's N source
+ *     packets of c_i times packet i, i.e. a matrix-vector product  (Sec. II, Eq. 1)
+ *   - madd: multiply a region by a constant and add (XOR) it into an
+ *     accumulator region; c = 0 is a no-op, c = 1 a plain XOR      (Sec. II, Sec. IV)
+ *   - decoding (Sec. I mentions that a generation can fail to decode) is
+ *     Gauss-Jordan elimination of the coefficient matrix.
+ *
+ * Field polynomials (the paper names none): GF(4) x^2+x+1, GF(16) x^4+x+1,
+ * GF(256) x^8+x^4+x^3+x^2+1; GF(2) multiplication is AND.
+ *
+ * Conventions for every call
+ *   - Pointers named d_* or documented as "device" are device memory (e.g.
+ *     hipMalloc'd or a torch CUDA tensor's data pointer); the caller owns
+ *     them.  Host arrays are documented as such.
+ *   - Payload is uint8 bytes holding 8/n words each; word k of a byte is
+ *     bits [n*k, n*k+n).  Coefficients are one field element per byte (< q).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Every compute
+ *     call only enqueues work on `stream` and returns; results are visible
+ *     after the stream is synchronised.
+ *   - Return value: GF_OK (0) or a negative GF_E* code.  Argument errors are
+ *     detected before anything is enqueued; nothing is written then.
+ *   - Lengths are in bytes; any length >= 0 and any alignment is accepted
+ *     (16-byte-aligned rows take the fast path).  len = 0 is a no-op.
+ */
+#ifndef GFNC_H
+#define GFNC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Field selector: the value is the number of bits per word, n. */
+typedef enum { GF_2 = 1, GF_4 = 2, GF_16 = 4, GF_256 = 8 } gf_field;
+
+enum {
+    GF_OK = 0,
+    GF_EINVAL = -1,      /* bad argument: field, coefficient >= q, size, null, overlap */
+    GF_ENOTINIT = -2,    /* library could not initialise its tables */
+    GF_EDEVICE = -3,     /* a HIP runtime call failed */
+    GF_ESINGULAR = -4,   /* coefficient matrix not invertible (from gf_decode_sync) */
+    GF_ENOMEM = -5,      /* device or host allocation failed (plan creation only) */
+    GF_ERANGE = -6       /* size above a documented limit */
+};
+
+/* Initialise the field tables on the current device.  Idempotent and
+ * thread-safe; called implicitly by every entry point.  Returns GF_OK or
+ * GF_EDEVICE. */
+int gf_init(void);
+
+/* Static text for a GF_* code. */
+const char *gf_strerror(int code);
+
+/* Largest generation size N accepted by encode and decode. */
+#define GF_MAX_N 256
+
+/* ----------------------------------------------------------- region ops
+ * madd (Sec. II; the shuffle kernel of Sec. IV-A, Algorithm 1):
+ *     y[j] := y[j] + c * x[j]   for every word of the len bytes.
+ * c = 0 enqueues nothing; c = 1 is a plain XOR.  y == x (exact alias) is
+ * allowed and gives (1 + c) * x; any other overlap is GF_EINVAL.
+ * y, x: device, len bytes each.  c < q (GF(2): c in {0, 1}). */
+int gf_region_madd(int field, uint8_t *y, const uint8_t *x, int c, size_t len, void *stream);
+
+/* y[j] := c * x[j] (y == x allowed, other overlap GF_EINVAL).  c = 0 zero-fills y. */
+int gf_region_mul(int field, uint8_t *y, const uint8_t *x, int c, size_t len, void *stream);
+
+/* One region of a batched madd.  y, x are device pointers. */
+typedef struct {
+    uint8_t *y;
+    const uint8_t *x;
+    uint64_t len;
+    uint32_t c;
+    uint32_t reserved;   /* must be 0 */
+} gf_region;
+
+/* Many independent madds (Sec. II) in one launch.
+ * d_regions: device array of `count` gf_region; every len <= max_len.
+ * Regions must not overlap one another (a region may alias its own x).
+ * The descriptors are not validated on the host (they live on the device);
+ * a coefficient >= q is treated as 0 by the kernel. */
+int gf_region_madd_batched(int field, const gf_region *d_regions, int count, size_t max_len,
+                           void *stream);
+
+/* --------------------------------------------------------------- encode
+ * Eq. (1) for K coding vectors at once:
+ *     Y[k][j] = sum_{i<N} C[k][i] * S[i][j],   k < K, j < len,
+ * a product of the K x N coefficient matrix with the generation.
+ * C: device, K x N row-major, one element per byte (entries >= q are an error
+ *    only if checked: the kernel reads them modulo nothing -- callers keep
+ *    them < q).
+ * S: device, N rows of len bytes, row i at S + i*ld_s (ld_s >= len).
+ * Y: device, K rows, row k at Y + k*ld_y (ld_y >= len); overwritten.
+ * Y must not overlap S or C.  1 <= N <= GF_MAX_N, K >= 0. */
+int gf_encode(int field, const uint8_t *C, int K, int N, const uint8_t *S, size_t ld_s,
+              uint8_t *Y, size_t ld_y, size_t len, void *stream);
+
+/* --------------------------------------------------------------- decode
+ * Gauss-Jordan decoding of one generation: S = C^-1 B.
+ * C: device, N x N coefficient rows of the N received coded packets.
+ * B: device, N coded packets, row i at B + i*ld_b.
+ * S: device output, row i at S + i*ld_s; written only if C is invertible.
+ * ws: device workspace of at least gf_decode_workspace(N) bytes.
+ * d_rank: device int (may be NULL); receives rank(C).  The call returns
+ * GF_OK once enqueued; rank < N means singular and S untouched.
+ * 1 <= N <= GF_MAX_N. */
+size_t gf_decode_workspace(int N);
+int gf_decode(int field, const uint8_t *C, int N, const uint8_t *B, size_t ld_b,
+              uint8_t *S, size_t ld_s, size_t len, void *ws, size_t ws_bytes,
+              int *d_rank, void *stream);
+
+/* Invert one N x N matrix: Cinv (device, N x N) := C^-1; *d_rank := rank(C).
+ * Cinv is written only if C is invertible.  Uses no workspace. */
+int gf_invert(int field, const uint8_t *C, int N, uint8_t *Cinv, int *d_rank, void *stream);
+
+/* ----------------------------------------------------- batched (plans)
+ * A plan describes many uneven generations once; launching it is a single
+ * persistent kernel (encode) or an elimination kernel plus a persistent
+ * apply kernel (decode).  Plans own their device schedule and workspace;
+ * creating one allocates and synchronises, launching one does neither. */
+typedef struct {
+    const uint8_t *C;   /* device, K x N */
+    const uint8_t *S;   /* device, N rows, ld_s apart */
+    uint8_t *Y;         /* device, K rows, ld_y apart */
+    uint32_t K, N;
+    uint64_t len, ld_s, ld_y;
+} gf_gen;
+
+typedef struct {
+    const uint8_t *C;   /* device, N x N */
+    const uint8_t *B;   /* device, N coded rows, ld_b apart */
+    uint8_t *S;         /* device, N decoded rows, ld_s apart */
+    uint32_t N, reserved;
+    uint64_t len, ld_b, ld_s;
+} gf_sys;
+
+/* Kernel schedule knobs.  Zero fields mean "autotuned". */
+typedef struct {
+    int form;          /* 0 auto, 1 table (VALU byte-permute), 2 bit-matrix MFMA */
+    int bytes_per_lane;/* 4, 8 or 16 */
+    int rows_per_block; /* coded packets accumulated per workgroup: 8, 16 or 32 */
+    int grid_blocks;   /* persistent workgroups; 0 = 8 per compute unit */
+} gf_tuning;
+
+typedef struct gf_plan gf_plan;
+
+/* gens: HOST array of `count` descriptors (pointers inside are device). */
+int gf_plan_encode(int field, const gf_gen *gens, int count, const gf_tuning *tune,
+                   gf_plan **out);
+/* sys: HOST array of `count` systems. */
+int gf_plan_decode(int field, const gf_sys *sys, int count, const gf_tuning *tune,
+                   gf_plan **out);
+/* Encode every generation of the plan in one persistent launch. */
+int gf_encode_batched(gf_plan *plan, void *stream);
+/* Decode every system: d_rank (device, `count` ints, may be NULL) gets each rank. */
+int gf_decode_batched(gf_plan *plan, int *d_rank, void *stream);
+/* Same work as the plan's batched call, replayed from a HIP graph captured on
+ * first use (d_rank as for gf_decode_batched; must be the same pointer on
+ * every replay of a decode plan). */
+int gf_plan_launch_graph(gf_plan *plan, int *d_rank, void *stream);
+/* The schedule the plan uses (after autotuning). */
+int gf_plan_tuning(const gf_plan *plan, gf_tuning *out);
+void gf_plan_destroy(gf_plan *plan);
+
+/* Per-generation launches of the same work (the unbatched baseline): one
+ * gf_encode per descriptor, on `stream`.  gens is a HOST array. */
+int gf_encode_each(int field, const gf_gen *gens, int count, const gf_tuning *tune, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

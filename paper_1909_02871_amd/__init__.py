@@ -1,0 +1,339 @@
+"""Python binding of ``libgfnc.so`` (the C ABI in ``include/gfnc.h``).
+
+GF(2^n) random linear network coding on MI355X: region multiply-add,
+encoding (a coefficient matrix times a generation of source packets) and
+Gauss-Jordan decoding, after Guenther, Appel and Carle, arXiv 1909.02871
+(Sec. II defines the operations; Sec. IV the table-lookup and
+bit-decomposition kernels they are computed with on CPUs).
+
+This module only marshals arguments: torch CUDA tensors supply device
+pointers and streams, every computation runs in the library's HIP kernels.
+If the library is missing or no GPU is present the calls raise; there is no
+CPU fallback.
+
+Names match the C entry points: ``gf_init``, ``gf_region_madd``,
+``gf_region_mul``, ``gf_region_madd_batched``, ``gf_encode``, ``gf_decode``,
+``gf_invert``, ``gf_plan_encode``/``gf_plan_decode`` with
+``gf_encode_batched``/``gf_decode_batched``/``gf_plan_launch_graph``, and
+``gf_encode_each``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence, Tuple
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgfnc.so")
+
+GF_2, GF_4, GF_16, GF_256 = 1, 2, 4, 8
+FIELDS = (GF_2, GF_4, GF_16, GF_256)
+GF_OK, GF_EINVAL, GF_ENOTINIT, GF_EDEVICE, GF_ESINGULAR, GF_ENOMEM, GF_ERANGE = 0, -1, -2, -3, -4, -5, -6
+GF_MAX_N = 256
+
+_lib = None
+
+
+class GFError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (what, strerror(code) if _lib else "error", code))
+
+
+class gf_region(C.Structure):
+    _fields_ = [("y", C.c_void_p), ("x", C.c_void_p), ("len", C.c_uint64), ("c", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+class gf_gen(C.Structure):
+    _fields_ = [("C", C.c_void_p), ("S", C.c_void_p), ("Y", C.c_void_p), ("K", C.c_uint32), ("N", C.c_uint32),
+                ("len", C.c_uint64), ("ld_s", C.c_uint64), ("ld_y", C.c_uint64)]
+
+
+class gf_sys(C.Structure):
+    _fields_ = [("C", C.c_void_p), ("B", C.c_void_p), ("S", C.c_void_p), ("N", C.c_uint32),
+                ("reserved", C.c_uint32), ("len", C.c_uint64), ("ld_b", C.c_uint64), ("ld_s", C.c_uint64)]
+
+
+class gf_tuning(C.Structure):
+    _fields_ = [("form", C.c_int), ("bytes_per_lane", C.c_int), ("rows_per_block", C.c_int),
+                ("grid_blocks", C.c_int)]
+
+
+_SIGS = {
+    "gf_init": (C.c_int, []),
+    "gf_strerror": (C.c_char_p, [C.c_int]),
+    "gf_region_madd": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_size_t, C.c_void_p]),
+    "gf_region_mul": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_size_t, C.c_void_p]),
+    "gf_region_madd_batched": (C.c_int, [C.c_int, C.c_void_p, C.c_int, C.c_size_t, C.c_void_p]),
+    "gf_encode": (C.c_int, [C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p,
+                            C.c_size_t, C.c_size_t, C.c_void_p]),
+    "gf_decode_workspace": (C.c_size_t, [C.c_int]),
+    "gf_decode": (C.c_int, [C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t,
+                            C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
+    "gf_invert": (C.c_int, [C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gf_plan_encode": (C.c_int, [C.c_int, C.POINTER(gf_gen), C.c_int, C.POINTER(gf_tuning),
+                                 C.POINTER(C.c_void_p)]),
+    "gf_plan_decode": (C.c_int, [C.c_int, C.POINTER(gf_sys), C.c_int, C.POINTER(gf_tuning),
+                                 C.POINTER(C.c_void_p)]),
+    "gf_encode_batched": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "gf_decode_batched": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gf_plan_launch_graph": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gf_plan_tuning": (C.c_int, [C.c_void_p, C.POINTER(gf_tuning)]),
+    "gf_plan_destroy": (None, [C.c_void_p]),
+    "gf_encode_each": (C.c_int, [C.c_int, C.POINTER(gf_gen), C.c_int, C.POINTER(gf_tuning), C.c_void_p]),
+}
+
+#: every symbol the header declares
+EXPORTS = tuple(_SIGS)
+
+
+def lib():
+    """Load ``libgfnc.so`` (building it first only if it does not exist)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _build
+            _build.build()
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().gf_strerror(code).decode()
+
+
+def _check(rc: int, what: str):
+    if rc != GF_OK:
+        raise GFError(rc, what)
+
+
+# ------------------------------------------------------------------ helpers
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("gfnc needs a ROCm GPU; torch.cuda.is_available() is False")
+    return torch
+
+
+def _stream(stream) -> Optional[int]:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _dev_u8(t, name: str):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.uint8:
+        raise TypeError("%s must be a CUDA uint8 tensor" % name)
+    return t
+
+
+def _rows(t, name: str) -> Tuple[int, int, int]:
+    """(rows, row length, leading dimension in bytes) of a 2-D uint8 tensor with unit inner stride."""
+    _dev_u8(t, name)
+    if t.dim() != 2 or (t.stride(1) != 1 and t.shape[1] > 1):
+        raise ValueError("%s must be 2-D with contiguous rows" % name)
+    return t.shape[0], t.shape[1], max(t.stride(0), t.shape[1])
+
+
+# ------------------------------------------------------------------ API
+
+def gf_init():
+    _torch()
+    _check(lib().gf_init(), "gf_init")
+
+
+def gf_region_madd(field: int, y, x, c: int, length: Optional[int] = None, stream=None):
+    """y += c * x over ``length`` bytes (default: all of x). In place on y."""
+    _dev_u8(y, "y"); _dev_u8(x, "x")
+    n = x.numel() if length is None else length
+    if n > x.numel() or n > y.numel():
+        raise ValueError("length exceeds a buffer")
+    _check(lib().gf_region_madd(field, y.data_ptr(), x.data_ptr(), c, n, _stream(stream)), "gf_region_madd")
+
+
+def gf_region_mul(field: int, y, x, c: int, length: Optional[int] = None, stream=None):
+    """y = c * x over ``length`` bytes (default: all of x)."""
+    _dev_u8(y, "y"); _dev_u8(x, "x")
+    n = x.numel() if length is None else length
+    if n > x.numel() or n > y.numel():
+        raise ValueError("length exceeds a buffer")
+    _check(lib().gf_region_mul(field, y.data_ptr(), x.data_ptr(), c, n, _stream(stream)), "gf_region_mul")
+
+
+def make_regions(regions: Sequence[Tuple[int, int, int, int]]):
+    """Device descriptor array for gf_region_madd_batched from (y_ptr, x_ptr, len, c) tuples."""
+    torch = _torch()
+    arr = (gf_region * len(regions))()
+    for i, (yp, xp, n, c) in enumerate(regions):
+        arr[i] = gf_region(yp, xp, n, c, 0)
+    host = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8)
+    return host.to("cuda")
+
+
+def gf_region_madd_batched(field: int, d_regions, count: int, max_len: int, stream=None):
+    _dev_u8(d_regions, "d_regions")
+    if d_regions.numel() < count * C.sizeof(gf_region):
+        raise ValueError("descriptor buffer too small")
+    _check(lib().gf_region_madd_batched(field, d_regions.data_ptr(), count, max_len, _stream(stream)),
+           "gf_region_madd_batched")
+
+
+def gf_encode(field: int, Cm, S, Y, length: Optional[int] = None, stream=None):
+    """Y[:K, :length] = Cm (K x N) * S (N rows) over GF(2^field)."""
+    K, N, _ = _rows(Cm, "C")
+    if not Cm.is_contiguous():
+        raise ValueError("C must be contiguous")
+    nS, lS, ld_s = _rows(S, "S")
+    nY, lY, ld_y = _rows(Y, "Y")
+    L = min(lS, lY) if length is None else length
+    if nS < N or nY < K or L > lS or L > lY:
+        raise ValueError("shape mismatch")
+    _check(lib().gf_encode(field, Cm.data_ptr(), K, N, S.data_ptr(), ld_s, Y.data_ptr(), ld_y, L,
+                           _stream(stream)), "gf_encode")
+
+
+def gf_decode_workspace(N: int) -> int:
+    return int(lib().gf_decode_workspace(N))
+
+
+def gf_decode(field: int, Cm, B, S, ws=None, d_rank=None, length: Optional[int] = None, stream=None):
+    """S = Cm^-1 B (enqueued; S untouched if Cm is singular). d_rank: CUDA int32 tensor of 1 or None."""
+    torch = _torch()
+    N, N2, _ = _rows(Cm, "C")
+    if N != N2 or not Cm.is_contiguous():
+        raise ValueError("C must be a contiguous N x N matrix")
+    nB, lB, ld_b = _rows(B, "B")
+    nS, lS, ld_s = _rows(S, "S")
+    L = min(lB, lS) if length is None else length
+    if nB < N or nS < N or L > lB or L > lS:
+        raise ValueError("shape mismatch")
+    if ws is None:
+        ws = torch.empty(gf_decode_workspace(N), dtype=torch.uint8, device=Cm.device)
+    rp = 0
+    if d_rank is not None:
+        if d_rank.dtype != torch.int32 or d_rank.device.type != "cuda":
+            raise TypeError("d_rank must be a CUDA int32 tensor")
+        rp = d_rank.data_ptr()
+    _check(lib().gf_decode(field, Cm.data_ptr(), N, B.data_ptr(), ld_b, S.data_ptr(), ld_s, L, ws.data_ptr(),
+                           ws.numel(), rp or None, _stream(stream)), "gf_decode")
+    return ws
+
+
+def gf_invert(field: int, Cm, Cinv, d_rank=None, stream=None):
+    N, N2, _ = _rows(Cm, "C")
+    if N != N2 or not Cm.is_contiguous() or not Cinv.is_contiguous() or tuple(Cinv.shape) != (N, N):
+        raise ValueError("C and Cinv must be contiguous N x N matrices")
+    rp = d_rank.data_ptr() if d_rank is not None else None
+    _check(lib().gf_invert(field, Cm.data_ptr(), N, Cinv.data_ptr(), rp, _stream(stream)), "gf_invert")
+
+
+def _tuning(t: Optional[dict]):
+    if t is None:
+        return None
+    return C.byref(gf_tuning(t.get("form", 0), t.get("bytes_per_lane", 0), t.get("rows_per_block", 0),
+                             t.get("grid_blocks", 0)))
+
+
+class Plan:
+    """A batched plan (encode or decode) over many uneven generations."""
+
+    def __init__(self, handle: int, kind: str, count: int, keep):
+        self._h = C.c_void_p(handle)
+        self.kind = kind
+        self.count = count
+        self._keep = keep   # tensors the plan points into
+
+    def tuning(self) -> dict:
+        t = gf_tuning()
+        _check(lib().gf_plan_tuning(self._h, C.byref(t)), "gf_plan_tuning")
+        return {"form": t.form, "bytes_per_lane": t.bytes_per_lane, "rows_per_block": t.rows_per_block,
+                "grid_blocks": t.grid_blocks}
+
+    def destroy(self):
+        if self._h:
+            lib().gf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def _gen_desc(Cm, S, Y, length=None) -> gf_gen:
+    K, N, _ = _rows(Cm, "C")
+    nS, lS, ld_s = _rows(S, "S")
+    nY, lY, ld_y = _rows(Y, "Y")
+    L = min(lS, lY) if length is None else length
+    if nS < N or nY < K or L > lS or L > lY or not Cm.is_contiguous():
+        raise ValueError("shape mismatch")
+    return gf_gen(Cm.data_ptr(), S.data_ptr(), Y.data_ptr(), K, N, L, ld_s, ld_y)
+
+
+def gf_plan_encode(field: int, gens: Sequence[tuple], tune: Optional[dict] = None) -> Plan:
+    """gens: (C, S, Y) or (C, S, Y, length) tensors per generation."""
+    arr = (gf_gen * len(gens))(*[_gen_desc(*g) for g in gens])
+    h = C.c_void_p()
+    _check(lib().gf_plan_encode(field, arr, len(gens), _tuning(tune), C.byref(h)), "gf_plan_encode")
+    return Plan(h.value, "encode", len(gens), list(gens))
+
+
+def gf_plan_encode_desc(field: int, arr, count: int, tune: Optional[dict] = None, keep=None) -> Plan:
+    """Plan from a ctypes array of gf_gen built by the caller."""
+    h = C.c_void_p()
+    _check(lib().gf_plan_encode(field, arr, count, _tuning(tune), C.byref(h)), "gf_plan_encode")
+    return Plan(h.value, "encode", count, keep)
+
+
+def gf_plan_decode(field: int, systems: Sequence[tuple], tune: Optional[dict] = None) -> Plan:
+    """systems: (C, B, S) or (C, B, S, length) tensors per system."""
+    descs = []
+    for s in systems:
+        Cm, B, S = s[:3]
+        length = s[3] if len(s) > 3 else None
+        N, N2, _ = _rows(Cm, "C")
+        nB, lB, ld_b = _rows(B, "B")
+        nS, lS, ld_s = _rows(S, "S")
+        L = min(lB, lS) if length is None else length
+        if N != N2 or nB < N or nS < N or L > lB or L > lS or not Cm.is_contiguous():
+            raise ValueError("shape mismatch")
+        descs.append(gf_sys(Cm.data_ptr(), B.data_ptr(), S.data_ptr(), N, 0, L, ld_b, ld_s))
+    return gf_plan_decode_desc(field, (gf_sys * len(descs))(*descs), len(descs), tune, list(systems))
+
+
+def gf_plan_decode_desc(field: int, arr, count: int, tune: Optional[dict] = None, keep=None) -> Plan:
+    h = C.c_void_p()
+    _check(lib().gf_plan_decode(field, arr, count, _tuning(tune), C.byref(h)), "gf_plan_decode")
+    return Plan(h.value, "decode", count, keep)
+
+
+def gf_encode_batched(plan: Plan, stream=None):
+    _check(lib().gf_encode_batched(plan._h, _stream(stream)), "gf_encode_batched")
+
+
+def gf_decode_batched(plan: Plan, d_rank=None, stream=None):
+    rp = d_rank.data_ptr() if d_rank is not None else None
+    _check(lib().gf_decode_batched(plan._h, rp, _stream(stream)), "gf_decode_batched")
+
+
+def gf_plan_launch_graph(plan: Plan, d_rank=None, stream=None):
+    rp = d_rank.data_ptr() if d_rank is not None else None
+    _check(lib().gf_plan_launch_graph(plan._h, rp, _stream(stream)), "gf_plan_launch_graph")
+
+
+def gf_encode_each(field: int, gens, count: Optional[int] = None, tune: Optional[dict] = None, stream=None):
+    """Per-generation launches (unbatched baseline). gens: ctypes gf_gen array or tensor tuples."""
+    if not isinstance(gens, C.Array):
+        gens = (gf_gen * len(gens))(*[_gen_desc(*g) for g in gens])
+    n = len(gens) if count is None else count
+    _check(lib().gf_encode_each(field, gens, n, _tuning(tune), _stream(stream)), "gf_encode_each")

@@ -1,0 +1,661 @@
+// The C ABI (include/gfnc.h): argument validation, device tables, plans for
+// the batched launches, and HIP-graph replay.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "../../include/gfnc.h"
+#include "gf_internal.h"
+
+using namespace gfnc;
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+struct DevState {
+    bool ready = false;
+    DevTables t{nullptr, nullptr};
+    int cus = 0;
+};
+
+std::mutex g_mu;
+DevState g_dev[kMaxDevices];
+
+int current_state(DevState **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return GF_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevState &d = g_dev[dev];
+    if (!d.ready) {
+        const HostTables &h = host_tables();
+        void *pt = nullptr, *iv = nullptr;
+        if (hipMalloc(&pt, sizeof h.ptab) != hipSuccess)
+            return GF_EDEVICE;
+        if (hipMalloc(&iv, sizeof h.inv) != hipSuccess) {
+            (void)hipFree(pt);
+            return GF_EDEVICE;
+        }
+        if (hipMemcpy(pt, h.ptab, sizeof h.ptab, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(iv, h.inv, sizeof h.inv, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(pt);
+            (void)hipFree(iv);
+            return GF_EDEVICE;
+        }
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        d.t.ptab = static_cast<uint32_t *>(pt);
+        d.t.inv = static_cast<uint8_t *>(iv);
+        d.cus = cus;
+        d.ready = true;
+    }
+    *out = &d;
+    return GF_OK;
+}
+
+bool valid_field(int f) { return f == 1 || f == 2 || f == 4 || f == 8; }
+
+const uint32_t *field_ptab(const DevState *d, int field)
+{
+    return d->t.ptab + (size_t)field_index(field) * 256 * 8;
+}
+const uint8_t *field_inv(const DevState *d, int field) { return d->t.inv + (size_t)field_index(field) * 256; }
+
+int dev_err(hipError_t e) { return e == hipSuccess ? GF_OK : GF_EDEVICE; }
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    if (na == 0 || nb == 0)
+        return false;
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + nb && b0 < a0 + na;
+}
+
+size_t envelope(size_t rows, size_t ld, size_t len) { return rows == 0 || len == 0 ? 0 : (rows - 1) * ld + len; }
+
+bool aligned_rows(const void *p, uint64_t ld, int D)
+{
+    const uint64_t a = 4u * (uint64_t)D;
+    return ((uintptr_t)p % a) == 0 && (ld % a) == 0;
+}
+
+// Analytic choice of the encode variant for one generation: fill the GPU
+// with blocks first, then prefer more coded rows per block (fewer source
+// re-reads) and wider lanes (fewer table reads per byte) while the padding
+// waste stays small.
+Variant pick_variant(int K, int N, uint64_t len, int cus)
+{
+    (void)N;
+    static const int Ds[3] = {4, 2, 1};
+    static const int KWs[3] = {32, 16, 8};
+    Variant best{1, 8};
+    double best_cost = 1e300;
+    for (int kw : KWs)
+        for (int D : Ds) {
+            const uint64_t strip = strip_bytes(D);
+            const uint64_t strips = (len + strip - 1) / strip;
+            const uint64_t kb = (uint64_t)(K + kw - 1) / kw;
+            const double work = (double)strips * strip * kb * kw;     // padded byte-rows computed
+            const double blocks = (double)strips * kb;
+            // per-block fixed cost (table staging, prologue) ~ one strip of a row per source
+            double cost = work + blocks * strip * 2.0;
+            // cost of an underfilled GPU: time is set by the busiest CU
+            const double waves = std::max(1.0, blocks / (cus * 2.0));
+            cost = std::max(cost, (double)strip * kw * std::ceil(waves) * (cus * 2.0));
+            // per-byte table-read overhead shrinks with wider lanes
+            cost *= 1.0 + 0.08 / D;
+            if (cost < best_cost) {
+                best_cost = cost;
+                best = Variant{D, kw};
+            }
+        }
+    return best;
+}
+
+Variant from_tuning(const gf_tuning *t, const Variant &fallback)
+{
+    if (!t)
+        return fallback;
+    Variant v = fallback;
+    if (t->bytes_per_lane)
+        v.D = t->bytes_per_lane / 4;
+    if (t->rows_per_block)
+        v.KW = t->rows_per_block;
+    return v;
+}
+
+}  // namespace
+
+// =========================================================================
+
+struct gf_plan {
+    int kind = 0;     // 0 encode, 1 decode
+    int field = 8;
+    int dev = 0;
+    int count = 0;
+    Variant v{4, 32};
+    int grid = 0;
+    int ntiles = 0;
+    DevGen *d_gens = nullptr;
+    DevTile *d_tiles = nullptr;
+    unsigned *d_ctr = nullptr;
+    // decode
+    DevSys *d_sys = nullptr;
+    uint8_t *d_cinv = nullptr;
+    int *d_rank = nullptr;
+    int class_begin[4] = {0, 0, 0, 0};
+    int class_count[4] = {0, 0, 0, 0};
+    std::vector<int> sys_order;       // plan position -> caller's index
+    // graph replay
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int *graph_rank = nullptr;
+    // host copy of the descriptors (for gf_encode_each-style diagnostics)
+    std::vector<gf_gen> gens;
+};
+
+extern "C" {
+
+int gf_init(void)
+{
+    DevState *d;
+    return current_state(&d);
+}
+
+const char *gf_strerror(int code)
+{
+    switch (code) {
+    case GF_OK: return "success";
+    case GF_EINVAL: return "invalid argument";
+    case GF_ENOTINIT: return "library not initialised";
+    case GF_EDEVICE: return "HIP runtime error";
+    case GF_ESINGULAR: return "coefficient matrix is singular";
+    case GF_ENOMEM: return "out of memory";
+    case GF_ERANGE: return "size above the supported maximum";
+    default: return "unknown error";
+    }
+}
+
+static int region_common(int mode, int field, uint8_t *y, const uint8_t *x, int c, size_t len, void *stream)
+{
+    if (!valid_field(field) || c < 0 || c >= (1 << field))
+        return GF_EINVAL;
+    if (len == 0)
+        return GF_OK;
+    if (!y || !x)
+        return GF_EINVAL;
+    if (y != x && overlap(y, len, x, len))
+        return GF_EINVAL;
+    DevState *d;
+    int rc = current_state(&d);
+    if (rc)
+        return rc;
+    if (mode == 0 && c == 0)
+        return GF_OK;
+    const uint32_t *t = host_tables().ptab[field_index(field)][c];
+    return dev_err(launch_region(mode, y, x, len, t, (hipStream_t)stream));
+}
+
+int gf_region_madd(int field, uint8_t *y, const uint8_t *x, int c, size_t len, void *stream)
+{
+    return region_common(0, field, y, x, c, len, stream);
+}
+
+int gf_region_mul(int field, uint8_t *y, const uint8_t *x, int c, size_t len, void *stream)
+{
+    return region_common(1, field, y, x, c, len, stream);
+}
+
+int gf_region_madd_batched(int field, const gf_region *d_regions, int count, size_t max_len, void *stream)
+{
+    if (!valid_field(field) || count < 0)
+        return GF_EINVAL;
+    if (count == 0 || max_len == 0)
+        return GF_OK;
+    if (!d_regions)
+        return GF_EINVAL;
+    DevState *d;
+    int rc = current_state(&d);
+    if (rc)
+        return rc;
+    return dev_err(launch_region_batched(d_regions, count, max_len, field_ptab(d, field), 1 << field,
+                                         (hipStream_t)stream));
+}
+
+static int check_encode_args(int field, const uint8_t *C, int K, int N, const uint8_t *S, size_t ld_s,
+                             const uint8_t *Y, size_t ld_y, size_t len)
+{
+    if (!valid_field(field) || K < 0 || N < 1)
+        return GF_EINVAL;
+    if (N > GF_MAX_N)
+        return GF_ERANGE;
+    if (K == 0 || len == 0)
+        return GF_OK;
+    if (!C || !S || !Y)
+        return GF_EINVAL;
+    if ((N > 1 && ld_s < len) || (K > 1 && ld_y < len))
+        return GF_EINVAL;
+    const size_t ey = envelope(K, ld_y, len);
+    if (overlap(Y, ey, S, envelope(N, ld_s, len)) || overlap(Y, ey, C, (size_t)K * N))
+        return GF_EINVAL;
+    return GF_OK;
+}
+
+static int encode_impl(int field, const uint8_t *C, int K, int N, const uint8_t *S, size_t ld_s, uint8_t *Y,
+                       size_t ld_y, size_t len, const gf_tuning *tune, const int *status, int need, void *stream)
+{
+    DevState *d;
+    int rc = current_state(&d);
+    if (rc)
+        return rc;
+    Variant v = from_tuning(tune, pick_variant(K, N, len, d->cus));
+    if (!variant_ok(v))
+        return GF_EINVAL;
+    const bool al = aligned_rows(S, N > 1 ? ld_s : 0, v.D) && aligned_rows(Y, K > 1 ? ld_y : 0, v.D);
+    return dev_err(launch_encode(v, C, K, N, S, ld_s, Y, ld_y, len, field_ptab(d, field), status, need, al,
+                                 (hipStream_t)stream));
+}
+
+int gf_encode(int field, const uint8_t *C, int K, int N, const uint8_t *S, size_t ld_s, uint8_t *Y, size_t ld_y,
+              size_t len, void *stream)
+{
+    int rc = check_encode_args(field, C, K, N, S, ld_s, Y, ld_y, len);
+    if (rc || K == 0 || len == 0)
+        return rc;
+    return encode_impl(field, C, K, N, S, ld_s, Y, ld_y, len, nullptr, nullptr, 0, stream);
+}
+
+int gf_encode_each(int field, const gf_gen *gens, int count, const gf_tuning *tune, void *stream)
+{
+    if (count < 0 || (count > 0 && !gens) || !valid_field(field))
+        return GF_EINVAL;
+    for (int i = 0; i < count; i++) {
+        const gf_gen &g = gens[i];
+        int rc = check_encode_args(field, g.C, (int)g.K, (int)g.N, g.S, g.ld_s, g.Y, g.ld_y, g.len);
+        if (rc)
+            return rc;
+    }
+    for (int i = 0; i < count; i++) {
+        const gf_gen &g = gens[i];
+        if (g.K == 0 || g.len == 0)
+            continue;
+        int rc = encode_impl(field, g.C, (int)g.K, (int)g.N, g.S, g.ld_s, g.Y, g.ld_y, g.len, tune, nullptr, 0,
+                             stream);
+        if (rc)
+            return rc;
+    }
+    return GF_OK;
+}
+
+size_t gf_decode_workspace(int N)
+{
+    if (N < 1 || N > GF_MAX_N)
+        return 0;
+    return (((size_t)N * N + 255) / 256) * 256 + 256;
+}
+
+int gf_invert(int field, const uint8_t *C, int N, uint8_t *Cinv, int *d_rank, void *stream)
+{
+    if (!valid_field(field) || N < 1 || !C || !Cinv)
+        return GF_EINVAL;
+    if (N > GF_MAX_N)
+        return GF_ERANGE;
+    if (overlap(C, (size_t)N * N, Cinv, (size_t)N * N))
+        return GF_EINVAL;
+    DevState *d;
+    int rc = current_state(&d);
+    if (rc)
+        return rc;
+    return dev_err(launch_invert(nullptr, 0, C, N, Cinv, d_rank, field_ptab(d, field), field_inv(d, field),
+                                 (hipStream_t)stream));
+}
+
+int gf_decode(int field, const uint8_t *C, int N, const uint8_t *B, size_t ld_b, uint8_t *S, size_t ld_s,
+              size_t len, void *ws, size_t ws_bytes, int *d_rank, void *stream)
+{
+    if (!valid_field(field) || N < 1)
+        return GF_EINVAL;
+    if (N > GF_MAX_N)
+        return GF_ERANGE;
+    if (!C || !ws || ws_bytes < gf_decode_workspace(N))
+        return GF_EINVAL;
+    if (len > 0 && (!B || !S || (N > 1 && (ld_b < len || ld_s < len))))
+        return GF_EINVAL;
+    const size_t es = envelope(N, ld_s, len);
+    if (overlap(S, es, B, envelope(N, ld_b, len)) || overlap(S, es, C, (size_t)N * N) ||
+        overlap(S, es, ws, ws_bytes) || overlap(ws, ws_bytes, C, (size_t)N * N) ||
+        overlap(ws, ws_bytes, B, envelope(N, ld_b, len)))
+        return GF_EINVAL;
+    DevState *d;
+    int rc = current_state(&d);
+    if (rc)
+        return rc;
+    uint8_t *cinv = static_cast<uint8_t *>(ws);
+    int *rank = d_rank ? d_rank : reinterpret_cast<int *>(cinv + ((((size_t)N * N + 255) / 256) * 256));
+    hipError_t e = launch_invert(nullptr, 0, C, N, cinv, rank, field_ptab(d, field), field_inv(d, field),
+                                 (hipStream_t)stream);
+    if (e != hipSuccess)
+        return GF_EDEVICE;
+    if (len == 0)
+        return GF_OK;
+    return encode_impl(field, cinv, N, N, B, ld_b, S, ld_s, len, nullptr, rank, N, stream);
+}
+
+// ------------------------------------------------------------------ plans
+
+static void plan_free_device(gf_plan *p)
+{
+    if (p->exec)
+        (void)hipGraphExecDestroy(p->exec);
+    if (p->graph)
+        (void)hipGraphDestroy(p->graph);
+    if (p->cap)
+        (void)hipStreamDestroy(p->cap);
+    (void)hipFree(p->d_gens);
+    (void)hipFree(p->d_tiles);
+    (void)hipFree(p->d_ctr);
+    (void)hipFree(p->d_sys);
+    (void)hipFree(p->d_cinv);
+    (void)hipFree(p->d_rank);
+}
+
+}  // extern "C"
+
+template <class T>
+static int upload(T **dst, const std::vector<T> &src)
+{
+    *dst = nullptr;
+    if (src.empty())
+        return GF_OK;
+    if (hipMalloc(reinterpret_cast<void **>(dst), src.size() * sizeof(T)) != hipSuccess)
+        return GF_ENOMEM;
+    if (hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        return GF_EDEVICE;
+    return GF_OK;
+}
+
+// Choose one variant for a whole batch: minimise padded work plus per-tile
+// overhead summed over the generations.
+static Variant pick_batch_variant(const std::vector<DevGen> &g)
+{
+    static const int Ds[3] = {4, 2, 1};
+    static const int KWs[3] = {32, 16, 8};
+    Variant best{4, 32};
+    double best_cost = 1e300;
+    for (int kw : KWs)
+        for (int D : Ds) {
+            const uint64_t strip = strip_bytes(D);
+            double cost = 0;
+            for (const DevGen &x : g) {
+                if (x.K == 0 || x.len == 0)
+                    continue;
+                const double strips = (double)((x.len + strip - 1) / strip);
+                const double kb = (double)((x.K + kw - 1) / kw);
+                // padded (row, byte) pairs times sources, plus per-tile table staging and
+                // source re-reads, which fall with more rows per tile
+                cost += strips * kb * ((double)strip * kw * x.N * (1.0 + 0.08 / D) + (double)strip * x.N * 2.0 +
+                                       4096.0);
+            }
+            if (cost < best_cost) {
+                best_cost = cost;
+                best = Variant{D, kw};
+            }
+        }
+    return best;
+}
+
+static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, const gf_tuning *tune)
+{
+    DevState *d;
+    int rc = current_state(&d);
+    if (rc)
+        return rc;
+    p->v = from_tuning(tune, pick_batch_variant(gens));
+    if (!variant_ok(p->v))
+        return GF_EINVAL;
+    std::vector<DevGen> g = gens;
+    for (DevGen &x : g)
+        x.aligned = aligned_rows(x.S, x.N > 1 ? x.ld_s : 0, p->v.D) && aligned_rows(x.Y, x.K > 1 ? x.ld_y : 0, p->v.D);
+    const uint64_t strip = strip_bytes(p->v.D);
+    struct T {
+        DevTile t;
+        double cost;
+    };
+    std::vector<T> tiles;
+    for (size_t i = 0; i < g.size(); i++) {
+        const DevGen &x = g[i];
+        if (x.K == 0 || x.len == 0)
+            continue;
+        for (uint32_t k0 = 0; k0 < x.K; k0 += (uint32_t)p->v.KW)
+            for (uint64_t p0 = 0; p0 < x.len; p0 += strip) {
+                const double cost = (double)x.N * (double)std::min<uint64_t>(strip, x.len - p0);
+                tiles.push_back(T{DevTile{(uint32_t)i, k0, p0}, cost});
+            }
+    }
+    // longest tiles first (LPT order); ties keep a generation's tiles together
+    std::stable_sort(tiles.begin(), tiles.end(), [](const T &a, const T &b) { return a.cost > b.cost; });
+    std::vector<DevTile> tl(tiles.size());
+    for (size_t i = 0; i < tiles.size(); i++)
+        tl[i] = tiles[i].t;
+    p->ntiles = (int)tl.size();
+    if ((rc = upload(&p->d_gens, g)) || (rc = upload(&p->d_tiles, tl)))
+        return rc;
+    if (hipMalloc(reinterpret_cast<void **>(&p->d_ctr), 2 * sizeof(unsigned)) != hipSuccess)
+        return GF_ENOMEM;
+    if (hipMemset(p->d_ctr, 0, 2 * sizeof(unsigned)) != hipSuccess)
+        return GF_EDEVICE;
+    int grid = d->cus * encode_blocks_per_cu(p->v);
+    if (tune && tune->grid_blocks > 0)
+        grid = tune->grid_blocks;
+    p->grid = std::max(1, std::min(grid, std::max(1, p->ntiles)));
+    if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
+        return GF_EDEVICE;
+    if (hipDeviceSynchronize() != hipSuccess)
+        return GF_EDEVICE;
+    return GF_OK;
+}
+
+extern "C" {
+
+int gf_plan_encode(int field, const gf_gen *gens, int count, const gf_tuning *tune, gf_plan **out)
+{
+    if (!out)
+        return GF_EINVAL;
+    *out = nullptr;
+    if (!valid_field(field) || count < 0 || (count > 0 && !gens))
+        return GF_EINVAL;
+    std::vector<DevGen> g(count);
+    for (int i = 0; i < count; i++) {
+        const gf_gen &x = gens[i];
+        int rc = check_encode_args(field, x.C, (int)x.K, (int)x.N, x.S, x.ld_s, x.Y, x.ld_y, x.len);
+        if (rc)
+            return rc;
+        g[i] = DevGen{x.C, x.S, x.Y, x.len, x.ld_s, x.ld_y, x.K, x.N, nullptr, 0, 0};
+    }
+    gf_plan *p = new (std::nothrow) gf_plan;
+    if (!p)
+        return GF_ENOMEM;
+    p->kind = 0;
+    p->field = field;
+    p->count = count;
+    (void)hipGetDevice(&p->dev);
+    p->gens.assign(gens, gens + count);
+    int rc = build_encode_schedule(p, g, tune);
+    if (rc) {
+        plan_free_device(p);
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return GF_OK;
+}
+
+int gf_plan_decode(int field, const gf_sys *sys, int count, const gf_tuning *tune, gf_plan **out)
+{
+    if (!out)
+        return GF_EINVAL;
+    *out = nullptr;
+    if (!valid_field(field) || count < 0 || (count > 0 && !sys))
+        return GF_EINVAL;
+    for (int i = 0; i < count; i++) {
+        const gf_sys &s = sys[i];
+        if (s.N < 1 || s.reserved != 0)
+            return GF_EINVAL;
+        if (s.N > GF_MAX_N)
+            return GF_ERANGE;
+        if (!s.C || (s.len > 0 && (!s.B || !s.S || (s.N > 1 && (s.ld_b < s.len || s.ld_s < s.len)))))
+            return GF_EINVAL;
+        const size_t es = envelope(s.N, s.ld_s, s.len);
+        if (overlap(s.S, es, s.B, envelope(s.N, s.ld_b, s.len)) || overlap(s.S, es, s.C, (size_t)s.N * s.N))
+            return GF_EINVAL;
+    }
+    gf_plan *p = new (std::nothrow) gf_plan;
+    if (!p)
+        return GF_ENOMEM;
+    p->kind = 1;
+    p->field = field;
+    p->count = count;
+    (void)hipGetDevice(&p->dev);
+    int rc = GF_OK;
+    // inverse matrices and ranks live in the plan
+    std::vector<size_t> off(count + 1, 0);
+    for (int i = 0; i < count; i++)
+        off[i + 1] = off[i] + (((size_t)sys[i].N * sys[i].N + 15) / 16) * 16;
+    if (count > 0) {
+        if (hipMalloc(reinterpret_cast<void **>(&p->d_cinv), std::max<size_t>(off[count], 16)) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void **>(&p->d_rank), sizeof(int) * count) != hipSuccess)
+            rc = GF_ENOMEM;
+    }
+    // systems grouped by size class (N <= 32, 64, 128, 256) for the elimination launches
+    auto cls = [](uint32_t N) { return N <= 32 ? 0 : N <= 64 ? 1 : N <= 128 ? 2 : 3; };
+    std::vector<int> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cls(sys[a].N) < cls(sys[b].N); });
+    std::vector<DevSys> ds(count);
+    for (int j = 0; j < count; j++) {
+        const int i = order[j];
+        ds[j] = DevSys{sys[i].C, p->d_cinv + off[i], p->d_rank + i, sys[i].N, 0};
+        p->class_count[cls(sys[i].N)]++;
+    }
+    for (int c = 1; c < 4; c++)
+        p->class_begin[c] = p->class_begin[c - 1] + p->class_count[c - 1];
+    p->sys_order = order;
+    if (!rc)
+        rc = upload(&p->d_sys, ds);
+    std::vector<DevGen> g(count);
+    for (int i = 0; i < count; i++) {
+        const gf_sys &s = sys[i];
+        g[i] = DevGen{p->d_cinv + off[i], s.B, s.S, s.len, s.ld_b, s.ld_s, s.N, s.N, p->d_rank + i, (int)s.N, 0};
+    }
+    if (!rc)
+        rc = build_encode_schedule(p, g, tune);
+    if (rc) {
+        plan_free_device(p);
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return GF_OK;
+}
+
+static int run_plan(gf_plan *p, int *d_rank, hipStream_t s)
+{
+    DevState *d;
+    int rc = current_state(&d);
+    if (rc)
+        return rc;
+    const int f = p->field;
+    if (p->kind == 1) {
+        for (int c = 0; c < 4; c++) {
+            if (p->class_count[c] == 0)
+                continue;
+            hipError_t e = launch_invert(p->d_sys + p->class_begin[c], p->class_count[c], nullptr, 0, nullptr,
+                                         nullptr, field_ptab(d, f), field_inv(d, f), s);
+            if (e != hipSuccess)
+                return GF_EDEVICE;
+        }
+    }
+    hipError_t e =
+        launch_encode_persistent(p->v, p->d_gens, p->d_tiles, p->ntiles, p->d_ctr, p->grid, field_ptab(d, f), s);
+    if (e != hipSuccess)
+        return GF_EDEVICE;
+    if (p->kind == 1 && d_rank && p->count > 0)
+        if (hipMemcpyAsync(d_rank, p->d_rank, sizeof(int) * p->count, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return GF_EDEVICE;
+    return GF_OK;
+}
+
+int gf_encode_batched(gf_plan *p, void *stream)
+{
+    if (!p || p->kind != 0)
+        return GF_EINVAL;
+    return run_plan(p, nullptr, (hipStream_t)stream);
+}
+
+int gf_decode_batched(gf_plan *p, int *d_rank, void *stream)
+{
+    if (!p || p->kind != 1)
+        return GF_EINVAL;
+    return run_plan(p, d_rank, (hipStream_t)stream);
+}
+
+int gf_plan_launch_graph(gf_plan *p, int *d_rank, void *stream)
+{
+    if (!p)
+        return GF_EINVAL;
+    if (p->exec && p->graph_rank != d_rank) {
+        (void)hipGraphExecDestroy(p->exec);
+        (void)hipGraphDestroy(p->graph);
+        p->exec = nullptr;
+        p->graph = nullptr;
+    }
+    if (!p->exec) {
+        if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return GF_EDEVICE;
+        int rc = run_plan(p, p->kind == 1 ? d_rank : nullptr, p->cap);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(p->cap, &g);
+        if (rc)
+            return rc;
+        if (e != hipSuccess || !g)
+            return GF_EDEVICE;
+        hipGraphExec_t x = nullptr;
+        if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return GF_EDEVICE;
+        }
+        p->graph = g;
+        p->exec = x;
+        p->graph_rank = d_rank;
+    }
+    return dev_err(hipGraphLaunch(p->exec, (hipStream_t)stream));
+}
+
+int gf_plan_tuning(const gf_plan *p, gf_tuning *out)
+{
+    if (!p || !out)
+        return GF_EINVAL;
+    out->form = 1;
+    out->bytes_per_lane = 4 * p->v.D;
+    out->rows_per_block = p->v.KW;
+    out->grid_blocks = p->grid;
+    return GF_OK;
+}
+
+void gf_plan_destroy(gf_plan *p)
+{
+    if (!p)
+        return;
+    (void)hipDeviceSynchronize();
+    plan_free_device(p);
+    delete p;
+}
+
+}  // extern "C"

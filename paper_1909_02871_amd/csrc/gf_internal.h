@@ -1,0 +1,86 @@
+// Internal declarations shared by the host API and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace gfnc {
+
+// Field index 0..3 for n = 1, 2, 4, 8.
+inline int field_index(int n) { return n == 1 ? 0 : n == 2 ? 1 : n == 4 ? 2 : n == 8 ? 3 : -1; }
+
+// Device-resident tables for one device.
+//   ptab[f][c][0..7]: byte-permute product tables of coefficient c in field f
+//     dwords 0,1: c * v for the 8 bytes v whose set bits lie in bits 0-2
+//     dwords 2,3: c * (v << 3), v < 8
+//     dword  4  : c * (v << 6), v < 4
+//     dwords 5-7: zero
+//     (c * b is applied word by word, so every field shares one kernel; rows
+//      with c >= q are all zero.)
+//   inv[f][a]: multiplicative inverse of a (0 for a = 0 or a >= q).
+struct DevTables {
+    uint32_t *ptab;   // [4][256][8]
+    uint8_t *inv;     // [4][256]
+};
+
+// Host copies, built once by build_tables().
+struct HostTables {
+    uint32_t ptab[4][256][8];
+    uint8_t inv[4][256];
+    uint8_t mul[4][256][256];   // element products (row c, column a), a, c < q
+};
+const HostTables &host_tables();
+
+// Per-generation descriptor as the persistent kernels read it.
+struct DevGen {
+    const uint8_t *C;
+    const uint8_t *S;
+    uint8_t *Y;
+    uint64_t len, ld_s, ld_y;
+    uint32_t K, N;
+    const int *status;   // if non-null, the generation is skipped unless *status == need
+    int need;
+    uint32_t aligned;    // rows meet the vector-load alignment of the plan's variant
+};
+
+// One work tile of the persistent encode: KW coded rows x one block strip.
+struct DevTile {
+    uint32_t gen;
+    uint32_t k0;
+    uint64_t p0;
+};
+
+struct DevSys {
+    const uint8_t *C;
+    uint8_t *Cinv;
+    int *rank;
+    uint32_t N;
+    uint32_t pad;
+};
+
+struct Variant {
+    int D;    // dwords per lane (1, 2, 4)
+    int KW;   // coded rows per block (8, 16, 32)
+};
+
+// Strip of payload bytes covered by one 256-thread block.
+inline uint64_t strip_bytes(int D) { return 4ull * 64ull * 4ull * (uint64_t)D; }
+inline bool variant_ok(const Variant &v) {
+    return (v.D == 1 || v.D == 2 || v.D == 4) && (v.KW == 8 || v.KW == 16 || v.KW == 32);
+}
+
+hipError_t launch_region(int mode, uint8_t *y, const uint8_t *x, uint64_t len, const uint32_t *tab_host8,
+                         hipStream_t s);
+hipError_t launch_region_batched(const void *d_regions, int count, uint64_t max_len, const uint32_t *ptab_field,
+                                 int q, hipStream_t s);
+hipError_t launch_encode(const Variant &v, const uint8_t *C, int K, int N, const uint8_t *S, uint64_t ld_s,
+                         uint8_t *Y, uint64_t ld_y, uint64_t len, const uint32_t *ptab_field, const int *status,
+                         int need, bool aligned, hipStream_t s);
+hipError_t launch_encode_persistent(const Variant &v, const DevGen *gens, const DevTile *tiles, int ntiles,
+                                    unsigned *counters, int grid, const uint32_t *ptab_field, hipStream_t s);
+hipError_t launch_invert(const DevSys *sys, int count, const uint8_t *C, int N, uint8_t *Cinv, int *rank,
+                         const uint32_t *ptab_field, const uint8_t *inv_field, hipStream_t s);
+int encode_blocks_per_cu(const Variant &v);
+
+}  // namespace gfnc

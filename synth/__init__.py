@@ -209,3 +209,90 @@ def coded_arrivals(seed: int, N: int, loss: float = 0.1, max_packets: Optional[i
         lost = bool(unit_floats(key(seed, 7, i), 1)[0] < loss)
         yield i, lost
         i += 1
+
+
+# --------------------------------------------------------------------------
+# Batched layouts: every generation's rows padded to a multiple of 16 bytes,
+# generations packed back to back in one payload blob and one coefficient blob.
+# --------------------------------------------------------------------------
+
+ROW_ALIGN = 16
+
+
+def padded(length: int, align: int = ROW_ALIGN) -> int:
+    return (int(length) + align - 1) // align * align
+
+
+@dataclass
+class Batch:
+    n: int
+    Ns: np.ndarray          # generation sizes
+    Ks: np.ndarray          # coded rows per generation
+    Ls: np.ndarray          # packet lengths (bytes)
+    lds: np.ndarray         # row pitch (bytes)
+    s_off: np.ndarray       # byte offset of each generation's first source row in the payload blob
+    y_off: np.ndarray       # byte offset of each generation's first coded row in the output blob
+    c_off: np.ndarray       # byte offset of each generation's coefficients in the coefficient blob
+    s_bytes: int
+    y_bytes: int
+    c_bytes: int
+    seed: int
+
+    def source_blob(self) -> np.ndarray:
+        return random_bytes(key(self.seed, 11), self.s_bytes)
+
+    def coef_blob(self) -> np.ndarray:
+        return uniform_field(key(self.seed, 12), self.c_bytes, self.n)
+
+    def generation(self, i: int, S_blob: np.ndarray, C_blob: np.ndarray):
+        """(C[K, N], S[N, L]) views of generation i."""
+        N, K, L, ld = int(self.Ns[i]), int(self.Ks[i]), int(self.Ls[i]), int(self.lds[i])
+        S = S_blob[self.s_off[i]:self.s_off[i] + N * ld].reshape(N, ld)[:, :L]
+        C = C_blob[self.c_off[i]:self.c_off[i] + K * N].reshape(K, N)
+        return C, S
+
+    @property
+    def source_bytes(self) -> int:
+        """Useful source payload (sum of N * L)."""
+        return int((self.Ns * self.Ls).sum())
+
+    @property
+    def byte_madds(self) -> int:
+        return int((self.Ks * self.Ns * self.Ls).sum())
+
+
+def _layout(n: int, Ns, Ks, Ls, seed: int) -> Batch:
+    Ns = np.asarray(Ns, dtype=np.int64)
+    Ks = np.asarray(Ks, dtype=np.int64)
+    Ls = np.asarray(Ls, dtype=np.int64)
+    lds = (Ls + ROW_ALIGN - 1) // ROW_ALIGN * ROW_ALIGN
+    s_sz = Ns * lds
+    y_sz = Ks * lds
+    c_sz = (Ks * Ns + ROW_ALIGN - 1) // ROW_ALIGN * ROW_ALIGN
+    s_off = np.concatenate([[0], np.cumsum(s_sz)[:-1]]) if len(Ns) else np.zeros(0, np.int64)
+    y_off = np.concatenate([[0], np.cumsum(y_sz)[:-1]]) if len(Ns) else np.zeros(0, np.int64)
+    c_off = np.concatenate([[0], np.cumsum(c_sz)[:-1]]) if len(Ns) else np.zeros(0, np.int64)
+    return Batch(n, Ns, Ks, Ls, lds, s_off, y_off, c_off, int(s_sz.sum()), int(y_sz.sum()),
+                 int(c_sz.sum()), seed)
+
+
+def uneven_batch(n: int, count: int = 10000, seed_off: int = 0) -> Batch:
+    """The uneven batch: N ~ U{8..256}, L log-uniform in [64, 9000] B, K = N."""
+    Ns, Ls = uneven_shapes(count, n, seed_off)
+    return _layout(n, Ns, Ns, Ls, key(BASE_SEED + 2, n, seed_off, 7))
+
+
+def sweep_batch(n: int, length: int, count: int = 4096, N: int = 64, K: int = 64) -> Batch:
+    """The plain sweep: ``count`` generations of N = K = 64 packets of ``length`` bytes."""
+    return _layout(n, np.full(count, N), np.full(count, K), np.full(count, length),
+                   key(BASE_SEED + 1, n, length, 7))
+
+
+def decode_batch(count: int = 2048, length: int = 1500, seed_off: int = 0) -> Batch:
+    """The decode batch over GF(256): N uniform over {32, 64, 128}, L = 1500 B.
+
+    ``coef_blob`` holds first candidates only; invertibility is decided by the
+    caller with ``decode_candidate`` redraws.
+    """
+    Ns = decode_shapes(count, seed_off)
+    return _layout(8, Ns, Ns, np.full(count, length), key(BASE_SEED + 3, seed_off, 7))

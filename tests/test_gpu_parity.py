@@ -1,0 +1,316 @@
+"""GPU results against the CPU oracle, byte for byte (integer work: bit-exact).
+
+Region madd (paper Sec. II and Sec. IV), encoding (Sec. II, Eq. 1 for K
+coding vectors) and Gauss-Jordan decoding, over GF(2), GF(4), GF(16) and
+GF(256), through the C ABI.  Inputs come from the seeded generators; sizes
+span several tiles and ragged tails; unaligned rows and offsets take the
+byte path and are covered too.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import dev, host, padded_rows, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = [1, 2, 4, 8]
+
+
+@pytest.fixture(scope="module")
+def gf():
+    torch_cuda()
+    import paper_1909_02871_amd as g
+    g.gf_init()
+    return g
+
+
+def _coefs(n):
+    q = 1 << n
+    return sorted({0, 1, q - 1, min(2, q - 1), (0x53 % q)})
+
+
+# ------------------------------------------------------------------ region
+
+@pytest.mark.parametrize("n", FIELDS)
+@pytest.mark.parametrize("length", [0, 1, 15, 16, 17, 1000, 4109, 70001])
+def test_region_madd_mul(gf, n, length):
+    torch = torch_cuda()
+    x = synth.random_bytes(synth.key(1, n, length), length)
+    y = synth.random_bytes(synth.key(2, n, length), length)
+    for c in _coefs(n):
+        print("region", n, length, c, flush=True)
+        yd = dev(y) if length else torch.zeros(0, dtype=torch.uint8, device="cuda")
+        xd = dev(x) if length else torch.zeros(0, dtype=torch.uint8, device="cuda")
+        gf.gf_region_madd(n, yd, xd, c)
+        assert (host(yd) == oracle.region_madd(n, y, x, c)).all()
+        gf.gf_region_mul(n, yd, xd, c)
+        assert (host(yd) == oracle.region_mul(n, x, c)).all()
+
+
+@pytest.mark.parametrize("n", FIELDS)
+@pytest.mark.parametrize("xo,yo", [(1, 1), (3, 0), (0, 5), (7, 9)])
+def test_region_unaligned(gf, n, xo, yo):
+    torch = torch_cuda()
+    L = 3001
+    x = synth.random_bytes(synth.key(3, n, xo), L)
+    y = synth.random_bytes(synth.key(4, n, yo), L)
+    c = (1 << n) - 1
+    xb = torch.zeros(L + 32, dtype=torch.uint8, device="cuda")
+    yb = torch.zeros(L + 32, dtype=torch.uint8, device="cuda")
+    xb[xo:xo + L] = dev(x)
+    yb[yo:yo + L] = dev(y)
+    gf.gf_region_madd(n, yb[yo:yo + L], xb[xo:xo + L], c)
+    out = host(yb)
+    assert (out[yo:yo + L] == oracle.region_madd(n, y, x, c)).all()
+    assert (out[:yo] == 0).all() and (out[yo + L:] == 0).all()
+
+
+@pytest.mark.parametrize("n", FIELDS)
+def test_region_alias(gf, n):
+    x = synth.random_bytes(5, 5000)
+    for c in _coefs(n):
+        xd = dev(x)
+        gf.gf_region_madd(n, xd, xd, c)   # y == x: (1 + c) x
+        assert (host(xd) == oracle.region_madd(n, x, x, c)).all()
+
+
+@pytest.mark.parametrize("n", FIELDS)
+def test_region_batched(gf, n):
+    torch = torch_cuda()
+    cnt = 300
+    Ls = synth.log_uniform_ints(synth.key(6, n), cnt, 1, 20000)
+    cs = synth.uniform_field(synth.key(7, n), cnt, n)
+    xs = [synth.random_bytes(synth.key(8, n, i), int(L)) for i, L in enumerate(Ls)]
+    ys = [synth.random_bytes(synth.key(9, n, i), int(L)) for i, L in enumerate(Ls)]
+    xd = [dev(a) for a in xs]
+    yd = [dev(a) for a in ys]
+    regs = gf.make_regions([(yd[i].data_ptr(), xd[i].data_ptr(), int(Ls[i]), int(cs[i])) for i in range(cnt)])
+    gf.gf_region_madd_batched(n, regs, cnt, int(Ls.max()))
+    torch.cuda.synchronize()
+    for i in range(cnt):
+        assert (host(yd[i]) == oracle.region_madd(n, ys[i], xs[i], int(cs[i]))).all(), i
+
+
+# ------------------------------------------------------------------ encode
+
+SHAPES = [(1, 1, 1), (3, 7, 33), (16, 16, 1500), (64, 64, 1500), (40, 200, 513), (255, 256, 77),
+          (8, 256, 9000), (33, 5, 4096 + 5), (2, 3, 20000)]
+
+
+@pytest.mark.parametrize("n", FIELDS)
+@pytest.mark.parametrize("K,N,L", SHAPES)
+def test_encode(gf, n, K, N, L):
+    torch = torch_cuda()
+    print("encode", n, K, N, L, flush=True)
+    g = synth.generation(synth.key(10, n, K, N, L), n, N, K, L)
+    want = oracle.encode(n, g.C, g.S)
+    Cd = dev(g.C)
+    for ld_pad, off in [(0, 0), (16, 0), (3, 1)]:
+        ld = synth.padded(L) + ld_pad if ld_pad != 3 else L + 3
+        _, Sd = padded_rows(g.S, ld, off)
+        yb, Yd = padded_rows(np.zeros((K, L), np.uint8), ld, off, fill=0x5A)
+        gf.gf_encode(n, Cd, Sd, Yd)
+        got = host(Yd)
+        assert (got == want).all(), (ld_pad, off)
+        # bytes between rows and around the output are untouched
+        raw = host(yb)
+        mask = np.ones(raw.size, bool)
+        for k in range(K):
+            mask[off + k * ld: off + k * ld + L] = False
+        assert (raw[mask] == 0x5A).all()
+
+
+@pytest.mark.parametrize("n", [4, 8])
+@pytest.mark.parametrize("bpl", [4, 8, 16])
+@pytest.mark.parametrize("rows", [8, 16, 32])
+def test_encode_every_variant(gf, n, bpl, rows):
+    """Every schedule of the table kernel gives the same bytes (batched path, 30 generations)."""
+    torch = torch_cuda()
+    gens, keep, wants = [], [], []
+    for i in range(30):
+        N = int(synth.uniform_ints(synth.key(11, i), 1, 1, 80)[0])
+        K = int(synth.uniform_ints(synth.key(12, i), 1, 1, 70)[0])
+        L = int(synth.uniform_ints(synth.key(13, i), 1, 1, 5000)[0])
+        g = synth.generation(synth.key(14, n, i), n, N, K, L)
+        wants.append(oracle.encode(n, g.C, g.S))
+        Cd = dev(g.C)
+        _, Sd = padded_rows(g.S, synth.padded(L))
+        _, Yd = padded_rows(np.zeros((K, L), np.uint8), synth.padded(L))
+        keep.append((Cd, Sd, Yd))
+    plan = gf.gf_plan_encode(n, keep, tune={"bytes_per_lane": bpl, "rows_per_block": rows})
+    assert plan.tuning()["bytes_per_lane"] == bpl and plan.tuning()["rows_per_block"] == rows
+    for rep in range(2):      # the work counter resets itself between launches
+        for _, _, Yd in keep:
+            Yd.zero_()
+        gf.gf_encode_batched(plan)
+        torch.cuda.synchronize()
+        for (Cd, Sd, Yd), w in zip(keep, wants):
+            assert (host(Yd) == w).all()
+    # per-generation launches with the same schedule
+    for _, _, Yd in keep:
+        Yd.zero_()
+    gf.gf_encode_each(n, keep, tune={"bytes_per_lane": bpl, "rows_per_block": rows})
+    torch.cuda.synchronize()
+    for (Cd, Sd, Yd), w in zip(keep, wants):
+        assert (host(Yd) == w).all()
+
+
+def test_encode_single_generation_workload(gf):
+    """GF(256), 16 packets of 1500 B, 16 x 16 nonzero coefficients; then decode back."""
+    torch = torch_cuda()
+    g = synth.single_generation()
+    want = oracle.encode(8, g.C, g.S)
+    Cd, Sd = dev(g.C), dev(g.S)
+    Yd = torch.zeros((16, 1500), dtype=torch.uint8, device="cuda")
+    gf.gf_encode(8, Cd, Sd, Yd)
+    assert (host(Yd) == want).all()
+    r, S_or = oracle.decode(8, g.C, want)
+    out = torch.zeros((16, 1500), dtype=torch.uint8, device="cuda")
+    rank = torch.zeros(1, dtype=torch.int32, device="cuda")
+    gf.gf_decode(8, Cd, Yd, out, d_rank=rank)
+    assert int(rank.item()) == r
+    if r == 16:
+        assert (host(out) == S_or).all() and (host(out) == g.S).all()
+
+
+# ------------------------------------------------------------------ decode
+
+def _invertible(n, N, seed):
+    a = 0
+    while True:
+        Cm = synth.uniform_field(synth.key(seed, a), N * N, n).reshape(N, N)
+        if oracle.rank(n, Cm) == N:
+            return Cm
+        a += 1
+
+
+@pytest.mark.parametrize("n", FIELDS)
+@pytest.mark.parametrize("N", [1, 2, 3, 7, 16, 33, 64, 100, 128, 200, 256])
+def test_invert(gf, n, N):
+    torch = torch_cuda()
+    print("invert", n, N, flush=True)
+    Cm = _invertible(n, N, synth.key(20, n, N))
+    Ci = torch.zeros((N, N), dtype=torch.uint8, device="cuda")
+    rank = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    gf.gf_invert(n, dev(Cm), Ci, rank)
+    torch.cuda.synchronize()
+    assert int(rank.item()) == N
+    assert (host(Ci) == oracle.invert(n, Cm)).all()
+
+
+@pytest.mark.parametrize("n", FIELDS)
+@pytest.mark.parametrize("N,L", [(1, 10), (5, 1000), (32, 1500), (64, 1500), (128, 1500), (256, 300)])
+def test_decode(gf, n, N, L):
+    torch = torch_cuda()
+    print("decode", n, N, L, flush=True)
+    Cm = _invertible(n, N, synth.key(21, n, N))
+    S = synth.random_bytes(synth.key(22, n, N), N * L).reshape(N, L)
+    B = oracle.encode(n, Cm, S)
+    out = torch.zeros((N, L), dtype=torch.uint8, device="cuda")
+    rank = torch.zeros(1, dtype=torch.int32, device="cuda")
+    gf.gf_decode(n, dev(Cm), dev(B), out, d_rank=rank)
+    torch.cuda.synchronize()
+    assert int(rank.item()) == N
+    assert (host(out) == S).all()
+
+
+@pytest.mark.parametrize("n", FIELDS)
+@pytest.mark.parametrize("N", [2, 9, 64, 130])
+def test_decode_singular(gf, n, N):
+    torch = torch_cuda()
+    Cm = synth.uniform_field(synth.key(23, n, N), N * N, n).reshape(N, N)
+    Cm[N - 1] = Cm[0]
+    if N > 8:
+        Cm[3] = 0
+        Cm[5] = Cm[1] ^ Cm[2] if n == 1 else Cm[5]
+    want_rank = oracle.rank(n, Cm)
+    assert want_rank < N
+    L = 100
+    out = torch.full((N, L), 0x77, dtype=torch.uint8, device="cuda")
+    rank = torch.zeros(1, dtype=torch.int32, device="cuda")
+    gf.gf_decode(n, dev(Cm), dev(synth.random_bytes(1, N * L).reshape(N, L)), out, d_rank=rank)
+    Ci = torch.full((N, N), 0x33, dtype=torch.uint8, device="cuda")
+    rank2 = torch.zeros(1, dtype=torch.int32, device="cuda")
+    gf.gf_invert(n, dev(Cm), Ci, rank2)
+    torch.cuda.synchronize()
+    assert int(rank.item()) == want_rank == int(rank2.item())
+    assert (host(out) == 0x77).all() and (host(Ci) == 0x33).all()
+
+
+# ------------------------------------------------------------------ batched
+
+def _uneven(n, count, seed, maxN=256, maxL=9000):
+    torch = torch_cuda()
+    items = []
+    for i in range(count):
+        N = int(synth.uniform_ints(synth.key(seed, 1, i), 1, 1, maxN)[0])
+        L = int(synth.log_uniform_ints(synth.key(seed, 2, i), 1, 1, maxL)[0])
+        g = synth.generation(synth.key(seed, 3, i), n, N, N, L)
+        _, Sd = padded_rows(g.S, synth.padded(L))
+        _, Yd = padded_rows(np.zeros((N, L), np.uint8), synth.padded(L))
+        items.append((g, dev(g.C), Sd, Yd))
+    return items
+
+
+@pytest.mark.parametrize("n", FIELDS)
+def test_batched_encode_and_graph(gf, n):
+    torch = torch_cuda()
+    items = _uneven(n, 60, synth.key(30, n), maxN=96, maxL=3000)
+    wants = [oracle.encode(n, g.C, g.S) for g, _, _, _ in items]
+    plan = gf.gf_plan_encode(n, [(C, S, Y) for _, C, S, Y in items])
+    gf.gf_encode_batched(plan)
+    torch.cuda.synchronize()
+    for (g, _, _, Yd), w in zip(items, wants):
+        assert (host(Yd) == w).all()
+    # graph replays, with eager work and synchronisation in between
+    for rep in range(3):
+        for _, _, _, Yd in items:
+            Yd.fill_(rep + 1)
+        torch.cuda.synchronize()
+        gf.gf_plan_launch_graph(plan)
+        torch.cuda.synchronize()
+        for (g, _, _, Yd), w in zip(items, wants):
+            assert (host(Yd) == w).all(), rep
+
+
+@pytest.mark.parametrize("n", FIELDS)
+def test_batched_decode(gf, n):
+    torch = torch_cuda()
+    count = 40
+    systems, wants, ranks_or = [], [], []
+    for i in range(count):
+        N = [1, 17, 32, 33, 64, 65, 128, 129, 200, 256][i % 10]
+        L = int(synth.uniform_ints(synth.key(31, n, i), 1, 1, 2000)[0])
+        if i % 7 == 3:
+            Cm = synth.uniform_field(synth.key(32, n, i), N * N, n).reshape(N, N)
+            Cm[N - 1] = 0
+        else:
+            Cm = _invertible(n, N, synth.key(33, n, i))
+        S = synth.random_bytes(synth.key(34, n, i), N * L).reshape(N, L)
+        B = oracle.encode(n, Cm, S)
+        r = oracle.rank(n, Cm)
+        ranks_or.append(r)
+        wants.append(S if r == N else None)
+        out = torch.full((N, L), 0x3C, dtype=torch.uint8, device="cuda")
+        systems.append((dev(Cm), dev(B), out))
+    plan = gf.gf_plan_decode(n, systems)
+    rank = torch.full((count,), -1, dtype=torch.int32, device="cuda")
+    for mode in ("eager", "graph", "graph"):
+        for _, _, out in systems:
+            out.fill_(0x3C)
+        torch.cuda.synchronize()
+        if mode == "eager":
+            gf.gf_decode_batched(plan, rank)
+        else:
+            gf.gf_plan_launch_graph(plan, rank)
+        torch.cuda.synchronize()
+        assert host(rank).tolist() == ranks_or
+        for (Cd, Bd, out), w in zip(systems, wants):
+            if w is None:
+                assert (host(out) == 0x3C).all()
+            else:
+                assert (host(out) == w).all()
