@@ -145,12 +145,12 @@ typedef struct {
     uint64_t len, ld_b, ld_s;
 } gf_sys;
 
-/* Kernel schedule knobs.  Zero fields mean "autotuned". */
+/* Kernel schedule knobs.  Zero fields mean "chosen by the library". */
 typedef struct {
-    int form;          /* 0 auto, 1 table (VALU byte-permute), 2 bit-matrix MFMA */
-    int bytes_per_lane;/* 4, 8 or 16 */
-    int rows_per_block; /* coded packets accumulated per workgroup: 8, 16 or 32 */
-    int grid_blocks;   /* persistent workgroups; 0 = 8 per compute unit */
+    int form;           /* 0 auto, 1 table (VALU byte-select) */
+    int bytes_per_lane; /* 0 = per tile; else 4, 8 or 16 payload bytes per lane everywhere */
+    int grid_blocks;    /* persistent workgroups; 0 = as many as fit on the GPU at once */
+    int reserved;       /* must be 0 */
 } gf_tuning;
 
 typedef struct gf_plan gf_plan;

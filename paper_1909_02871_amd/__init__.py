@@ -24,7 +24,7 @@ import os
 from typing import List, Optional, Sequence, Tuple
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgfnc.so")
+LIB_PATH = os.environ.get("GFNC_LIB") or os.path.join(_HERE, "libgfnc.so")
 
 GF_2, GF_4, GF_16, GF_256 = 1, 2, 4, 8
 FIELDS = (GF_2, GF_4, GF_16, GF_256)
@@ -56,8 +56,8 @@ class gf_sys(C.Structure):
 
 
 class gf_tuning(C.Structure):
-    _fields_ = [("form", C.c_int), ("bytes_per_lane", C.c_int), ("rows_per_block", C.c_int),
-                ("grid_blocks", C.c_int)]
+    _fields_ = [("form", C.c_int), ("bytes_per_lane", C.c_int), ("grid_blocks", C.c_int),
+                ("reserved", C.c_int)]
 
 
 _SIGS = {
@@ -239,8 +239,7 @@ def gf_invert(field: int, Cm, Cinv, d_rank=None, stream=None):
 def _tuning(t: Optional[dict]):
     if t is None:
         return None
-    return C.byref(gf_tuning(t.get("form", 0), t.get("bytes_per_lane", 0), t.get("rows_per_block", 0),
-                             t.get("grid_blocks", 0)))
+    return C.byref(gf_tuning(t.get("form", 0), t.get("bytes_per_lane", 0), t.get("grid_blocks", 0), 0))
 
 
 class Plan:
@@ -255,8 +254,7 @@ class Plan:
     def tuning(self) -> dict:
         t = gf_tuning()
         _check(lib().gf_plan_tuning(self._h, C.byref(t)), "gf_plan_tuning")
-        return {"form": t.form, "bytes_per_lane": t.bytes_per_lane, "rows_per_block": t.rows_per_block,
-                "grid_blocks": t.grid_blocks}
+        return {"form": t.form, "bytes_per_lane": t.bytes_per_lane, "grid_blocks": t.grid_blocks}
 
     def destroy(self):
         if self._h:

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <numeric>
 #include <vector>
@@ -79,55 +80,48 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb)
 
 size_t envelope(size_t rows, size_t ld, size_t len) { return rows == 0 || len == 0 ? 0 : (rows - 1) * ld + len; }
 
-bool aligned_rows(const void *p, uint64_t ld, int D)
+// Largest of 16, 8, 4 (else 1) that divides every row start: the widest
+// vector access the rows allow.
+uint32_t row_align(const void *S, uint64_t ld_s, const void *Y, uint64_t ld_y)
 {
-    const uint64_t a = 4u * (uint64_t)D;
-    return ((uintptr_t)p % a) == 0 && (ld % a) == 0;
+    const uint64_t bits = (uint64_t)(uintptr_t)S | (uint64_t)(uintptr_t)Y | ld_s | ld_y;
+    for (uint32_t a : {16u, 8u, 4u})
+        if (bits % a == 0)
+            return a;
+    return 1;
 }
 
-// Analytic choice of the encode variant for one generation: fill the GPU
-// with blocks first, then prefer more coded rows per block (fewer source
-// re-reads) and wider lanes (fewer table reads per byte) while the padding
-// waste stays small.
-Variant pick_variant(int K, int N, uint64_t len, int cus)
+struct Single {
+    int D;
+    int nsplit;
+};
+
+// Schedule of a single-generation launch.  Lane width: padded payload work,
+// inflated for narrow lanes (more table reads per byte).  When the tiles do
+// not fill the GPU (2 waves on each of its SIMDs), the sources are split into
+// slices whose partial sums are XORed into the output with atomics, provided
+// the rows are 4-byte aligned and every slice keeps at least 8 sources.
+Single pick_single(int K, int N, uint64_t len, uint32_t align, int cus)
 {
-    (void)N;
-    static const int Ds[3] = {4, 2, 1};
-    static const int KWs[3] = {32, 16, 8};
-    Variant best{1, 8};
+    Single best{1, 1};
     double best_cost = 1e300;
-    for (int kw : KWs)
-        for (int D : Ds) {
-            const uint64_t strip = strip_bytes(D);
-            const uint64_t strips = (len + strip - 1) / strip;
-            const uint64_t kb = (uint64_t)(K + kw - 1) / kw;
-            const double work = (double)strips * strip * kb * kw;     // padded byte-rows computed
-            const double blocks = (double)strips * kb;
-            // per-block fixed cost (table staging, prologue) ~ one strip of a row per source
-            double cost = work + blocks * strip * 2.0;
-            // cost of an underfilled GPU: time is set by the busiest CU
-            const double waves = std::max(1.0, blocks / (cus * 2.0));
-            cost = std::max(cost, (double)strip * kw * std::ceil(waves) * (cus * 2.0));
-            // per-byte table-read overhead shrinks with wider lanes
-            cost *= 1.0 + 0.08 / D;
-            if (cost < best_cost) {
-                best_cost = cost;
-                best = Variant{D, kw};
-            }
+    const double fill = (double)cus * 8.0;
+    const bool can_split = align >= 4 && len >= 4;
+    for (int D : {4, 2, 1}) {
+        const uint64_t s = wave_strip(D);
+        const double strips = (double)((len + s - 1) / s);
+        const double tiles = strips * (double)((K + ENC_ROWS - 1) / ENC_ROWS);
+        int split = 1;
+        if (can_split && tiles < fill)
+            split = std::max(1, std::min((int)std::ceil(fill / tiles), N / 8));
+        const double par = std::min(1.0, tiles * split / fill);
+        const double cost = strips * (double)s * (1.0 + 0.15 / D) * (1.0 + 0.02 * split) / par;
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = Single{D, split};
         }
+    }
     return best;
-}
-
-Variant from_tuning(const gf_tuning *t, const Variant &fallback)
-{
-    if (!t)
-        return fallback;
-    Variant v = fallback;
-    if (t->bytes_per_lane)
-        v.D = t->bytes_per_lane / 4;
-    if (t->rows_per_block)
-        v.KW = t->rows_per_block;
-    return v;
 }
 
 }  // namespace
@@ -139,7 +133,7 @@ struct gf_plan {
     int field = 8;
     int dev = 0;
     int count = 0;
-    Variant v{4, 32};
+    int fixed_D = 0;   // 0: lane width chosen per tile
     int grid = 0;
     int ntiles = 0;
     DevGen *d_gens = nullptr;
@@ -255,12 +249,15 @@ static int encode_impl(int field, const uint8_t *C, int K, int N, const uint8_t 
     int rc = current_state(&d);
     if (rc)
         return rc;
-    Variant v = from_tuning(tune, pick_variant(K, N, len, d->cus));
-    if (!variant_ok(v))
-        return GF_EINVAL;
-    const bool al = aligned_rows(S, N > 1 ? ld_s : 0, v.D) && aligned_rows(Y, K > 1 ? ld_y : 0, v.D);
-    return dev_err(launch_encode(v, C, K, N, S, ld_s, Y, ld_y, len, field_ptab(d, field), status, need, al,
-                                 (hipStream_t)stream));
+    const uint32_t al = row_align(S, N > 1 ? ld_s : 0, Y, K > 1 ? ld_y : 0);
+    Single sc = pick_single(K, N, len, al, d->cus);
+    if (tune && tune->bytes_per_lane) {
+        if (tune->bytes_per_lane != 4 && tune->bytes_per_lane != 8 && tune->bytes_per_lane != 16)
+            return GF_EINVAL;
+        sc.D = tune->bytes_per_lane / 4;
+    }
+    return dev_err(launch_encode(sc.D, sc.nsplit, C, K, N, S, ld_s, Y, ld_y, len, field_ptab(d, field), status, need,
+                                 al >= 4u * (uint32_t)sc.D, (hipStream_t)stream));
 }
 
 int gf_encode(int field, const uint8_t *C, int K, int N, const uint8_t *S, size_t ld_s, uint8_t *Y, size_t ld_y,
@@ -381,34 +378,26 @@ static int upload(T **dst, const std::vector<T> &src)
     return GF_OK;
 }
 
-// Choose one variant for a whole batch: minimise padded work plus per-tile
-// overhead summed over the generations.
-static Variant pick_batch_variant(const std::vector<DevGen> &g)
+// Wave tiles of one generation: blocks of ENC_ROWS coded rows times payload
+// strips.  Full strips use 16 bytes per lane (1024 B per wave); the last
+// partial strip uses the narrowest lane width that covers it, so at most a
+// few lanes idle.  `fixed_D` forces one width for every strip.
+static void gen_tiles(uint32_t gi, const DevGen &x, int fixed_D, std::vector<std::pair<DevTile, double>> &out)
 {
-    static const int Ds[3] = {4, 2, 1};
-    static const int KWs[3] = {32, 16, 8};
-    Variant best{4, 32};
-    double best_cost = 1e300;
-    for (int kw : KWs)
-        for (int D : Ds) {
-            const uint64_t strip = strip_bytes(D);
-            double cost = 0;
-            for (const DevGen &x : g) {
-                if (x.K == 0 || x.len == 0)
-                    continue;
-                const double strips = (double)((x.len + strip - 1) / strip);
-                const double kb = (double)((x.K + kw - 1) / kw);
-                // padded (row, byte) pairs times sources, plus per-tile table staging and
-                // source re-reads, which fall with more rows per tile
-                cost += strips * kb * ((double)strip * kw * x.N * (1.0 + 0.08 / D) + (double)strip * x.N * 2.0 +
-                                       4096.0);
-            }
-            if (cost < best_cost) {
-                best_cost = cost;
-                best = Variant{D, kw};
-            }
+    if (x.K == 0 || x.len == 0)
+        return;
+    for (uint32_t k0 = 0; k0 < x.K; k0 += ENC_ROWS) {
+        const double rows = (double)std::min<uint32_t>(ENC_ROWS, x.K - k0);
+        uint64_t p0 = 0;
+        while (p0 < x.len) {
+            const uint64_t rest = x.len - p0;
+            int D = fixed_D;
+            if (!D)
+                D = rest > wave_strip(2) ? 4 : rest > wave_strip(1) ? 2 : 1;
+            out.push_back({DevTile{gi, (uint16_t)k0, (uint16_t)D, p0}, (double)x.N * rows * (double)wave_strip(D)});
+            p0 += wave_strip(D);
         }
-    return best;
+    }
 }
 
 static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, const gf_tuning *tune)
@@ -417,33 +406,25 @@ static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, co
     int rc = current_state(&d);
     if (rc)
         return rc;
-    p->v = from_tuning(tune, pick_batch_variant(gens));
-    if (!variant_ok(p->v))
-        return GF_EINVAL;
+    if (tune && tune->bytes_per_lane) {
+        if (tune->bytes_per_lane != 4 && tune->bytes_per_lane != 8 && tune->bytes_per_lane != 16)
+            return GF_EINVAL;
+        p->fixed_D = tune->bytes_per_lane / 4;
+    }
     std::vector<DevGen> g = gens;
     for (DevGen &x : g)
-        x.aligned = aligned_rows(x.S, x.N > 1 ? x.ld_s : 0, p->v.D) && aligned_rows(x.Y, x.K > 1 ? x.ld_y : 0, p->v.D);
-    const uint64_t strip = strip_bytes(p->v.D);
-    struct T {
-        DevTile t;
-        double cost;
-    };
-    std::vector<T> tiles;
-    for (size_t i = 0; i < g.size(); i++) {
-        const DevGen &x = g[i];
-        if (x.K == 0 || x.len == 0)
-            continue;
-        for (uint32_t k0 = 0; k0 < x.K; k0 += (uint32_t)p->v.KW)
-            for (uint64_t p0 = 0; p0 < x.len; p0 += strip) {
-                const double cost = (double)x.N * (double)std::min<uint64_t>(strip, x.len - p0);
-                tiles.push_back(T{DevTile{(uint32_t)i, k0, p0}, cost});
-            }
-    }
+        x.align = row_align(x.S, x.N > 1 ? x.ld_s : 0, x.Y, x.K > 1 ? x.ld_y : 0);
+    std::vector<std::pair<DevTile, double>> tiles;
+    for (size_t i = 0; i < g.size(); i++)
+        gen_tiles((uint32_t)i, g[i], p->fixed_D, tiles);
     // longest tiles first (LPT order); ties keep a generation's tiles together
-    std::stable_sort(tiles.begin(), tiles.end(), [](const T &a, const T &b) { return a.cost > b.cost; });
+    std::stable_sort(tiles.begin(), tiles.end(),
+                     [](const std::pair<DevTile, double> &a, const std::pair<DevTile, double> &b) {
+                         return a.second > b.second;
+                     });
     std::vector<DevTile> tl(tiles.size());
     for (size_t i = 0; i < tiles.size(); i++)
-        tl[i] = tiles[i].t;
+        tl[i] = tiles[i].first;
     p->ntiles = (int)tl.size();
     if ((rc = upload(&p->d_gens, g)) || (rc = upload(&p->d_tiles, tl)))
         return rc;
@@ -451,10 +432,10 @@ static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, co
         return GF_ENOMEM;
     if (hipMemset(p->d_ctr, 0, 2 * sizeof(unsigned)) != hipSuccess)
         return GF_EDEVICE;
-    int grid = d->cus * encode_blocks_per_cu(p->v);
+    int grid = d->cus * encode_blocks_per_cu();
     if (tune && tune->grid_blocks > 0)
         grid = tune->grid_blocks;
-    p->grid = std::max(1, std::min(grid, std::max(1, p->ntiles)));
+    p->grid = std::max(1, std::min(grid, std::max(1, (p->ntiles + 3) / 4)));
     if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
         return GF_EDEVICE;
     if (hipDeviceSynchronize() != hipSuccess)
@@ -477,7 +458,7 @@ int gf_plan_encode(int field, const gf_gen *gens, int count, const gf_tuning *tu
         int rc = check_encode_args(field, x.C, (int)x.K, (int)x.N, x.S, x.ld_s, x.Y, x.ld_y, x.len);
         if (rc)
             return rc;
-        g[i] = DevGen{x.C, x.S, x.Y, x.len, x.ld_s, x.ld_y, x.K, x.N, nullptr, 0, 0};
+        g[i] = DevGen{x.C, x.S, x.Y, x.len, x.ld_s, x.ld_y, x.K, x.N, nullptr, 0, 1};
     }
     gf_plan *p = new (std::nothrow) gf_plan;
     if (!p)
@@ -552,7 +533,7 @@ int gf_plan_decode(int field, const gf_sys *sys, int count, const gf_tuning *tun
     std::vector<DevGen> g(count);
     for (int i = 0; i < count; i++) {
         const gf_sys &s = sys[i];
-        g[i] = DevGen{p->d_cinv + off[i], s.B, s.S, s.len, s.ld_b, s.ld_s, s.N, s.N, p->d_rank + i, (int)s.N, 0};
+        g[i] = DevGen{p->d_cinv + off[i], s.B, s.S, s.len, s.ld_b, s.ld_s, s.N, s.N, p->d_rank + i, (int)s.N, 1};
     }
     if (!rc)
         rc = build_encode_schedule(p, g, tune);
@@ -582,8 +563,7 @@ static int run_plan(gf_plan *p, int *d_rank, hipStream_t s)
                 return GF_EDEVICE;
         }
     }
-    hipError_t e =
-        launch_encode_persistent(p->v, p->d_gens, p->d_tiles, p->ntiles, p->d_ctr, p->grid, field_ptab(d, f), s);
+    hipError_t e = launch_encode_persistent(p->d_gens, p->d_tiles, p->ntiles, p->d_ctr, p->grid, field_ptab(d, f), s);
     if (e != hipSuccess)
         return GF_EDEVICE;
     if (p->kind == 1 && d_rank && p->count > 0)
@@ -643,9 +623,9 @@ int gf_plan_tuning(const gf_plan *p, gf_tuning *out)
     if (!p || !out)
         return GF_EINVAL;
     out->form = 1;
-    out->bytes_per_lane = 4 * p->v.D;
-    out->rows_per_block = p->v.KW;
+    out->bytes_per_lane = 4 * p->fixed_D;
     out->grid_blocks = p->grid;
+    out->reserved = 0;
     return GF_OK;
 }
 

@@ -41,13 +41,15 @@ struct DevGen {
     uint32_t K, N;
     const int *status;   // if non-null, the generation is skipped unless *status == need
     int need;
-    uint32_t aligned;    // rows meet the vector-load alignment of the plan's variant
+    uint32_t align;      // largest of 16, 8, 4, 1 dividing S, Y, ld_s and ld_y
 };
 
-// One work tile of the persistent encode: KW coded rows x one block strip.
+// One wave tile of the persistent encode: up to ENC_ROWS coded rows from k0,
+// over the 256*D payload bytes starting at p0 (D dwords per lane).
 struct DevTile {
     uint32_t gen;
-    uint32_t k0;
+    uint16_t k0;
+    uint16_t D;
     uint64_t p0;
 };
 
@@ -59,28 +61,26 @@ struct DevSys {
     uint32_t pad;
 };
 
-struct Variant {
-    int D;    // dwords per lane (1, 2, 4)
-    int KW;   // coded rows per block (8, 16, 32)
-};
-
-// Strip of payload bytes covered by one 256-thread block.
-inline uint64_t strip_bytes(int D) { return 4ull * 64ull * 4ull * (uint64_t)D; }
-inline bool variant_ok(const Variant &v) {
-    return (v.D == 1 || v.D == 2 || v.D == 4) && (v.KW == 8 || v.KW == 16 || v.KW == 32);
-}
+#ifndef GF_ENC_ROWS
+#define GF_ENC_ROWS 24
+#endif
+#ifndef GF_ENC_WAVES_PER_SIMD
+#define GF_ENC_WAVES_PER_SIMD 2
+#endif
+constexpr int ENC_ROWS = GF_ENC_ROWS;   // coded rows per wave tile
+inline uint64_t wave_strip(int D) { return 256ull * (uint64_t)D; }
 
 hipError_t launch_region(int mode, uint8_t *y, const uint8_t *x, uint64_t len, const uint32_t *tab_host8,
                          hipStream_t s);
 hipError_t launch_region_batched(const void *d_regions, int count, uint64_t max_len, const uint32_t *ptab_field,
                                  int q, hipStream_t s);
-hipError_t launch_encode(const Variant &v, const uint8_t *C, int K, int N, const uint8_t *S, uint64_t ld_s,
+hipError_t launch_encode(int D, int nsplit, const uint8_t *C, int K, int N, const uint8_t *S, uint64_t ld_s,
                          uint8_t *Y, uint64_t ld_y, uint64_t len, const uint32_t *ptab_field, const int *status,
                          int need, bool aligned, hipStream_t s);
-hipError_t launch_encode_persistent(const Variant &v, const DevGen *gens, const DevTile *tiles, int ntiles,
-                                    unsigned *counters, int grid, const uint32_t *ptab_field, hipStream_t s);
+hipError_t launch_encode_persistent(const DevGen *gens, const DevTile *tiles, int ntiles, unsigned *counters,
+                                    int grid, const uint32_t *ptab_field, hipStream_t s);
 hipError_t launch_invert(const DevSys *sys, int count, const uint8_t *C, int N, uint8_t *Cinv, int *rank,
                          const uint32_t *ptab_field, const uint8_t *inv_field, hipStream_t s);
-int encode_blocks_per_cu(const Variant &v);
+int encode_blocks_per_cu();
 
 }  // namespace gfnc

@@ -16,6 +16,8 @@
 // payload strip in registers and streams the N source rows through them once;
 // the per-(row, source) tables are staged in LDS and read with wave-uniform
 // addresses (broadcast, no bank conflicts).
+#include <algorithm>
+
 #include "gf_internal.h"
 
 namespace gfnc {
@@ -196,19 +198,55 @@ __global__ __launch_bounds__(256) void k_region_batched(const RegionDesc *__rest
 
 // ------------------------------------------------------------------ encode
 
-// One tile: KW coded rows (k0 ...) x one block strip of 4 waves * 64 lanes *
-// 4D bytes starting at p0.  Every thread of the block must call this.
-template <int D, int KW>
-__device__ __forceinline__ void enc_tile(const uint8_t *__restrict__ C, int K, int N,
-                                         const uint8_t *__restrict__ S, uint64_t ld_s, uint8_t *__restrict__ Y,
-                                         uint64_t ld_y, uint64_t len, int k0, uint64_t p0, bool vec,
-                                         const uint4 *__restrict__ ptab4, uint4 (*tabs)[NC][2])
+constexpr int KW = ENC_ROWS;   // coded rows per wave tile
+constexpr int NCW = 8;     // source rows per table stage (even)
+constexpr int WAVES = 4;   // waves per workgroup
+
+// One wave's staged product tables: [coded row][source row][2 x uint4].
+struct WaveStage {
+    uint4 t[KW][NCW][2];
+};
+
+__device__ __forceinline__ void wave_sync()
 {
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const uint64_t p = p0 + (uint64_t)wave * (256u * D) + (uint64_t)lane * (4u * D);
-    const bool active = p < len;
-    const uint64_t avail = active ? len - p : 0;
+    // LDS operations of one wavefront complete in order; this only keeps the
+    // compiler from moving LDS accesses across the stage boundary.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+template <int D>
+__device__ __forceinline__ void load_lane(const uint8_t *p, uint64_t avail, bool vec, uint32_t (&x)[D])
+{
+    if (avail == 0) {
+#pragma unroll
+        for (int d = 0; d < D; d++)
+            x[d] = 0;
+    } else {
+        load_row<D>(p, avail, vec, x);
+    }
+}
+
+// One wave tile: coded rows k0 .. k0+min(KW, K-k0)-1 over the 256*D payload
+// bytes starting at p0 (4*D bytes per lane).  The N source rows stream
+// through in pairs; each coded row accumulates, per dword of 4 bytes, the
+// three byte-select products of both sources with two 3-input XORs.
+template <int D>
+__device__ __forceinline__ void wave_tile(const uint8_t *__restrict__ C, int K, int N,
+                                          const uint8_t *__restrict__ S, uint64_t ld_s, uint8_t *__restrict__ Y,
+                                          uint64_t ld_y, uint64_t len, int k0, uint64_t p0, bool vec,
+                                          const uint4 *__restrict__ ptab4, WaveStage &st, int lane, int nb, int ne,
+                                          bool atomic_out)
+{
+    const uint64_t p = p0 + (uint64_t)lane * (4u * D);
+    const uint64_t avail = p < len ? len - p : 0;
+    const int kv = min(KW, K - k0);
 
     uint32_t acc[KW][D];
 #pragma unroll
@@ -217,93 +255,211 @@ __device__ __forceinline__ void enc_tile(const uint8_t *__restrict__ C, int K, i
         for (int d = 0; d < D; d++)
             acc[kk][d] = 0;
 
-    for (int n0 = 0; n0 < N; n0 += NC) {
-        const int nc = min(NC, N - n0);
-        __syncthreads();
-        for (int idx = tid; idx < KW * NC; idx += 256) {
-            const int kk = idx / NC, nn = idx % NC;
-            const int k = k0 + kk;
-            const uint32_t c = (k < K && nn < nc) ? (uint32_t)C[(uint64_t)k * N + n0 + nn] : 0u;
-            tabs[kk][nn][0] = ptab4[c * 2];
-            tabs[kk][nn][1] = ptab4[c * 2 + 1];
+    const uint8_t *src = S + p;
+    uint32_t xa[D], xb[D];
+    load_lane<D>(src + (uint64_t)nb * ld_s, avail, vec, xa);
+    if (nb + 1 < ne)
+        load_lane<D>(src + (uint64_t)(nb + 1) * ld_s, avail, vec, xb);
+    else
+#pragma unroll
+        for (int d = 0; d < D; d++)
+            xb[d] = 0;
+
+    for (int g = nb; g < ne; g += 2) {
+        const int nn = (g - nb) & (NCW - 1);
+        if (nn == 0) {
+            wave_sync();
+            const int nc = min(NCW, ne - g);
+#pragma unroll
+            for (int e = lane; e < KW * NCW; e += 64) {
+                const int kk = e / NCW, j = e % NCW;
+                const uint32_t c = (kk < kv && j < nc) ? (uint32_t)C[(uint64_t)(k0 + kk) * N + g + j] : 0u;
+                st.t[kk][j][0] = ptab4[c * 2];
+                st.t[kk][j][1] = ptab4[c * 2 + 1];
+            }
+            wave_sync();
         }
-        __syncthreads();
-        if (active) {
-            const uint8_t *src = S + (uint64_t)n0 * ld_s + p;
-            uint32_t xn[D];
-            load_row<D>(src, avail, vec, xn);
-            for (int nn = 0; nn < nc; nn++) {
-                uint32_t x[D];
+        Sel sa[D], sb[D];
 #pragma unroll
-                for (int d = 0; d < D; d++)
-                    x[d] = xn[d];
-                if (nn + 1 < nc)
-                    load_row<D>(src + (uint64_t)(nn + 1) * ld_s, avail, vec, xn);
-                Sel s[D];
+        for (int d = 0; d < D; d++) {
+            sa[d] = split(xa[d]);
+            sb[d] = split(xb[d]);
+        }
+        const bool two = g + 1 < ne;
+        if (g + 2 < ne)
+            load_lane<D>(src + (uint64_t)(g + 2) * ld_s, avail, vec, xa);
+        if (g + 3 < ne)
+            load_lane<D>(src + (uint64_t)(g + 3) * ld_s, avail, vec, xb);
+        if (two) {
 #pragma unroll
-                for (int d = 0; d < D; d++)
-                    s[d] = split(x[d]);
+            for (int k8 = 0; k8 < KW; k8 += 8) {
+                if (k8 < kv) {
 #pragma unroll
-                for (int kk = 0; kk < KW; kk++) {
-                    const uint4 ta = tabs[kk][nn][0];
-                    const uint32_t tb = tabs[kk][nn][1].x;
+                    for (int kk = k8; kk < k8 + 8; kk++) {
+                        const uint4 a0 = st.t[kk][nn][0];
+                        const uint32_t b0 = st.t[kk][nn][1].x;
+                        const uint4 a1 = st.t[kk][nn + 1][0];
+                        const uint32_t b1 = st.t[kk][nn + 1][1].x;
 #pragma unroll
-                    for (int d = 0; d < D; d++)
-                        acc[kk][d] ^= prod(ta.x, ta.y, ta.z, ta.w, tb, s[d]);
+                        for (int d = 0; d < D; d++) {
+                            const uint32_t p0_ = __builtin_amdgcn_perm(a0.y, a0.x, sa[d].a);
+                            const uint32_t p1_ = __builtin_amdgcn_perm(a0.w, a0.z, sa[d].b);
+                            const uint32_t p2_ = __builtin_amdgcn_perm(b0, b0, sa[d].c);
+                            const uint32_t q0_ = __builtin_amdgcn_perm(a1.y, a1.x, sb[d].a);
+                            const uint32_t q1_ = __builtin_amdgcn_perm(a1.w, a1.z, sb[d].b);
+                            const uint32_t q2_ = __builtin_amdgcn_perm(b1, b1, sb[d].c);
+                            acc[kk][d] = xor3(xor3(xor3(acc[kk][d], p0_, p1_), p2_, q0_), q1_, q2_);
+                        }
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k8 = 0; k8 < KW; k8 += 8) {
+                if (k8 < kv) {
+#pragma unroll
+                    for (int kk = k8; kk < k8 + 8; kk++) {
+                        const uint4 a0 = st.t[kk][nn][0];
+                        const uint32_t b0 = st.t[kk][nn][1].x;
+#pragma unroll
+                        for (int d = 0; d < D; d++) {
+                            const uint32_t p0_ = __builtin_amdgcn_perm(a0.y, a0.x, sa[d].a);
+                            const uint32_t p1_ = __builtin_amdgcn_perm(a0.w, a0.z, sa[d].b);
+                            const uint32_t p2_ = __builtin_amdgcn_perm(b0, b0, sa[d].c);
+                            acc[kk][d] = xor3(acc[kk][d], p0_, p1_) ^ p2_;
+                        }
+                    }
                 }
             }
         }
     }
-    if (active) {
+    if (avail == 0)
+        return;
+    if (atomic_out) {
+        // Partial sum over a slice of the sources: XOR it into the zeroed
+        // output.  Rows are 4-byte aligned here; only whole dwords below
+        // len & ~3 are written (the last 0-3 bytes of each row are computed
+        // by k_encode_tail).
+        const uint64_t len4 = len & ~(uint64_t)3;
 #pragma unroll
         for (int kk = 0; kk < KW; kk++)
-            if (k0 + kk < K)
-                store_row<D>(Y + (uint64_t)(k0 + kk) * ld_y + p, avail, vec, acc[kk]);
+            if (kk < kv) {
+                uint32_t *yp = reinterpret_cast<uint32_t *>(Y + (uint64_t)(k0 + kk) * ld_y + p);
+#pragma unroll
+                for (int d = 0; d < D; d++)
+                    if (p + 4u * d + 4u <= len4)
+                        atomicXor(yp + d, acc[kk][d]);
+            }
+        return;
+    }
+#pragma unroll
+    for (int kk = 0; kk < KW; kk++)
+        if (kk < kv)
+            store_row<D>(Y + (uint64_t)(k0 + kk) * ld_y + p, avail, vec, acc[kk]);
+}
+
+// Single generation: wave w of block b takes tile b*WAVES + w; tiles run
+// over payload strips of 256*D bytes, then over `nsplit` slices of the
+// sources (each slice's partial sum is XORed into a zeroed output), then over
+// blocks of KW coded rows.
+template <int D>
+__global__ __launch_bounds__(256, GF_ENC_WAVES_PER_SIMD) void k_encode_direct(
+    const uint8_t *__restrict__ C, int K, int N, const uint8_t *__restrict__ S, uint64_t ld_s,
+    uint8_t *__restrict__ Y, uint64_t ld_y, uint64_t len, const uint4 *__restrict__ ptab4,
+    const int *__restrict__ status, int need, int vec, uint32_t nstrips, uint32_t nsplit, uint32_t ntiles)
+{
+    __shared__ WaveStage stage[WAVES];
+    if (status && *status != need)
+        return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t t = blockIdx.x * WAVES + wave;
+    if (t >= ntiles)
+        return;
+    const uint32_t strip = t % nstrips;
+    const uint32_t rest = t / nstrips;
+    const uint32_t sl = rest % nsplit, kb = rest / nsplit;
+    const int chunk = (((N + (int)nsplit - 1) / (int)nsplit) + 1) & ~1;
+    const int nb = (int)sl * chunk, ne = min(N, nb + chunk);
+    if (nb >= ne)
+        return;
+    wave_tile<D>(C, K, N, S, ld_s, Y, ld_y, len, (int)(kb * KW), (uint64_t)strip * (256u * D), vec != 0, ptab4,
+                 stage[wave], lane, nb, ne, nsplit > 1);
+}
+
+// The last len % 4 bytes of every coded row, each computed in full by one
+// thread (used with the source-sliced launch, whose atomics cover whole dwords).
+__global__ __launch_bounds__(256) void k_encode_tail(const uint8_t *__restrict__ C, int K, int N,
+                                                     const uint8_t *__restrict__ S, uint64_t ld_s,
+                                                     uint8_t *__restrict__ Y, uint64_t ld_y, uint64_t len,
+                                                     const uint4 *__restrict__ ptab4,
+                                                     const int *__restrict__ status, int need)
+{
+    if (status && *status != need)
+        return;
+    const int tail = (int)(len & 3);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= K * tail)
+        return;
+    const int k = i / tail;
+    const uint64_t b = (len & ~(uint64_t)3) + (uint64_t)(i - k * tail);
+    uint32_t acc = 0;
+    for (int n = 0; n < N; n++) {
+        const uint32_t c = C[(uint64_t)k * N + n];
+        acc ^= prod4(ptab4[c * 2], ptab4[c * 2 + 1].x, (uint32_t)S[(uint64_t)n * ld_s + b]);
+    }
+    Y[(uint64_t)k * ld_y + b] = (uint8_t)acc;
+}
+
+// Y rows := 0 up to len & ~3 (before a launch that accumulates source slices
+// atomically).
+__global__ __launch_bounds__(256) void k_zero_rows(uint8_t *Y, uint64_t ld_y, uint64_t len, int K,
+                                                   const int *__restrict__ status, int need)
+{
+    if (status && *status != need)
+        return;
+    const uint64_t words = len / 4;
+    const uint64_t total = words * (uint64_t)K;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = i / words, w = i - k * words;
+        reinterpret_cast<uint32_t *>(Y + k * ld_y)[w] = 0;
     }
 }
 
-template <int D, int KW>
-__global__ __launch_bounds__(256) void k_encode(const uint8_t *__restrict__ C, int K, int N,
-                                                const uint8_t *__restrict__ S, uint64_t ld_s,
-                                                uint8_t *__restrict__ Y, uint64_t ld_y, uint64_t len,
-                                                const uint4 *__restrict__ ptab4, const int *__restrict__ status,
-                                                int need, int vec)
+// Persistent encode over a tile list; every wave takes tiles on its own.
+// counters[0] hands out tiles, counters[1] counts retired waves; the last
+// wave to retire resets both so the next launch (or graph replay) starts
+// from zero without a memset.
+__global__ __launch_bounds__(256, GF_ENC_WAVES_PER_SIMD) void k_encode_waves(const DevGen *__restrict__ gens,
+                                                      const DevTile *__restrict__ tiles, int ntiles,
+                                                      unsigned *counters, const uint4 *__restrict__ ptab4)
 {
-    __shared__ uint4 tabs[KW][NC][2];
-    if (status && *status != need)
-        return;
-    enc_tile<D, KW>(C, K, N, S, ld_s, Y, ld_y, len, (int)blockIdx.y * KW,
-                    (uint64_t)blockIdx.x * (1024u * D), vec != 0, ptab4, tabs);
-}
-
-// Persistent encode over a tile list.  counters[0] hands out tiles,
-// counters[1] counts retired blocks; the last block to retire resets both so
-// the next launch (or graph replay) starts from zero without a memset.
-template <int D, int KW>
-__global__ __launch_bounds__(256) void k_encode_persistent(const DevGen *__restrict__ gens,
-                                                           const DevTile *__restrict__ tiles, int ntiles,
-                                                           unsigned *counters, const uint4 *__restrict__ ptab4)
-{
-    __shared__ uint4 tabs[KW][NC][2];
-    __shared__ int s_tile;
+    __shared__ WaveStage stage[WAVES];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (;;) {
-        if (threadIdx.x == 0)
-            s_tile = (int)atomicAdd(&counters[0], 1u);
-        __syncthreads();
-        const int t = s_tile;
-        __syncthreads();
-        if (t >= ntiles)
+        unsigned t = 0;
+        if (lane == 0)
+            t = atomicAdd(&counters[0], 1u);
+        t = __builtin_amdgcn_readlane(t, 0);
+        if (t >= (unsigned)ntiles)
             break;
         const DevTile tl = tiles[t];
         const DevGen g = gens[tl.gen];
         if (g.status && *g.status != g.need)
             continue;
-        enc_tile<D, KW>(g.C, (int)g.K, (int)g.N, g.S, g.ld_s, g.Y, g.ld_y, g.len, (int)tl.k0, tl.p0,
-                        g.aligned != 0, ptab4, tabs);
+        if (tl.D == 4)
+            wave_tile<4>(g.C, (int)g.K, (int)g.N, g.S, g.ld_s, g.Y, g.ld_y, g.len, (int)tl.k0, tl.p0,
+                         g.align >= 16, ptab4, stage[wave], lane, 0, (int)g.N, false);
+        else if (tl.D == 2)
+            wave_tile<2>(g.C, (int)g.K, (int)g.N, g.S, g.ld_s, g.Y, g.ld_y, g.len, (int)tl.k0, tl.p0,
+                         g.align >= 8, ptab4, stage[wave], lane, 0, (int)g.N, false);
+        else
+            wave_tile<1>(g.C, (int)g.K, (int)g.N, g.S, g.ld_s, g.Y, g.ld_y, g.len, (int)tl.k0, tl.p0,
+                         g.align >= 4, ptab4, stage[wave], lane, 0, (int)g.N, false);
     }
-    if (threadIdx.x == 0) {
+    if (lane == 0) {
         __threadfence();
-        if (atomicAdd(&counters[1], 1u) == gridDim.x - 1) {
+        if (atomicAdd(&counters[1], 1u) == gridDim.x * WAVES - 1) {
             atomicExch(&counters[0], 0u);
             atomicExch(&counters[1], 0u);
         }
@@ -525,73 +681,65 @@ hipError_t launch_region_batched(const void *d_regions, int count, uint64_t max_
     return hipSuccess;
 }
 
-#define GF_ENC_DISPATCH(MACRO)                                                                                   \
-    switch (v.D * 100 + v.KW) {                                                                                  \
-    case 108: MACRO(1, 8); break;                                                                                \
-    case 116: MACRO(1, 16); break;                                                                               \
-    case 132: MACRO(1, 32); break;                                                                               \
-    case 208: MACRO(2, 8); break;                                                                                \
-    case 216: MACRO(2, 16); break;                                                                               \
-    case 232: MACRO(2, 32); break;                                                                               \
-    case 408: MACRO(4, 8); break;                                                                                \
-    case 416: MACRO(4, 16); break;                                                                               \
-    case 432: MACRO(4, 32); break;                                                                               \
-    default: return hipErrorInvalidValue;                                                                        \
-    }
-
-hipError_t launch_encode(const Variant &v, const uint8_t *C, int K, int N, const uint8_t *S, uint64_t ld_s,
+hipError_t launch_encode(int D, int nsplit, const uint8_t *C, int K, int N, const uint8_t *S, uint64_t ld_s,
                          uint8_t *Y, uint64_t ld_y, uint64_t len, const uint32_t *ptab_field, const int *status,
                          int need, bool aligned, hipStream_t s)
 {
     if (K <= 0 || len == 0)
         return hipSuccess;
-    const uint64_t gx = (len + strip_bytes(v.D) - 1) / strip_bytes(v.D);
-    const unsigned gy = (unsigned)((K + v.KW - 1) / v.KW);
+    if (nsplit < 1 || nsplit > N)
+        nsplit = 1;
+    const uint64_t strip = 256u * (uint64_t)D;
+    const uint64_t nstrips = (len + strip - 1) / strip;
+    const uint64_t ntiles = nstrips * (uint64_t)nsplit * (uint64_t)((K + KW - 1) / KW);
+    if (ntiles > 0xFFFFFFFFull / 2)
+        return hipErrorInvalidValue;
+    const unsigned blocks = (unsigned)((ntiles + WAVES - 1) / WAVES);
     const uint4 *pt = reinterpret_cast<const uint4 *>(ptab_field);
-#define GF_LAUNCH_ENC(DD, KK)                                                                                    \
-    hipLaunchKernelGGL((k_encode<DD, KK>), dim3((unsigned)gx, gy), dim3(256), 0, s, C, K, N, S, ld_s, Y, ld_y,    \
-                       len, pt, status, need, aligned ? 1 : 0)
-    GF_ENC_DISPATCH(GF_LAUNCH_ENC)
-#undef GF_LAUNCH_ENC
+    const int vec = aligned ? 1 : 0;
+    if (nsplit > 1) {
+        const uint64_t words = (len / 4) * (uint64_t)K;
+        if (words > 0) {
+            const unsigned zb = (unsigned)std::min<uint64_t>((words + 255) / 256, 4096);
+            hipLaunchKernelGGL(k_zero_rows, dim3(zb), dim3(256), 0, s, Y, ld_y, len, K, status, need);
+        }
+        if (len & 3) {
+            const unsigned tb = (unsigned)((K * (int)(len & 3) + 255) / 256);
+            hipLaunchKernelGGL(k_encode_tail, dim3(tb), dim3(256), 0, s, C, K, N, S, ld_s, Y, ld_y, len, pt, status,
+                               need);
+        }
+    }
+#define GF_DIRECT(DD)                                                                                            \
+    hipLaunchKernelGGL(k_encode_direct<DD>, dim3(blocks), dim3(256), 0, s, C, K, N, S, ld_s, Y, ld_y, len, pt,   \
+                       status, need, vec, (uint32_t)nstrips, (uint32_t)nsplit, (uint32_t)ntiles)
+    if (D == 4)
+        GF_DIRECT(4);
+    else if (D == 2)
+        GF_DIRECT(2);
+    else if (D == 1)
+        GF_DIRECT(1);
+    else
+        return hipErrorInvalidValue;
+#undef GF_DIRECT
     return hipGetLastError();
 }
 
-hipError_t launch_encode_persistent(const Variant &v, const DevGen *gens, const DevTile *tiles, int ntiles,
-                                    unsigned *counters, int grid, const uint32_t *ptab_field, hipStream_t s)
+hipError_t launch_encode_persistent(const DevGen *gens, const DevTile *tiles, int ntiles, unsigned *counters,
+                                    int grid, const uint32_t *ptab_field, hipStream_t s)
 {
     if (ntiles <= 0)
         return hipSuccess;
-    const uint4 *pt = reinterpret_cast<const uint4 *>(ptab_field);
-#define GF_LAUNCH_PERS(DD, KK)                                                                                   \
-    hipLaunchKernelGGL((k_encode_persistent<DD, KK>), dim3(grid), dim3(256), 0, s, gens, tiles, ntiles, counters, \
-                       pt)
-    GF_ENC_DISPATCH(GF_LAUNCH_PERS)
-#undef GF_LAUNCH_PERS
+    hipLaunchKernelGGL(k_encode_waves, dim3(grid), dim3(256), 0, s, gens, tiles, ntiles, counters,
+                       reinterpret_cast<const uint4 *>(ptab_field));
     return hipGetLastError();
 }
 
-int encode_blocks_per_cu(const Variant &v)
+int encode_blocks_per_cu()
 {
     int nb = 0;
-    hipError_t e = hipErrorInvalidValue;
-#define GF_OCC(DD, KK)                                                                                           \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(                         \
-                                                              &k_encode_persistent<DD, KK>),                      \
-                                                     256, 0)
-    switch (v.D * 100 + v.KW) {
-    case 108: GF_OCC(1, 8); break;
-    case 116: GF_OCC(1, 16); break;
-    case 132: GF_OCC(1, 32); break;
-    case 208: GF_OCC(2, 8); break;
-    case 216: GF_OCC(2, 16); break;
-    case 232: GF_OCC(2, 32); break;
-    case 408: GF_OCC(4, 8); break;
-    case 416: GF_OCC(4, 16); break;
-    case 432: GF_OCC(4, 32); break;
-    default: return 1;
-    }
-#undef GF_OCC
-    if (e != hipSuccess || nb < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_encode_waves), 256, 0) !=
+            hipSuccess ||
+        nb < 1)
         return 1;
     return nb;
 }

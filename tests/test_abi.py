@@ -1,0 +1,117 @@
+"""The C ABI without a GPU: the library loads, exports every declared entry
+point, and rejects bad arguments before touching a device."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1909_02871_amd as gf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gfnc.h")
+
+# Device pointers are never dereferenced by the argument checks; any nonzero
+# value stands in for one.  Buffers of 1 MiB at distinct addresses:
+P1, P2, P3, P4 = 0x10000000, 0x20000000, 0x30000000, 0x40000000
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gf_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(gf.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = gf.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", gf.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (gf_\w+)", out))
+    assert set(_declared()) <= exported
+
+
+def test_strerror():
+    assert gf.strerror(0) == "success"
+    assert "singular" in gf.strerror(gf.GF_ESINGULAR)
+    assert gf.strerror(-99) == "unknown error"
+
+
+def test_decode_workspace_sizes():
+    L = gf.lib()
+    assert L.gf_decode_workspace(0) == 0
+    assert L.gf_decode_workspace(257) == 0
+    for N in (1, 16, 100, 256):
+        ws = L.gf_decode_workspace(N)
+        assert ws >= N * N + 4 and ws % 256 == 0
+
+
+@pytest.mark.parametrize("field", [0, 3, 5, 16, -1])
+def test_bad_field(field):
+    L = gf.lib()
+    assert L.gf_region_madd(field, P1, P2, 1, 10, None) == gf.GF_EINVAL
+    assert L.gf_region_mul(field, P1, P2, 1, 10, None) == gf.GF_EINVAL
+    assert L.gf_encode(field, P1, 2, 2, P2, 10, P3, 10, 10, None) == gf.GF_EINVAL
+    assert L.gf_decode(field, P1, 2, P2, 10, P3, 10, 10, P4, 1 << 16, None, None) == gf.GF_EINVAL
+
+
+@pytest.mark.parametrize("field,c", [(1, 2), (2, 4), (4, 16), (8, 256), (8, -1)])
+def test_coefficient_outside_field(field, c):
+    assert gf.lib().gf_region_madd(field, P1, P2, c, 10, None) == gf.GF_EINVAL
+
+
+def test_region_argument_checks():
+    L = gf.lib()
+    # zero length is a no-op even with null pointers
+    assert L.gf_region_madd(8, None, None, 3, 0, None) == gf.GF_OK
+    assert L.gf_region_madd(8, None, P2, 3, 10, None) == gf.GF_EINVAL
+    # partial overlap is rejected
+    assert L.gf_region_madd(8, P1 + 5, P1, 3, 10, None) == gf.GF_EINVAL
+    assert L.gf_region_mul(8, P1, P1 + 9, 3, 10, None) == gf.GF_EINVAL
+
+
+def test_encode_argument_checks():
+    L = gf.lib()
+    assert L.gf_encode(8, P1, 2, 0, P2, 10, P3, 10, 10, None) == gf.GF_EINVAL      # N = 0
+    assert L.gf_encode(8, P1, -1, 2, P2, 10, P3, 10, 10, None) == gf.GF_EINVAL     # K < 0
+    assert L.gf_encode(8, P1, 2, 257, P2, 10, P3, 10, 10, None) == gf.GF_ERANGE    # N > 256
+    assert L.gf_encode(8, P1, 0, 2, P2, 10, P3, 10, 10, None) == gf.GF_OK          # K = 0: no-op
+    assert L.gf_encode(8, P1, 2, 2, P2, 10, P3, 10, 0, None) == gf.GF_OK           # len = 0: no-op
+    assert L.gf_encode(8, None, 2, 2, P2, 10, P3, 10, 10, None) == gf.GF_EINVAL
+    assert L.gf_encode(8, P1, 2, 2, P2, 5, P3, 10, 10, None) == gf.GF_EINVAL       # ld_s < len
+    assert L.gf_encode(8, P1, 2, 2, P2, 10, P2 + 5, 10, 10, None) == gf.GF_EINVAL  # Y overlaps S
+    assert L.gf_encode(8, P1, 2, 2, P2, 10, P1, 10, 10, None) == gf.GF_EINVAL      # Y overlaps C
+
+
+def test_decode_argument_checks():
+    L = gf.lib()
+    ws = L.gf_decode_workspace(4)
+    assert L.gf_decode(8, P1, 0, P2, 10, P3, 10, 10, P4, ws, None, None) == gf.GF_EINVAL
+    assert L.gf_decode(8, P1, 300, P2, 10, P3, 10, 10, P4, 1 << 20, None, None) == gf.GF_ERANGE
+    assert L.gf_decode(8, P1, 4, P2, 10, P3, 10, 10, P4, ws - 1, None, None) == gf.GF_EINVAL  # small ws
+    assert L.gf_decode(8, P1, 4, P2, 10, P2 + 3, 10, 10, P4, ws, None, None) == gf.GF_EINVAL  # S overlaps B
+    assert L.gf_decode(8, P1, 4, P2, 10, P3, 10, 10, P3 + 8, ws, None, None) == gf.GF_EINVAL  # ws overlaps S
+    assert L.gf_invert(8, P1, 4, P1 + 2, None, None) == gf.GF_EINVAL                          # Cinv overlaps C
+    assert L.gf_invert(8, P1, 0, P2, None, None) == gf.GF_EINVAL
+
+
+def test_plan_argument_checks():
+    L = gf.lib()
+    h = C.c_void_p()
+    bad = (gf.gf_gen * 1)(gf.gf_gen(P1, P2, P3, 2, 0, 10, 10, 10))       # N = 0
+    assert L.gf_plan_encode(8, bad, 1, None, C.byref(h)) == gf.GF_EINVAL and not h.value
+    big = (gf.gf_gen * 1)(gf.gf_gen(P1, P2, P3, 2, 300, 10, 10, 10))     # N > 256
+    assert L.gf_plan_encode(8, big, 1, None, C.byref(h)) == gf.GF_ERANGE
+    assert L.gf_plan_encode(3, bad, 1, None, C.byref(h)) == gf.GF_EINVAL
+    assert L.gf_plan_encode(8, bad, 1, None, None) == gf.GF_EINVAL
+    sysbad = (gf.gf_sys * 1)(gf.gf_sys(P1, P2, P3, 4, 1, 10, 10, 10))    # reserved != 0
+    assert L.gf_plan_decode(8, sysbad, 1, None, C.byref(h)) == gf.GF_EINVAL
+    assert L.gf_encode_batched(None, None) == gf.GF_EINVAL
+    assert L.gf_decode_batched(None, None, None) == gf.GF_EINVAL
+    assert L.gf_plan_launch_graph(None, None, None) == gf.GF_EINVAL
+    L.gf_plan_destroy(None)

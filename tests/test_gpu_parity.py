@@ -124,10 +124,10 @@ def test_encode(gf, n, K, N, L):
         assert (raw[mask] == 0x5A).all()
 
 
-@pytest.mark.parametrize("n", [4, 8])
-@pytest.mark.parametrize("bpl", [4, 8, 16])
-@pytest.mark.parametrize("rows", [8, 16, 32])
-def test_encode_every_variant(gf, n, bpl, rows):
+@pytest.mark.parametrize("n", FIELDS)
+@pytest.mark.parametrize("bpl", [0, 4, 8, 16])
+@pytest.mark.parametrize("grid", [0, 1, 7])
+def test_encode_every_variant(gf, n, bpl, grid):
     """Every schedule of the table kernel gives the same bytes (batched path, 30 generations)."""
     torch = torch_cuda()
     gens, keep, wants = [], [], []
@@ -141,8 +141,9 @@ def test_encode_every_variant(gf, n, bpl, rows):
         _, Sd = padded_rows(g.S, synth.padded(L))
         _, Yd = padded_rows(np.zeros((K, L), np.uint8), synth.padded(L))
         keep.append((Cd, Sd, Yd))
-    plan = gf.gf_plan_encode(n, keep, tune={"bytes_per_lane": bpl, "rows_per_block": rows})
-    assert plan.tuning()["bytes_per_lane"] == bpl and plan.tuning()["rows_per_block"] == rows
+    plan = gf.gf_plan_encode(n, keep, tune={"bytes_per_lane": bpl, "grid_blocks": grid})
+    assert plan.tuning()["bytes_per_lane"] == bpl
+    assert grid == 0 or plan.tuning()["grid_blocks"] == grid
     for rep in range(2):      # the work counter resets itself between launches
         for _, _, Yd in keep:
             Yd.zero_()
@@ -153,7 +154,7 @@ def test_encode_every_variant(gf, n, bpl, rows):
     # per-generation launches with the same schedule
     for _, _, Yd in keep:
         Yd.zero_()
-    gf.gf_encode_each(n, keep, tune={"bytes_per_lane": bpl, "rows_per_block": rows})
+    gf.gf_encode_each(n, keep, tune={"bytes_per_lane": bpl})
     torch.cuda.synchronize()
     for (Cd, Sd, Yd), w in zip(keep, wants):
         assert (host(Yd) == w).all()
