@@ -57,6 +57,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--bytes-per-lane", type=int, default=0)
+    ap.add_argument("--serve-requests", type=int, default=4000, help="requests per serving run (0: skip)")
+    ap.add_argument("--serve-budget-gib", type=float, default=4.0)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -95,7 +97,8 @@ def main():
         tune = {"bytes_per_lane": args.bytes_per_lane}
     t0 = time.time()
     plan = gf.gf_plan_encode_desc(n, descs, args.count, tune=tune, keep=(S_dev, C_dev, Y_dev))
-    log("plan built in %.2f s: %s" % (time.time() - t0, plan.tuning()))
+    tuning = plan.tuning()
+    log("plan built in %.2f s: %s" % (time.time() - t0, tuning))
 
     stream = torch.cuda.current_stream()
     launch = (lambda: gf.gf_encode_batched(plan)) if args.no_graph else (lambda: gf.gf_plan_launch_graph(plan))
@@ -189,6 +192,12 @@ def main():
                "seconds": round(dt, 2), "gpu_output_bit_exact_on_sample": ok}
         log("cpu oracle: %.4f GB/s over %d generations; GPU bit-exact on sample: %s" % (cpu["value"], len(picked), ok))
 
+    serve = None
+    if args.serve_requests > 0:
+        del S_dev, C_dev, Y_dev, plan
+        torch.cuda.empty_cache()
+        serve = serve_bench(gf, torch, args)
+
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
@@ -200,9 +209,100 @@ def main():
         "plain": plain,
         "speedup_vs_plain": round(value / plain["value"], 3) if plain else None,
         "hbm_roofline_gbs": round(hbm_roof_src, 1), "hbm_roofline_frac": round(value / hbm_roof_src, 4),
-        "roofline": roofline, "cpu_baseline": cpu, "tuning": plan.tuning(),
+        "roofline": roofline, "cpu_baseline": cpu, "tuning": tuning, "serve": serve,
     }
     print(json.dumps(out), flush=True)
+
+
+def serve_bench(gf, torch, args) -> dict:
+    """Serving: Poisson arrivals of 70% encode / 30% decode requests over GF(256).
+
+    N uniform in {8..256}, packet length log-uniform in [64, 9000] B; a decode
+    request receives the coded packets of a rateless sender (fresh uniform
+    coefficient vectors, 1.5 N emitted, 10% lost i.i.d., random order),
+    released one every microsecond from the request's arrival.  The server
+    admits requests by an HBM budget.  First a run with every request
+    arriving at once gives the saturation throughput; then runs at 50% and
+    80% of it give the latency percentiles.
+    """
+    from paper_1909_02871_amd.serving import TraceRequest, percentile, replay
+
+    n = 8
+    count = args.serve_requests
+    reqs = synth.serving_stream(count, 1.0)          # shapes and kinds; arrival times are rescaled below
+    unit_gaps = np.array([r.arrival_s for r in reqs])
+    # payload and coefficients: one blob each, sliced per request
+    enc = [r for r in reqs if r.kind == "encode"]
+    dec = [r for r in reqs if r.kind == "decode"]
+    pkt_per = {r.rid: int(np.ceil(1.5 * r.N)) for r in dec}
+    s_need = sum(r.N * synth.padded(r.length) for r in reqs)
+    c_need = sum(r.N * r.N for r in enc) + sum(pkt_per[r.rid] * r.N for r in dec)
+    base = synth.key(synth.BASE_SEED + 4, 99)
+    S_dev = torch.from_numpy(synth.random_bytes(synth.key(base, 1), s_need)).to("cuda")
+    C_dev = torch.from_numpy(synth.uniform_field(synth.key(base, 2), c_need, n)).to("cuda")
+    b_need = sum(pkt_per[r.rid] * synth.padded(r.length) for r in dec)
+    B_dev = torch.empty(max(b_need, 16), dtype=torch.uint8, device="cuda")
+    s_off = c_off = b_off = 0
+    trace = []
+    src_bytes = 0
+    for r in reqs:
+        ld = synth.padded(r.length)
+        S = S_dev[s_off:s_off + r.N * ld].view(r.N, ld)
+        s_off += r.N * ld
+        src_bytes += r.N * r.length
+        if r.kind == "encode":
+            Cm = C_dev[c_off:c_off + r.N * r.N].view(r.N, r.N)
+            c_off += r.N * r.N
+            trace.append(TraceRequest(r.rid, 0.0, "encode", r.N, r.length, C=Cm.data_ptr(), S=S.data_ptr(), K=r.N,
+                                      ld_s=ld))
+        else:
+            P = pkt_per[r.rid]
+            Cp = C_dev[c_off:c_off + P * r.N].view(P, r.N)
+            c_off += P * r.N
+            Bp = B_dev[b_off:b_off + P * ld].view(P, ld)
+            b_off += P * ld
+            gf.gf_encode(n, Cp, S[:, :r.length], Bp[:, :r.length])     # the sender's coded packets
+            lost = synth.unit_floats(synth.key(r.seed, 1), P) < 0.1
+            order = np.argsort(synth.words(synth.key(r.seed, 2), P))
+            pk = [(Cp[j].data_ptr(), Bp[j].data_ptr(), 1e-6 * t) for t, j in enumerate(order) if not lost[j]]
+            trace.append(TraceRequest(r.rid, 0.0, "decode", r.N, r.length, packets=pk))
+    torch.cuda.synchronize()
+    budget = int(args.serve_budget_gib * (1 << 30))
+
+    def run(rate):
+        for tr, g in zip(trace, unit_gaps):
+            tr.arrival = 0.0 if rate is None else float(g) / rate
+        srv = gf.Server(field=n, budget_bytes=budget)
+        t0 = time.perf_counter()
+        done = replay(srv, trace, timeout_s=300)
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        lat = [d["latency"] * 1e3 for d in done]
+        lat_e = [d["latency"] * 1e3 for d in done if d["kind"] == "encode"]
+        lat_d = [d["latency"] * 1e3 for d in done if d["kind"] == "decode"]
+        return {"offered_rps": None if rate is None else round(rate, 1), "completed": len(done),
+                "wall_s": round(wall, 3), "throughput_rps": round(len(done) / wall, 1),
+                "source_gbs": round(src_bytes / wall / 1e9, 3),
+                "p50_ms": round(percentile(lat, 50), 3), "p99_ms": round(percentile(lat, 99), 3),
+                "encode_p50_ms": round(percentile(lat_e, 50), 3), "encode_p99_ms": round(percentile(lat_e, 99), 3),
+                "decode_p50_ms": round(percentile(lat_d, 50), 3), "decode_p99_ms": round(percentile(lat_d, 99), 3),
+                "steps": st["steps"], "arena_peak_gib": round(st["arena_peak"] / (1 << 30), 3),
+                "packets_pushed": st["packets_pushed"], "packets_absorbed": st["packets_absorbed"]}
+
+    sat = run(None)
+    log("serve saturation: %s" % sat)
+    cap = sat["throughput_rps"]
+    loads = []
+    for frac in (0.5, 0.8):
+        res = run(cap * frac)
+        res["load_fraction"] = frac
+        loads.append(res)
+        log("serve at %.0f%%: %s" % (100 * frac, res))
+    return {"workload": "mixed_serving_gf256", "requests": count, "encode_fraction": round(len(enc) / count, 3),
+            "N": "U{8..256}", "packet_bytes": "log-U[64, 9000]", "loss": 0.1, "packet_gap_us": 1.0,
+            "budget_gib": args.serve_budget_gib, "saturation": sat, "loads": loads,
+            "p50_ms": loads[-1]["p50_ms"], "p99_ms": loads[-1]["p99_ms"]}
 
 
 if __name__ == "__main__":

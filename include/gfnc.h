@@ -177,6 +177,91 @@ void gf_plan_destroy(gf_plan *plan);
  * gf_encode per descriptor, on `stream`.  gens is a HOST array. */
 int gf_encode_each(int field, const gf_gen *gens, int count, const gf_tuning *tune, void *stream);
 
+/* ------------------------------------------------------------ serving
+ * Continuous batching of encode and decode requests on one device.
+ *
+ * Encode request: K coded packets Y = C * S of a generation (Eq. 1).
+ * Decode request: a generation of N packets of len bytes that is rebuilt
+ * from coded packets pushed one by one (coefficient vector + payload, in any
+ * order, with losses).  The server keeps, in device memory, the reduced row
+ * echelon form of the innovative coefficient vectors received so far; a
+ * packet whose vector reduces to zero is dropped (counted); at rank N the
+ * source packets are S = Csel^-1 * Bsel over the innovative packets.
+ *
+ * Memory: the server owns one device arena of budget_bytes.  A request is
+ * admitted (FIFO; the queue waits at its head) once a service slot and its
+ * working set are free: encode K * ld bytes for its output; decode about
+ * 3 N^2 + 2 N * ld bytes of state and output, ld = len rounded up to 16.
+ * Inputs (C, S, packets) stay in caller-owned device memory and must be
+ * ready (their producing stream synchronised) before they are submitted or
+ * pushed, and stay valid until the request completes.
+ *
+ * Time: `now` and `release` are caller clock readings in seconds; a packet is
+ * used once a step runs at or after its release time.  Completion time is
+ * the `now` of the call that observed it.
+ *
+ * Not thread-safe across calls on one server except where noted: calls are
+ * serialised by an internal mutex.  A completed request's output (device,
+ * `out` with row pitch `ld_out`) stays valid until gf_serve_release. */
+typedef struct gf_server gf_server;
+
+typedef struct {
+    int field;              /* GF_2 .. GF_256 */
+    int max_slots;          /* requests in service at once; 0 = 1024 */
+    int burst;              /* packets one decode request absorbs per step; 0 = 64 */
+    int dry_run;            /* 1: scheduling only, no device memory or kernels
+                               (decode packets are then assumed innovative) */
+    uint64_t budget_bytes;  /* device arena for request state and outputs */
+} gf_serve_config;
+
+typedef struct {
+    uint64_t id;
+    int kind;                /* 0 encode, 1 decode */
+    int status;              /* GF_OK */
+    int rank;                /* decode: N; encode: K */
+    int packets_seen;        /* decode: packets taken into the echelon state */
+    int packets_dropped;     /* decode: of those, not innovative */
+    const uint8_t *out;      /* device: encode K rows / decode N rows */
+    uint64_t ld_out;
+    double t_submit, t_admit, t_done;
+} gf_serve_done;
+
+typedef struct {
+    uint64_t steps, submitted, admitted, completed;
+    uint64_t queued, active, inflight_steps;
+    uint64_t arena_bytes, arena_used, arena_peak;
+    uint64_t packets_pushed, packets_absorbed;
+    uint64_t encode_tiles, absorb_items;
+} gf_serve_counters;
+
+int gf_serve_create(const gf_serve_config *cfg, gf_server **out);
+void gf_serve_destroy(gf_server *sv);
+/* C: device K x N; S: device N rows ld_s apart.  GF_ERANGE if the request
+ * could never fit the arena. */
+int gf_serve_submit_encode(gf_server *sv, uint64_t id, const uint8_t *C, int K, int N, const uint8_t *S,
+                           size_t ld_s, size_t len, double now);
+int gf_serve_submit_decode(gf_server *sv, uint64_t id, int N, size_t len, double now);
+/* coef: device, N bytes; payload: device, len bytes. */
+int gf_serve_push_packet(gf_server *sv, uint64_t id, const uint8_t *coef, const uint8_t *payload, double release);
+/* The same for n packets at once: coef[i], payload[i], release[i] (host arrays). */
+int gf_serve_push_packets(gf_server *sv, uint64_t id, int n, const uint8_t *const *coef,
+                          const uint8_t *const *payload, const double *release);
+/* Collect finished steps, admit, and enqueue one step.  Non-blocking unless
+ * the in-flight window is full.  Returns the steps in flight (>= 0). */
+int gf_serve_step(gf_server *sv, double now);
+/* Up to `max` completed requests, oldest first; returns how many. */
+int gf_serve_poll(gf_server *sv, gf_serve_done *out, int max);
+/* Copy a polled request's output rows (K for encode, N for decode; len
+ * bytes each) to dst (device, rows ld_dst apart).  The copy is enqueued on
+ * `stream` (the caller's), after the caller's earlier work on it. */
+int gf_serve_copy_out(gf_server *sv, uint64_t id, uint8_t *dst, size_t ld_dst, void *stream);
+/* Return a polled request's memory to the arena (deferred until no step in
+ * flight refers to it). */
+int gf_serve_release(gf_server *sv, uint64_t id);
+/* Wait for every step in flight and collect it. */
+int gf_serve_drain(gf_server *sv, double now);
+int gf_serve_stats(gf_server *sv, gf_serve_counters *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -335,3 +335,137 @@ def gf_encode_each(field: int, gens, count: Optional[int] = None, tune: Optional
         gens = (gf_gen * len(gens))(*[_gen_desc(*g) for g in gens])
     n = len(gens) if count is None else count
     _check(lib().gf_encode_each(field, gens, n, _tuning(tune), _stream(stream)), "gf_encode_each")
+
+
+# ------------------------------------------------------------------ serving
+
+class gf_serve_config(C.Structure):
+    _fields_ = [("field", C.c_int), ("max_slots", C.c_int), ("burst", C.c_int), ("dry_run", C.c_int),
+                ("budget_bytes", C.c_uint64)]
+
+
+class gf_serve_done(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("kind", C.c_int), ("status", C.c_int), ("rank", C.c_int),
+                ("packets_seen", C.c_int), ("packets_dropped", C.c_int), ("out", C.c_void_p),
+                ("ld_out", C.c_uint64), ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
+class gf_serve_counters(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("steps", "submitted", "admitted", "completed", "queued", "active",
+                                           "inflight_steps", "arena_bytes", "arena_used", "arena_peak",
+                                           "packets_pushed", "packets_absorbed", "encode_tiles", "absorb_items")]
+
+
+_SERVE_SIGS = {
+    "gf_serve_create": (C.c_int, [C.POINTER(gf_serve_config), C.POINTER(C.c_void_p)]),
+    "gf_serve_destroy": (None, [C.c_void_p]),
+    "gf_serve_submit_encode": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.c_int, C.c_void_p,
+                                         C.c_size_t, C.c_size_t, C.c_double]),
+    "gf_serve_submit_decode": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int, C.c_size_t, C.c_double]),
+    "gf_serve_push_packet": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.c_double]),
+    "gf_serve_push_packets": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gf_serve_step": (C.c_int, [C.c_void_p, C.c_double]),
+    "gf_serve_poll": (C.c_int, [C.c_void_p, C.POINTER(gf_serve_done), C.c_int]),
+    "gf_serve_release": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "gf_serve_copy_out": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "gf_serve_drain": (C.c_int, [C.c_void_p, C.c_double]),
+    "gf_serve_stats": (C.c_int, [C.c_void_p, C.POINTER(gf_serve_counters)]),
+}
+_SIGS.update(_SERVE_SIGS)
+EXPORTS = tuple(_SIGS)
+
+
+class Server:
+    """The serving runtime (``gf_serve_*``): continuous batching of encode and
+    progressive-decode requests in one device arena.
+
+    Inputs are device pointers (ints) or CUDA uint8 tensors; outputs are
+    device pointers into the server's arena, valid until ``release``.
+    ``dry_run=True`` runs the scheduler only (no GPU needed)."""
+
+    def __init__(self, field: int = GF_256, budget_bytes: int = 1 << 30, max_slots: int = 0, burst: int = 0,
+                 dry_run: bool = False):
+        if not dry_run:
+            _torch()
+        cfg = gf_serve_config(field, max_slots, burst, 1 if dry_run else 0, budget_bytes)
+        h = C.c_void_p()
+        _check(lib().gf_serve_create(C.byref(cfg), C.byref(h)), "gf_serve_create")
+        self._h = h
+        self.field = field
+        self._buf = (gf_serve_done * 1024)()
+
+    @staticmethod
+    def _ptr(x):
+        return x.data_ptr() if hasattr(x, "data_ptr") else int(x)
+
+    def submit_encode(self, rid: int, Cm, S, K: int, N: int, ld_s: int, length: int, now: float):
+        _check(lib().gf_serve_submit_encode(self._h, rid, self._ptr(Cm), K, N, self._ptr(S), ld_s, length, now),
+               "gf_serve_submit_encode")
+
+    def submit_decode(self, rid: int, N: int, length: int, now: float):
+        _check(lib().gf_serve_submit_decode(self._h, rid, N, length, now), "gf_serve_submit_decode")
+
+    def push_packet(self, rid: int, coef, payload, release: float):
+        _check(lib().gf_serve_push_packet(self._h, rid, self._ptr(coef), self._ptr(payload), release),
+               "gf_serve_push_packet")
+
+    def push_packets(self, rid: int, coefs, payloads, releases):
+        """Push many packets: sequences of device pointers and release times."""
+        import numpy as np
+        c = np.ascontiguousarray(np.asarray(coefs, dtype=np.uint64))
+        p = np.ascontiguousarray(np.asarray(payloads, dtype=np.uint64))
+        r = np.ascontiguousarray(np.asarray(releases, dtype=np.float64))
+        if not (c.size == p.size == r.size):
+            raise ValueError("length mismatch")
+        _check(lib().gf_serve_push_packets(self._h, rid, int(c.size), c.ctypes.data, p.ctypes.data, r.ctypes.data),
+               "gf_serve_push_packets")
+
+    def step(self, now: float) -> int:
+        rc = lib().gf_serve_step(self._h, now)
+        if rc < 0:
+            raise GFError(rc, "gf_serve_step")
+        return rc
+
+    def poll(self) -> List[dict]:
+        out = []
+        while True:
+            n = lib().gf_serve_poll(self._h, self._buf, len(self._buf))
+            if n < 0:
+                raise GFError(n, "gf_serve_poll")
+            for i in range(n):
+                d = self._buf[i]
+                out.append({"id": d.id, "kind": "encode" if d.kind == 0 else "decode", "status": d.status,
+                            "rank": d.rank, "packets_seen": d.packets_seen, "packets_dropped": d.packets_dropped,
+                            "out": d.out, "ld_out": d.ld_out, "t_submit": d.t_submit, "t_admit": d.t_admit,
+                            "t_done": d.t_done})
+            if n < len(self._buf):
+                return out
+
+    def release(self, rid: int):
+        _check(lib().gf_serve_release(self._h, rid), "gf_serve_release")
+
+    def copy_out(self, rid: int, dst, stream=None):
+        """Copy a completed request's output rows into the 2-D CUDA uint8 tensor `dst`
+        (enqueued on `stream`, default torch's current stream)."""
+        _dev_u8(dst, "dst")
+        _check(lib().gf_serve_copy_out(self._h, rid, dst.data_ptr(), max(dst.stride(0), dst.shape[1]),
+                                       _stream(stream)), "gf_serve_copy_out")
+
+    def drain(self, now: float):
+        _check(lib().gf_serve_drain(self._h, now), "gf_serve_drain")
+
+    def stats(self) -> dict:
+        c = gf_serve_counters()
+        _check(lib().gf_serve_stats(self._h, C.byref(c)), "gf_serve_stats")
+        return {n: getattr(c, n) for n, _ in gf_serve_counters._fields_}
+
+    def close(self):
+        if self._h:
+            lib().gf_serve_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

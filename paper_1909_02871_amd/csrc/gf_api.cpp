@@ -13,6 +13,21 @@
 
 using namespace gfnc;
 
+namespace gfnc {
+
+// Largest of 16, 8, 4 (else 1) that divides every row start: the widest
+// vector access the rows allow.
+uint32_t row_align(const void *S, uint64_t ld_s, const void *Y, uint64_t ld_y)
+{
+    const uint64_t bits = (uint64_t)(uintptr_t)S | (uint64_t)(uintptr_t)Y | ld_s | ld_y;
+    for (uint32_t a : {16u, 8u, 4u})
+        if (bits % a == 0)
+            return a;
+    return 1;
+}
+
+}  // namespace gfnc
+
 namespace {
 
 constexpr int kMaxDevices = 64;
@@ -80,17 +95,6 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb)
 
 size_t envelope(size_t rows, size_t ld, size_t len) { return rows == 0 || len == 0 ? 0 : (rows - 1) * ld + len; }
 
-// Largest of 16, 8, 4 (else 1) that divides every row start: the widest
-// vector access the rows allow.
-uint32_t row_align(const void *S, uint64_t ld_s, const void *Y, uint64_t ld_y)
-{
-    const uint64_t bits = (uint64_t)(uintptr_t)S | (uint64_t)(uintptr_t)Y | ld_s | ld_y;
-    for (uint32_t a : {16u, 8u, 4u})
-        if (bits % a == 0)
-            return a;
-    return 1;
-}
-
 struct Single {
     int D;
     int nsplit;
@@ -154,6 +158,19 @@ struct gf_plan {
     // host copy of the descriptors (for gf_encode_each-style diagnostics)
     std::vector<gf_gen> gens;
 };
+
+int gfnc::gfnc_field_tables(int field, const uint32_t **ptab, const uint8_t **inv)
+{
+    if (!valid_field(field))
+        return GF_EINVAL;
+    DevState *d;
+    int rc = current_state(&d);
+    if (rc)
+        return rc;
+    *ptab = field_ptab(d, field);
+    *inv = field_inv(d, field);
+    return GF_OK;
+}
 
 extern "C" {
 
@@ -378,6 +395,8 @@ static int upload(T **dst, const std::vector<T> &src)
     return GF_OK;
 }
 
+namespace gfnc {
+
 // Wave tiles of one generation: blocks of ENC_ROWS coded rows times payload
 // strips.  Full strips use 16 bytes per lane (1024 B per wave); the last
 // partial strip uses the narrowest lane width that covers it, so at most a
@@ -400,6 +419,24 @@ static void gen_tiles(uint32_t gi, const DevGen &x, int fixed_D, std::vector<std
     }
 }
 
+// Tiles of every generation, longest first (LPT order); ties keep a
+// generation's tiles together.
+void build_tiles(const DevGen *g, size_t n, int fixed_D, std::vector<DevTile> &out)
+{
+    std::vector<std::pair<DevTile, double>> tiles;
+    for (size_t i = 0; i < n; i++)
+        gen_tiles((uint32_t)i, g[i], fixed_D, tiles);
+    std::stable_sort(tiles.begin(), tiles.end(),
+                     [](const std::pair<DevTile, double> &a, const std::pair<DevTile, double> &b) {
+                         return a.second > b.second;
+                     });
+    out.resize(tiles.size());
+    for (size_t i = 0; i < tiles.size(); i++)
+        out[i] = tiles[i].first;
+}
+
+}  // namespace gfnc
+
 static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, const gf_tuning *tune)
 {
     DevState *d;
@@ -414,17 +451,8 @@ static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, co
     std::vector<DevGen> g = gens;
     for (DevGen &x : g)
         x.align = row_align(x.S, x.N > 1 ? x.ld_s : 0, x.Y, x.K > 1 ? x.ld_y : 0);
-    std::vector<std::pair<DevTile, double>> tiles;
-    for (size_t i = 0; i < g.size(); i++)
-        gen_tiles((uint32_t)i, g[i], p->fixed_D, tiles);
-    // longest tiles first (LPT order); ties keep a generation's tiles together
-    std::stable_sort(tiles.begin(), tiles.end(),
-                     [](const std::pair<DevTile, double> &a, const std::pair<DevTile, double> &b) {
-                         return a.second > b.second;
-                     });
-    std::vector<DevTile> tl(tiles.size());
-    for (size_t i = 0; i < tiles.size(); i++)
-        tl[i] = tiles[i].first;
+    std::vector<DevTile> tl;
+    build_tiles(g.data(), g.size(), p->fixed_D, tl);
     p->ntiles = (int)tl.size();
     if ((rc = upload(&p->d_gens, g)) || (rc = upload(&p->d_tiles, tl)))
         return rc;

@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace gfnc {
 
 // Field index 0..3 for n = 1, 2, 4, 8.
@@ -67,6 +69,30 @@ struct DevSys {
 #ifndef GF_ENC_WAVES_PER_SIMD
 #define GF_ENC_WAVES_PER_SIMD 2
 #endif
+// Device state of one generation being decoded progressively (serving).
+struct DevDecSlot {
+    uint8_t *R;      // reduced echelon rows of the innovative coefficient vectors, row stride rs
+    uint8_t *Csel;   // the innovative coefficient vectors as received, N x N (stride N)
+    uint8_t *Cinv;   // Csel^-1 once the rank reaches N, N x N
+    uint8_t *Bsel;   // payloads of the innovative packets, row i at Bsel + i*ld
+    int *meta;       // [0] rank, [1] step that completed it (-1 before), [2] packets seen,
+                     // [3] packets that were not innovative, [4 .. 4+N) pivot column of row i
+    uint64_t len, ld;
+    uint32_t N, rs;
+};
+
+struct DevAbsorb {
+    DevDecSlot s;
+    uint32_t pk0, npk;   // packets [pk0, pk0 + npk) of the step's packet list
+    int step;
+    int pad;
+};
+
+struct DevPacket {
+    const uint8_t *coef;      // N coefficients
+    const uint8_t *payload;   // len bytes
+};
+
 constexpr int ENC_ROWS = GF_ENC_ROWS;   // coded rows per wave tile
 inline uint64_t wave_strip(int D) { return 256ull * (uint64_t)D; }
 
@@ -82,5 +108,13 @@ hipError_t launch_encode_persistent(const DevGen *gens, const DevTile *tiles, in
 hipError_t launch_invert(const DevSys *sys, int count, const uint8_t *C, int N, uint8_t *Cinv, int *rank,
                          const uint32_t *ptab_field, const uint8_t *inv_field, hipStream_t s);
 int encode_blocks_per_cu();
+uint32_t row_align(const void *S, uint64_t ld_s, const void *Y, uint64_t ld_y);
+// Device tables of `field` on the current device (initialising it if needed).
+int gfnc_field_tables(int field, const uint32_t **ptab, const uint8_t **inv);
+void build_tiles(const DevGen *g, size_t n, int fixed_D, std::vector<DevTile> &out);
+hipError_t launch_absorb(const DevAbsorb *items, int n, const DevPacket *pkts, const uint32_t *ptab_field,
+                         const uint8_t *inv_field, hipStream_t s);
+hipError_t launch_meta_init(int *const *metas, int n, hipStream_t s);
+hipError_t launch_status_gather(int *const *metas, int n, int4 *out, hipStream_t s);
 
 }  // namespace gfnc

@@ -639,6 +639,158 @@ __global__ __launch_bounds__(256) void k_invert_batched(const DevSys *__restrict
     invert_body<MAXN>(s.C, (int)s.N, s.Cinv, s.rank, ptab4, invg);
 }
 
+// ------------------------------------------------------------------ serving
+
+// Progressive decoding of one generation (one workgroup per generation).
+// The innovative coefficient vectors received so far are kept in reduced row
+// echelon form R.  An arriving vector c is reduced against R in one pass:
+// since every row of R is zero in the other rows' pivot columns, subtracting
+// c[pivot(r)] * R[r] for all r at once clears every pivot column.  If nothing
+// is left the packet carried no new information.  Otherwise c is scaled to a
+// leading 1, its pivot column is cleared from the rows of R, and it is stored
+// with its raw coefficients and payload.  At rank N the raw coefficient
+// matrix is inverted (Gauss-Jordan, as in gf_invert) and the completion step
+// is recorded, which releases the payload product S = Csel^-1 * Bsel.
+__global__ __launch_bounds__(256) void k_absorb(const DevAbsorb *__restrict__ items,
+                                                const DevPacket *__restrict__ pkts, const uint4 *__restrict__ ptab4,
+                                                const uint8_t *__restrict__ invg)
+{
+    __shared__ uint32_t cw[64];
+    __shared__ uint32_t part[4][64];
+    __shared__ uint4 T[256][2];
+    __shared__ uint8_t IV[256];
+    __shared__ uint8_t fcol[256];
+    __shared__ int pivc[256];
+    __shared__ int cand[4];
+    __shared__ int inv_rank;
+    const DevAbsorb it = items[blockIdx.x];
+    const DevDecSlot &s = it.s;
+    const int N = (int)s.N, NW = (N + 3) >> 2;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    int rank = s.meta[0];
+    if (rank >= N || N > 256)
+        return;
+    for (int i = tid; i < 512; i += 256)
+        T[i >> 1][i & 1] = ptab4[i];
+    IV[tid] = invg[tid];
+    for (int i = tid; i < rank; i += 256)
+        pivc[i] = s.meta[4 + i];
+    int seen = 0, dropped = 0;
+    __syncthreads();
+
+    for (uint32_t q = 0; q < it.npk && rank < N; q++) {
+        const DevPacket pk = pkts[it.pk0 + q];
+        if (tid < NW) {
+            uint32_t v = 0;
+            for (int b = 0; b < 4; b++)
+                if (4 * tid + b < N)
+                    v |= (uint32_t)pk.coef[4 * tid + b] << (8 * b);
+            cw[tid] = v;
+        }
+        __syncthreads();
+        if (lane < NW) {
+            uint32_t acc = 0;
+            for (int r = wave; r < rank; r += 4) {
+                const int pc = pivc[r];
+                const uint32_t f = (cw[pc >> 2] >> (8 * (pc & 3))) & 0xFFu;
+                if (f)
+                    acc ^= prod4(T[f][0], T[f][1].x,
+                                 reinterpret_cast<const uint32_t *>(s.R + (uint64_t)r * s.rs)[lane]);
+            }
+            part[wave][lane] = acc;
+        }
+        __syncthreads();
+        if (tid < NW)
+            cw[tid] ^= part[0][tid] ^ part[1][tid] ^ part[2][tid] ^ part[3][tid];
+        __syncthreads();
+        const bool nz = tid < N && ((cw[tid >> 2] >> (8 * (tid & 3))) & 0xFFu) != 0;
+        const uint64_t m = __ballot(nz);
+        if (lane == 0)
+            cand[wave] = m ? wave * 64 + __builtin_ctzll(m) : (1 << 30);
+        __syncthreads();
+        const int lead = min(min(cand[0], cand[1]), min(cand[2], cand[3]));
+        seen++;
+        if (lead >= N) {
+            dropped++;
+            __syncthreads();
+            continue;
+        }
+        if (tid < NW) {   // wave 0 reads the leading entry before any lane rewrites it
+            const uint32_t lv = (cw[lead >> 2] >> (8 * (lead & 3))) & 0xFFu;
+            const uint32_t iv = IV[lv];
+            cw[tid] = prod4(T[iv][0], T[iv][1].x, cw[tid]);
+        }
+        for (int r = tid; r < rank; r += 256)
+            fcol[r] = s.R[(uint64_t)r * s.rs + lead];
+        __syncthreads();
+        for (int e = tid; e < rank * NW; e += 256) {
+            const int r = e / NW, l = e - r * NW;
+            const uint32_t f = fcol[r];
+            if (f) {
+                uint32_t *rp = reinterpret_cast<uint32_t *>(s.R + (uint64_t)r * s.rs) + l;
+                *rp ^= prod4(T[f][0], T[f][1].x, cw[l]);
+            }
+        }
+        if (tid < NW)
+            reinterpret_cast<uint32_t *>(s.R + (uint64_t)rank * s.rs)[tid] = cw[tid];
+        for (int b = tid; b < N; b += 256)
+            s.Csel[(uint64_t)rank * N + b] = pk.coef[b];
+        uint8_t *dst = s.Bsel + (uint64_t)rank * s.ld;
+        if (((((uintptr_t)dst) | ((uintptr_t)pk.payload)) & 3u) == 0) {
+            const uint64_t words = s.len >> 2;
+            for (uint64_t w = tid; w < words; w += 256)
+                reinterpret_cast<uint32_t *>(dst)[w] = reinterpret_cast<const uint32_t *>(pk.payload)[w];
+            for (uint64_t b = (words << 2) + tid; b < s.len; b += 256)
+                dst[b] = pk.payload[b];
+        } else {
+            for (uint64_t b = tid; b < s.len; b += 256)
+                dst[b] = pk.payload[b];
+        }
+        if (tid == 0)
+            pivc[rank] = lead;
+        rank++;
+        __syncthreads();
+    }
+    for (int i = tid; i < rank; i += 256)
+        s.meta[4 + i] = pivc[i];
+    if (tid == 0) {
+        s.meta[0] = rank;
+        s.meta[2] += seen;
+        s.meta[3] += dropped;
+    }
+    if (rank == N) {
+        __syncthreads();
+        invert_body<256>(s.Csel, N, s.Cinv, &inv_rank, ptab4, invg);
+        __syncthreads();
+        if (tid == 0) {
+            __threadfence();
+            s.meta[1] = it.step;
+        }
+    }
+}
+
+__global__ void k_meta_init(int *const *__restrict__ metas, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        int *m = metas[i];
+        m[0] = 0;
+        m[1] = -1;
+        m[2] = 0;
+        m[3] = 0;
+    }
+}
+
+__global__ void k_status_gather(int *const *__restrict__ metas, int n, int4 *__restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const int *m = metas[i];
+        out[i] = make_int4(m[0], m[1], m[2], m[3]);
+    }
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------- launchers
@@ -766,6 +918,32 @@ hipError_t launch_invert(const DevSys *sys, int count, const uint8_t *C, int N, 
     hipLaunchKernelGGL(k_invert_batched<64>, dim3(count), dim3(256), 0, s, sys, pt, inv_field);
     hipLaunchKernelGGL(k_invert_batched<128>, dim3(count), dim3(256), 0, s, sys, pt, inv_field);
     hipLaunchKernelGGL(k_invert_batched<256>, dim3(count), dim3(256), 0, s, sys, pt, inv_field);
+    return hipGetLastError();
+}
+
+hipError_t launch_absorb(const DevAbsorb *items, int n, const DevPacket *pkts, const uint32_t *ptab_field,
+                         const uint8_t *inv_field, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_absorb, dim3(n), dim3(256), 0, s, items, pkts, reinterpret_cast<const uint4 *>(ptab_field),
+                       inv_field);
+    return hipGetLastError();
+}
+
+hipError_t launch_meta_init(int *const *metas, int n, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_meta_init, dim3((n + 255) / 256), dim3(256), 0, s, metas, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_status_gather(int *const *metas, int n, int4 *out, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_status_gather, dim3((n + 255) / 256), dim3(256), 0, s, metas, n, out);
     return hipGetLastError();
 }
 
