@@ -40,6 +40,20 @@ VALU_LANE_OPS = 256 * 64 * 2.4e9
 TABLE_OPS_PER_MADD = 4.5 / 4.0
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the batched encode kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# (calibrated against a 1 GiB copy: fetch x 2.000, write x 1.000), valid only for the kernel
+# source they were taken with (sha256 of csrc/gf_kernels.hip); otherwise reported as null.
+MEASURED_TRAFFIC = {
+    "14d2e6f58585212c738f649aa0729171021f4fdf89aad0996bab7777c4207171": 8126270 * 1024 * 2.0 + 2409897 * 1024,
+}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    path = os.path.join(ROOT, "paper_1909_02871_amd", "csrc", "gf_kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -59,6 +73,8 @@ def main():
     ap.add_argument("--bytes-per-lane", type=int, default=0)
     ap.add_argument("--serve-requests", type=int, default=4000, help="requests per serving run (0: skip)")
     ap.add_argument("--serve-budget-gib", type=float, default=4.0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a device-to-device copy of this many MiB (to calibrate HBM counters) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -73,6 +89,15 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_calibration_mib:
+        nb = args.copy_calibration_mib << 20
+        src = torch.empty(nb, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nb}))
+        return
     gf.gf_init()
     n = args.field
 
@@ -152,8 +177,10 @@ def main():
     peak = VALU_LANE_OPS / TABLE_OPS_PER_MADD / 1e12
     hbm_bytes = b.source_bytes + int((b.Ks * b.Ls).sum()) + int((b.Ks * b.Ns).sum())
     hbm_roof_src = HBM_PEAK_GBS * b.source_bytes / hbm_bytes
+    traffic = MEASURED_TRAFFIC.get(kernel_source_hash()) if n == 8 and args.count == 10000 else None
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
-                "unit": "T byte-madd/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "unit": "T byte-madd/s", "frac": round(achieved / peak, 4),
+                "traffic": None if traffic is None else int(traffic),
                 "kernel": "k_encode_waves", "kernel_ms": round(kern_ms, 4),
                 "algorithmic_bytes": hbm_bytes}
 
