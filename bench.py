@@ -39,12 +39,13 @@ VALU_LANE_OPS = 256 * 64 * 2.4e9
 # The table form spends 3 byte-selects + 1.5 three-input XORs per dword of 4 byte-madds.
 TABLE_OPS_PER_MADD = 4.5 / 4.0
 HBM_PEAK_GBS = 8000.0
+MFMA_FP4_TFLOPS = 10100.0
 
 # HBM bytes per launch of the batched encode kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE
 # (calibrated against a 1 GiB copy: fetch x 2.000, write x 1.000), valid only for the kernel
 # source they were taken with (sha256 of csrc/gf_kernels.hip); otherwise reported as null.
 MEASURED_TRAFFIC = {
-    "14d2e6f58585212c738f649aa0729171021f4fdf89aad0996bab7777c4207171": 8126270 * 1024 * 2.0 + 2409897 * 1024,
+    ("14d2e6f58585212c738f649aa0729171021f4fdf89aad0996bab7777c4207171", 1): 8126270 * 1024 * 2.0 + 2409897 * 1024,
 }
 
 
@@ -71,6 +72,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--bytes-per-lane", type=int, default=0)
+    ap.add_argument("--form", type=int, default=0, help="0 autotune, 1 table, 2 bit-matrix MFMA")
     ap.add_argument("--serve-requests", type=int, default=4000, help="requests per serving run (0: skip)")
     ap.add_argument("--serve-budget-gib", type=float, default=4.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -117,15 +119,34 @@ def main():
     for i in range(args.count):
         descs[i] = gf.gf_gen(c0 + int(b.c_off[i]), s0 + int(b.s_off[i]), y0 + int(b.y_off[i]), int(b.Ks[i]),
                              int(b.Ns[i]), int(b.Ls[i]), int(b.lds[i]), int(b.lds[i]))
-    tune = None
+    tune = {"form": args.form}
     if args.bytes_per_lane:
-        tune = {"bytes_per_lane": args.bytes_per_lane}
+        tune["bytes_per_lane"] = args.bytes_per_lane
     t0 = time.time()
     plan = gf.gf_plan_encode_desc(n, descs, args.count, tune=tune, keep=(S_dev, C_dev, Y_dev))
     tuning = plan.tuning()
     log("plan built in %.2f s: %s" % (time.time() - t0, tuning))
-
     stream = torch.cuda.current_stream()
+
+    # each kernel form on its own, graph-replayed (the autotuned plan keeps the faster)
+    forms = {}
+    for f in (1, 2):
+        pf = gf.gf_plan_encode_desc(n, descs, args.count, tune={"form": f}, keep=(S_dev, C_dev, Y_dev))
+        for _ in range(2):
+            gf.gf_plan_launch_graph(pf)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(5):
+            gf.gf_plan_launch_graph(pf)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        fms = e0.elapsed_time(e1) / 5
+        forms["table" if f == 1 else "bitmatrix_mfma"] = {"ms": round(fms, 4),
+                                                          "gbs": round(b.source_bytes / (fms * 1e-3) / 1e9, 3)}
+        pf.destroy()
+    log("forms: %s" % forms)
+
     launch = (lambda: gf.gf_encode_batched(plan)) if args.no_graph else (lambda: gf.gf_plan_launch_graph(plan))
 
     # ------------------------------------------------------------ batched
@@ -173,16 +194,23 @@ def main():
 
     # ------------------------------------------------------------ roofline
     madds = b.byte_madds
-    achieved = madds / (kern_ms * 1e-3) / 1e12
-    peak = VALU_LANE_OPS / TABLE_OPS_PER_MADD / 1e12
     hbm_bytes = b.source_bytes + int((b.Ks * b.Ls).sum()) + int((b.Ks * b.Ns).sum())
     hbm_roof_src = HBM_PEAK_GBS * b.source_bytes / hbm_bytes
-    traffic = MEASURED_TRAFFIC.get(kernel_source_hash()) if n == 8 and args.count == 10000 else None
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
-                "unit": "T byte-madd/s", "frac": round(achieved / peak, 4),
-                "traffic": None if traffic is None else int(traffic),
-                "kernel": "k_encode_waves", "kernel_ms": round(kern_ms, 4),
-                "algorithmic_bytes": hbm_bytes}
+    traffic = MEASURED_TRAFFIC.get((kernel_source_hash(), tuning["form"])) if n == 8 and args.count == 10000 \
+        else None
+    if tuning["form"] == 2:
+        # the bit-matrix product: 8K x 8N x L bit multiply-adds = 64 per byte-madd, 2 flops each,
+        # against the dense FP4 matrix-core peak
+        achieved = 128.0 * madds / (kern_ms * 1e-3) / 1e12
+        roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": MFMA_FP4_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / MFMA_FP4_TFLOPS, 4), "kernel": "k_encode_mfma"}
+    else:
+        achieved = madds / (kern_ms * 1e-3) / 1e12
+        peak = VALU_LANE_OPS / TABLE_OPS_PER_MADD / 1e12
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
+                    "unit": "T byte-madd/s", "frac": round(achieved / peak, 4), "kernel": "k_encode_waves"}
+    roofline.update({"traffic": None if traffic is None else int(traffic), "kernel_ms": round(kern_ms, 4),
+                     "algorithmic_bytes": hbm_bytes, "byte_madds_per_s": round(madds / (kern_ms * 1e-3), 1)})
 
     # ------------------------------------------------------------ CPU oracle
     cpu = None
@@ -236,7 +264,7 @@ def main():
         "plain": plain,
         "speedup_vs_plain": round(value / plain["value"], 3) if plain else None,
         "hbm_roofline_gbs": round(hbm_roof_src, 1), "hbm_roofline_frac": round(value / hbm_roof_src, 4),
-        "roofline": roofline, "cpu_baseline": cpu, "tuning": tuning, "serve": serve,
+        "roofline": roofline, "forms": forms, "cpu_baseline": cpu, "tuning": tuning, "serve": serve,
     }
     print(json.dumps(out), flush=True)
 

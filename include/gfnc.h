@@ -145,9 +145,14 @@ typedef struct {
     uint64_t len, ld_b, ld_s;
 } gf_sys;
 
-/* Kernel schedule knobs.  Zero fields mean "chosen by the library". */
+/* Kernel schedule knobs.  Zero fields mean "chosen by the library".
+ * form 1: byte-select table lookups on the vector ALUs.
+ * form 2: the product as a GF(2) bit-matrix multiply on the matrix cores.
+ * form 0 on an encode plan: both forms are timed on the plan's own batch
+ * while the plan is created (which writes the plan's outputs) and the faster
+ * is kept; on a decode plan form 0 means form 1. */
 typedef struct {
-    int form;           /* 0 auto, 1 table (VALU byte-select) */
+    int form;           /* 0 auto, 1 table, 2 bit-matrix */
     int bytes_per_lane; /* 0 = per tile; else 4, 8 or 16 payload bytes per lane everywhere */
     int grid_blocks;    /* persistent workgroups; 0 = as many as fit on the GPU at once */
     int reserved;       /* must be 0 */

@@ -34,7 +34,7 @@ constexpr int kMaxDevices = 64;
 
 struct DevState {
     bool ready = false;
-    DevTables t{nullptr, nullptr};
+    DevTables t{nullptr, nullptr, nullptr};
     int cus = 0;
 };
 
@@ -50,17 +50,20 @@ int current_state(DevState **out)
     DevState &d = g_dev[dev];
     if (!d.ready) {
         const HostTables &h = host_tables();
-        void *pt = nullptr, *iv = nullptr;
+        void *pt = nullptr, *iv = nullptr, *rw = nullptr;
         if (hipMalloc(&pt, sizeof h.ptab) != hipSuccess)
             return GF_EDEVICE;
-        if (hipMalloc(&iv, sizeof h.inv) != hipSuccess) {
+        if (hipMalloc(&iv, sizeof h.inv) != hipSuccess || hipMalloc(&rw, sizeof h.rows) != hipSuccess) {
             (void)hipFree(pt);
+            (void)hipFree(iv);
             return GF_EDEVICE;
         }
         if (hipMemcpy(pt, h.ptab, sizeof h.ptab, hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(iv, h.inv, sizeof h.inv, hipMemcpyHostToDevice) != hipSuccess) {
+            hipMemcpy(iv, h.inv, sizeof h.inv, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(rw, h.rows, sizeof h.rows, hipMemcpyHostToDevice) != hipSuccess) {
             (void)hipFree(pt);
             (void)hipFree(iv);
+            (void)hipFree(rw);
             return GF_EDEVICE;
         }
         int cus = 0;
@@ -68,6 +71,7 @@ int current_state(DevState **out)
             cus = 256;
         d.t.ptab = static_cast<uint32_t *>(pt);
         d.t.inv = static_cast<uint8_t *>(iv);
+        d.t.rows = static_cast<uint8_t *>(rw);
         d.cus = cus;
         d.ready = true;
     }
@@ -82,6 +86,7 @@ const uint32_t *field_ptab(const DevState *d, int field)
     return d->t.ptab + (size_t)field_index(field) * 256 * 8;
 }
 const uint8_t *field_inv(const DevState *d, int field) { return d->t.inv + (size_t)field_index(field) * 256; }
+const uint8_t *field_rows(const DevState *d, int field) { return d->t.rows + (size_t)field_index(field) * 256 * 8; }
 
 int dev_err(hipError_t e) { return e == hipSuccess ? GF_OK : GF_EDEVICE; }
 
@@ -138,6 +143,8 @@ struct gf_plan {
     int dev = 0;
     int count = 0;
     int fixed_D = 0;   // 0: lane width chosen per tile
+    int form = 1;      // 1 table (VALU byte-select), 2 bit-matrix on the matrix cores
+    double tune_ms[3] = {0, 0, 0};   // autotuning trial times per form (0: not timed)
     int grid = 0;
     int ntiles = 0;
     DevGen *d_gens = nullptr;
@@ -170,6 +177,14 @@ int gfnc::gfnc_field_tables(int field, const uint32_t **ptab, const uint8_t **in
     *ptab = field_ptab(d, field);
     *inv = field_inv(d, field);
     return GF_OK;
+}
+
+const uint8_t *gfnc::gfnc_field_rows(int field)
+{
+    DevState *d;
+    if (!valid_field(field) || current_state(&d))
+        return nullptr;
+    return field_rows(d, field);
 }
 
 extern "C" {
@@ -437,7 +452,85 @@ void build_tiles(const DevGen *g, size_t n, int fixed_D, std::vector<DevTile> &o
 
 }  // namespace gfnc
 
-static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, const gf_tuning *tune)
+// Workgroup tiles of the bit-matrix form: MF_ROWS coded rows over the whole
+// packet length, longest first.
+static void build_tiles_mfma(const DevGen *g, size_t n, std::vector<DevTile> &out)
+{
+    std::vector<std::pair<DevTile, double>> tiles;
+    for (size_t i = 0; i < n; i++) {
+        const DevGen &x = g[i];
+        if (x.K == 0 || x.len == 0)
+            continue;
+        const double strips = (double)((x.len + MF_STRIP - 1) / MF_STRIP);
+        for (uint32_t k0 = 0; k0 < x.K; k0 += MF_ROWS)
+            tiles.push_back({DevTile{(uint32_t)i, (uint16_t)k0, 0, 0}, (double)((x.N + 7) / 8) * (strips + 1.0)});
+    }
+    std::stable_sort(tiles.begin(), tiles.end(),
+                     [](const std::pair<DevTile, double> &a, const std::pair<DevTile, double> &b) {
+                         return a.second > b.second;
+                     });
+    out.resize(tiles.size());
+    for (size_t i = 0; i < tiles.size(); i++)
+        out[i] = tiles[i].first;
+}
+
+static int launch_schedule(gf_plan *p, DevState *d, hipStream_t s)
+{
+    const int f = p->field;
+    hipError_t e;
+    if (p->form == 2)
+        e = launch_encode_mfma(p->d_gens, p->d_tiles, p->ntiles, p->d_ctr, p->grid, field_rows(d, f), s);
+    else
+        e = launch_encode_persistent(p->d_gens, p->d_tiles, p->ntiles, p->d_ctr, p->grid, field_ptab(d, f), s);
+    return dev_err(e);
+}
+
+// Tile list, grid and device copies for one form.
+static int make_schedule(gf_plan *p, DevState *d, const std::vector<DevGen> &g, int form, const gf_tuning *tune)
+{
+    std::vector<DevTile> tl;
+    if (form == 2)
+        build_tiles_mfma(g.data(), g.size(), tl);
+    else
+        build_tiles(g.data(), g.size(), p->fixed_D, tl);
+    (void)hipFree(p->d_tiles);
+    p->d_tiles = nullptr;
+    p->form = form;
+    p->ntiles = (int)tl.size();
+    int rc = upload(&p->d_tiles, tl);
+    if (rc)
+        return rc;
+    int grid = d->cus * (form == 2 ? encode_mfma_blocks_per_cu() : encode_blocks_per_cu());
+    if (tune && tune->grid_blocks > 0)
+        grid = tune->grid_blocks;
+    const int per_block = form == 2 ? 1 : 4;
+    p->grid = std::max(1, std::min(grid, std::max(1, (p->ntiles + per_block - 1) / per_block)));
+    return GF_OK;
+}
+
+// Milliseconds of one launch of the current schedule (after one untimed launch).
+static double time_schedule(gf_plan *p, DevState *d)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    double ms = -1;
+    if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
+        launch_schedule(p, d, p->cap) == GF_OK && hipEventRecord(e0, p->cap) == hipSuccess &&
+        launch_schedule(p, d, p->cap) == GF_OK && hipEventRecord(e1, p->cap) == hipSuccess &&
+        hipEventSynchronize(e1) == hipSuccess) {
+        float f = 0;
+        if (hipEventElapsedTime(&f, e0, e1) == hipSuccess)
+            ms = f;
+    }
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    return ms;
+}
+
+// form: 1 table, 2 bit-matrix; 0 = time both on the plan's own data and keep
+// the faster (only when `may_run` allows launching before the caller asks).
+static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, const gf_tuning *tune, bool may_run)
 {
     DevState *d;
     int rc = current_state(&d);
@@ -448,27 +541,42 @@ static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, co
             return GF_EINVAL;
         p->fixed_D = tune->bytes_per_lane / 4;
     }
+    int form = tune ? tune->form : 0;
+    if (form < 0 || form > 2)
+        return GF_EINVAL;
     std::vector<DevGen> g = gens;
     for (DevGen &x : g)
         x.align = row_align(x.S, x.N > 1 ? x.ld_s : 0, x.Y, x.K > 1 ? x.ld_y : 0);
-    std::vector<DevTile> tl;
-    build_tiles(g.data(), g.size(), p->fixed_D, tl);
-    p->ntiles = (int)tl.size();
-    if ((rc = upload(&p->d_gens, g)) || (rc = upload(&p->d_tiles, tl)))
+    if ((rc = upload(&p->d_gens, g)))
         return rc;
     if (hipMalloc(reinterpret_cast<void **>(&p->d_ctr), 2 * sizeof(unsigned)) != hipSuccess)
         return GF_ENOMEM;
     if (hipMemset(p->d_ctr, 0, 2 * sizeof(unsigned)) != hipSuccess)
         return GF_EDEVICE;
-    int grid = d->cus * encode_blocks_per_cu();
-    if (tune && tune->grid_blocks > 0)
-        grid = tune->grid_blocks;
-    p->grid = std::max(1, std::min(grid, std::max(1, (p->ntiles + 3) / 4)));
     if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
         return GF_EDEVICE;
     if (hipDeviceSynchronize() != hipSuccess)
         return GF_EDEVICE;
-    return GF_OK;
+    if (form == 0 && !may_run)
+        form = 1;
+    if (form != 0)
+        return make_schedule(p, d, g, form, tune);
+    // autotune: both forms on the real batch
+    double best = -1;
+    int best_form = 1;
+    for (int f : {1, 2}) {
+        if ((rc = make_schedule(p, d, g, f, tune)))
+            return rc;
+        const double ms = time_schedule(p, d);
+        p->tune_ms[f] = ms;
+        if (ms > 0 && (best < 0 || ms < best)) {
+            best = ms;
+            best_form = f;
+        }
+    }
+    if (best_form != p->form && (rc = make_schedule(p, d, g, best_form, tune)))
+        return rc;
+    return hipDeviceSynchronize() == hipSuccess ? GF_OK : GF_EDEVICE;
 }
 
 extern "C" {
@@ -496,7 +604,7 @@ int gf_plan_encode(int field, const gf_gen *gens, int count, const gf_tuning *tu
     p->count = count;
     (void)hipGetDevice(&p->dev);
     p->gens.assign(gens, gens + count);
-    int rc = build_encode_schedule(p, g, tune);
+    int rc = build_encode_schedule(p, g, tune, true);
     if (rc) {
         plan_free_device(p);
         delete p;
@@ -564,7 +672,7 @@ int gf_plan_decode(int field, const gf_sys *sys, int count, const gf_tuning *tun
         g[i] = DevGen{p->d_cinv + off[i], s.B, s.S, s.len, s.ld_b, s.ld_s, s.N, s.N, p->d_rank + i, (int)s.N, 1};
     }
     if (!rc)
-        rc = build_encode_schedule(p, g, tune);
+        rc = build_encode_schedule(p, g, tune, false);
     if (rc) {
         plan_free_device(p);
         delete p;
@@ -591,9 +699,8 @@ static int run_plan(gf_plan *p, int *d_rank, hipStream_t s)
                 return GF_EDEVICE;
         }
     }
-    hipError_t e = launch_encode_persistent(p->d_gens, p->d_tiles, p->ntiles, p->d_ctr, p->grid, field_ptab(d, f), s);
-    if (e != hipSuccess)
-        return GF_EDEVICE;
+    if ((rc = launch_schedule(p, d, s)))
+        return rc;
     if (p->kind == 1 && d_rank && p->count > 0)
         if (hipMemcpyAsync(d_rank, p->d_rank, sizeof(int) * p->count, hipMemcpyDeviceToDevice, s) != hipSuccess)
             return GF_EDEVICE;
@@ -650,7 +757,7 @@ int gf_plan_tuning(const gf_plan *p, gf_tuning *out)
 {
     if (!p || !out)
         return GF_EINVAL;
-    out->form = 1;
+    out->form = p->form;
     out->bytes_per_lane = 4 * p->fixed_D;
     out->grid_blocks = p->grid;
     out->reserved = 0;

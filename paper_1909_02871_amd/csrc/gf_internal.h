@@ -21,9 +21,12 @@ inline int field_index(int n) { return n == 1 ? 0 : n == 2 ? 1 : n == 4 ? 2 : n 
 //     (c * b is applied word by word, so every field shares one kernel; rows
 //      with c >= q are all zero.)
 //   inv[f][a]: multiplicative inverse of a (0 for a = 0 or a >= q).
+//   rows[f][c][i]: row i of the 8 x 8 bit matrix of "multiply a byte by c":
+//     bit j is bit i of c * (1 << j)  (the product is GF(2)-linear in the byte).
 struct DevTables {
     uint32_t *ptab;   // [4][256][8]
     uint8_t *inv;     // [4][256]
+    uint8_t *rows;    // [4][256][8]
 };
 
 // Host copies, built once by build_tables().
@@ -31,6 +34,7 @@ struct HostTables {
     uint32_t ptab[4][256][8];
     uint8_t inv[4][256];
     uint8_t mul[4][256][256];   // element products (row c, column a), a, c < q
+    uint8_t rows[4][256][8];    // bit-matrix rows, as in DevTables
 };
 const HostTables &host_tables();
 
@@ -93,6 +97,12 @@ struct DevPacket {
     const uint8_t *payload;   // len bytes
 };
 
+#ifndef GF_MF_PREFETCH
+#define GF_MF_PREFETCH 3
+#endif
+#ifndef GF_MF_WAVES_PER_SIMD
+#define GF_MF_WAVES_PER_SIMD 2
+#endif
 constexpr int ENC_ROWS = GF_ENC_ROWS;   // coded rows per wave tile
 inline uint64_t wave_strip(int D) { return 256ull * (uint64_t)D; }
 
@@ -105,12 +115,20 @@ hipError_t launch_encode(int D, int nsplit, const uint8_t *C, int K, int N, cons
                          int need, bool aligned, hipStream_t s);
 hipError_t launch_encode_persistent(const DevGen *gens, const DevTile *tiles, int ntiles, unsigned *counters,
                                     int grid, const uint32_t *ptab_field, hipStream_t s);
+// Bit-matrix form on the matrix cores: workgroup tiles of MF_ROWS coded rows x
+// MF_STRIP payload bytes (DevTile.D unused).
+constexpr int MF_ROWS = 16;
+constexpr int MF_STRIP = 256;
+hipError_t launch_encode_mfma(const DevGen *gens, const DevTile *tiles, int ntiles, unsigned *counters, int grid,
+                              const uint8_t *rows_field, hipStream_t s);
+int encode_mfma_blocks_per_cu();
 hipError_t launch_invert(const DevSys *sys, int count, const uint8_t *C, int N, uint8_t *Cinv, int *rank,
                          const uint32_t *ptab_field, const uint8_t *inv_field, hipStream_t s);
 int encode_blocks_per_cu();
 uint32_t row_align(const void *S, uint64_t ld_s, const void *Y, uint64_t ld_y);
 // Device tables of `field` on the current device (initialising it if needed).
 int gfnc_field_tables(int field, const uint32_t **ptab, const uint8_t **inv);
+const uint8_t *gfnc_field_rows(int field);
 void build_tiles(const DevGen *g, size_t n, int fixed_D, std::vector<DevTile> &out);
 hipError_t launch_absorb(const DevAbsorb *items, int n, const DevPacket *pkts, const uint32_t *ptab_field,
                          const uint8_t *inv_field, hipStream_t s);

@@ -466,6 +466,255 @@ __global__ __launch_bounds__(256, GF_ENC_WAVES_PER_SIMD) void k_encode_waves(con
     }
 }
 
+// ------------------------------------------------------- encode, bit-matrix form
+//
+// Multiplication by a constant c is a GF(2)-linear map of a byte's 8 bits, an
+// 8 x 8 bit matrix M_c, so a generation's encode is one GF(2) matrix product:
+// (8K x 8N coefficient bits) x (8N x L source bits), each output bit the parity
+// of a dot product of 0/1 values.  The matrix cores compute those dot products
+// exactly: operands are FP4 (E2M1) values 0 or 1.0, accumulation is FP32
+// (counts <= 8N <= 2048 are exact), and the parity is the count's lowest bit.
+//
+// One MFMA 32x32x64: rows = 32 output bits (4 coded packets x 8 bits), columns
+// = 32 payload bytes, reduction = 64 input bits (8 source packets x 8 bits).
+// A workgroup tile is 16 coded packets (4 row tiles) x 256 payload bytes; wave
+// w covers 64 bytes (2 column tiles) and builds row tile w's operand for the
+// whole workgroup in LDS each step.
+
+typedef int gf_v8i __attribute__((ext_vector_type(8)));
+typedef float gf_v16f __attribute__((ext_vector_type(16)));
+
+// Bits m and m + 4 of every byte of x as FP4 nibbles (0 or 1.0 = 0b0010): the
+// low nibble of byte s holds bit m, the high nibble bit m + 4.  Both operands
+// of an MFMA use this packing, so their reduction indices line up.
+__device__ __forceinline__ uint32_t fp4_bits(uint32_t x, int m)
+{
+    const uint32_t t = m == 0 ? (x << 1) : (x >> (m - 1));
+    return t & 0x22222222u;
+}
+
+__device__ __forceinline__ gf_v8i fp4_operand(uint32_t x)
+{
+    gf_v8i v;
+    v[0] = (int)fp4_bits(x, 0);
+    v[1] = (int)fp4_bits(x, 1);
+    v[2] = (int)fp4_bits(x, 2);
+    v[3] = (int)fp4_bits(x, 3);
+    v[4] = v[5] = v[6] = v[7] = 0;
+    return v;
+}
+
+// Bytes col and col + 1 of a row of len >= 1 bytes (zero past the end),
+// without branches: the addresses are clamped into the row and the bytes
+// outside it masked off, so a wave issues its loads back to back.  EVEN: the
+// row start is 2-byte aligned and len >= 2 (one 16-bit load).
+template <bool EVEN>
+__device__ __forceinline__ uint32_t load_pair(const uint8_t *row, uint64_t col, uint64_t len)
+{
+    uint32_t v;
+    if constexpr (EVEN) {
+        const uint64_t c = col < len - 2 ? col : len - 2;
+        v = *reinterpret_cast<const __attribute__((address_space(1))) uint16_t *>(
+            reinterpret_cast<uintptr_t>(row + c));
+        v = col + 1 == len ? v >> 8 : v;
+    } else {
+        const uint64_t c0 = col < len - 1 ? col : len - 1;
+        const uint64_t c1 = col + 1 < len - 1 ? col + 1 : len - 1;
+        const auto *gr = reinterpret_cast<const __attribute__((address_space(1))) uint8_t *>(
+            reinterpret_cast<uintptr_t>(row));
+        v = (uint32_t)gr[c0] | ((uint32_t)gr[c1] << 8);
+    }
+    v = col + 1 < len ? v : (v & 0xFFu);
+    return col < len ? v : 0u;
+}
+
+// Row r of a 32-row tile of the coefficient-bit operand stands for coded
+// packet 2*(r >> 4) + ((r >> 2) & 1) of the tile's four and for output bit
+// 4*((r >> 3) & 1) + (r & 3).  With the 32x32 output layout of the matrix
+// cores (lane c + 32h holds rows 8q + 4h + t, q, t < 4, as values 4q + t),
+// lane c + 32h then holds all 8 bits of the output bytes of packets h and
+// 2 + h at its column: values 8j .. 8j+7 are bits 0..7 of packet 2j + h.
+__device__ __forceinline__ int mf_row_packet(int r) { return 2 * (r >> 4) + ((r >> 2) & 1); }
+__device__ __forceinline__ int mf_row_bit(int r) { return 4 * ((r >> 3) & 1) + (r & 3); }
+
+// Parities of 8 exact integer counts (as floats) -> one byte, bit u from v[base + u].
+__device__ __forceinline__ uint32_t parity_byte(const gf_v16f &v, int base)
+{
+    uint32_t f[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++)
+        f[u] = __float_as_uint(v[base + u] + 8388608.0f);   // 2^23: the count's lowest bit is bit 0
+    // low bytes of four floats side by side, then bit 0 of byte k moved to bit 24 + k
+    const uint32_t w0 = __builtin_amdgcn_perm(f[1], f[0], 0x0c0c0400u) | __builtin_amdgcn_perm(f[3], f[2], 0x04000c0cu);
+    const uint32_t w1 = __builtin_amdgcn_perm(f[5], f[4], 0x0c0c0400u) | __builtin_amdgcn_perm(f[7], f[6], 0x04000c0cu);
+    const uint32_t lo = ((w0 & 0x01010101u) * 0x01020408u) >> 24;
+    const uint32_t hi = ((w1 & 0x01010101u) * 0x01020408u) >> 24;
+    return lo | (hi << 4);
+}
+
+// The strips of one tile for one wave: 64 payload bytes of every strip,
+// all MF_ROWS coded rows, accumulating over the generation's sources 8 at a
+// time; the source bytes of a step are loaded two steps ahead.
+template <bool EVEN>
+__device__ __forceinline__ void mf_tile(const DevGen &g, int k0, int nks, const uint32_t (*Ybuf)[4][64],
+                                        gf_v16f (&acc)[4][2], int wave, int lane)
+{
+    const int r = lane & 31, h = lane >> 5;
+    const int K = (int)g.K, N = (int)g.N;
+    const uint64_t nstrips = (g.len + MF_STRIP - 1) / MF_STRIP;
+    const uint64_t lane_col = (uint64_t)wave * 64u + 2u * (uint64_t)r;
+    auto load_src = [&](uint64_t strip, int ks, uint32_t (&u)[4]) {
+        const uint64_t col = strip * MF_STRIP + lane_col;
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+            const int n = ks * 8 + 4 * h + s;
+            const uint32_t v = load_pair<EVEN>(g.S + (uint64_t)(n < N ? n : N - 1) * g.ld_s, col, g.len);
+            u[s] = (n < N && strip < nstrips) ? v : 0u;
+        }
+    };
+    // prefetch position: (ps, pk) runs two steps ahead of (strip, ks)
+    uint64_t ps = 0;
+    int pk = 0;
+    auto advance = [&]() {
+        if (++pk == nks) {
+            pk = 0;
+            ps++;
+        }
+    };
+    uint32_t cur[4], nxt[4];
+    load_src(ps, pk, cur);
+    advance();
+    load_src(ps, pk, nxt);
+    advance();
+    for (uint64_t strip = 0; strip < nstrips; strip++) {
+        for (int ks = 0; ks < nks; ks++) {
+            const uint32_t t01 = __builtin_amdgcn_perm(cur[1], cur[0], 0x05010400u);
+            const uint32_t t23 = __builtin_amdgcn_perm(cur[3], cur[2], 0x05010400u);
+            const gf_v8i b0 = fp4_operand(__builtin_amdgcn_perm(t23, t01, 0x05040100u));
+            const gf_v8i b1 = fp4_operand(__builtin_amdgcn_perm(t23, t01, 0x07060302u));
+#pragma unroll
+            for (int s = 0; s < 4; s++)
+                cur[s] = nxt[s];
+            load_src(ps, pk, nxt);
+            advance();
+            if (ks == 0) {
+                const gf_v16f zero = {};
+#pragma unroll
+                for (int rt = 0; rt < 4; rt++) {
+                    const gf_v8i a = fp4_operand(Ybuf[ks][rt][lane]);
+                    acc[rt][0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b0, zero, 4, 4, 0, 127, 0, 127);
+                    acc[rt][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b1, zero, 4, 4, 0, 127, 0, 127);
+                }
+            } else {
+#pragma unroll
+                for (int rt = 0; rt < 4; rt++) {
+                    const gf_v8i a = fp4_operand(Ybuf[ks][rt][lane]);
+                    acc[rt][0] =
+                        __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b0, acc[rt][0], 4, 4, 0, 127, 0, 127);
+                    acc[rt][1] =
+                        __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b1, acc[rt][1], 4, 4, 0, 127, 0, 127);
+                }
+            }
+        }
+        // output bytes of this strip: packets 2j + h of every row tile
+        const uint64_t col = strip * MF_STRIP + lane_col;
+        if (col < g.len) {
+#pragma unroll
+            for (int rt = 0; rt < 4; rt++)
+#pragma unroll
+                for (int j = 0; j < 2; j++) {
+                    const int row = k0 + 4 * rt + 2 * j + h;
+                    if (row >= K)
+                        continue;
+                    const uint32_t v0 = parity_byte(acc[rt][0], 8 * j);
+                    const uint32_t v1 = parity_byte(acc[rt][1], 8 * j);
+                    uint8_t *yp = g.Y + (uint64_t)row * g.ld_y + col;
+                    if (col + 1 < g.len && ((((uintptr_t)yp) & 1u) == 0)) {
+                        *reinterpret_cast<uint16_t *>(yp) = (uint16_t)(v0 | (v1 << 8));
+                    } else {
+                        yp[0] = (uint8_t)v0;
+                        if (col + 1 < g.len)
+                            yp[1] = (uint8_t)v1;
+                    }
+                }
+        }
+    }
+}
+
+// Persistent: each workgroup takes tiles of MF_ROWS coded rows of one
+// generation and runs over the whole packet length in strips of MF_STRIP
+// bytes, so the coefficient-bit operand is built once per tile.
+__global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma(const DevGen *__restrict__ gens,
+                                                                         const DevTile *__restrict__ tiles,
+                                                                         int ntiles, unsigned *counters,
+                                                                         const uint8_t *__restrict__ rows_f)
+{
+    __shared__ uint8_t TR[256 * 8];
+    __shared__ uint32_t Ybuf[256 / 8][4][64];   // coefficient bit rows per step, row tile and lane
+    __shared__ uint32_t Cl[MF_ROWS][64];
+    __shared__ int s_tile;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 31, h = lane >> 5;
+    uint8_t *Cb = reinterpret_cast<uint8_t *>(Cl);
+    for (int i = tid; i < 256 * 8; i += 256)
+        TR[i] = rows_f[i];
+    gf_v16f acc[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++)
+#pragma unroll
+            for (int v = 0; v < 16; v++)
+                acc[a][b][v] = 0.0f;
+
+    for (;;) {
+        if (tid == 0)
+            s_tile = (int)atomicAdd(&counters[0], 1u);
+        __syncthreads();
+        const int t = s_tile;
+        __syncthreads();
+        if (t >= ntiles)
+            break;
+        const DevTile tl = tiles[t];
+        const DevGen g = gens[tl.gen];
+        if (g.status && *g.status != g.need)
+            continue;
+        const int K = (int)g.K, N = (int)g.N, k0 = (int)tl.k0;
+        const int NP = (N + 7) & ~7;
+        const int nks = NP >> 3;
+        for (int e = tid; e < MF_ROWS * NP; e += 256) {
+            const int pr = e / NP, n = e - pr * NP;
+            Cb[pr * 256 + n] = (k0 + pr < K && n < N) ? g.C[(uint64_t)(k0 + pr) * N + n] : 0;
+        }
+        __syncthreads();
+        // Coefficient bit rows of the whole tile: for lane (rr, hh) of row tile
+        // rt at step ks, byte s is row mf_row_bit(rr) of the bit matrix of
+        // C[k0 + 4 rt + mf_row_packet(rr)][8 ks + 4 hh + s].
+        for (int e = tid; e < nks * 256; e += 256) {
+            const int ks = e >> 8, rt = (e >> 6) & 3, ln = e & 63;
+            const int rr = ln & 31, hh = ln >> 5;
+            const int pk = rt * 4 + mf_row_packet(rr), bit = mf_row_bit(rr);
+            const uint32_t cw = Cl[pk][(ks * 8 + 4 * hh) >> 2];
+            uint32_t Y = 0;
+#pragma unroll
+            for (int s = 0; s < 4; s++)
+                Y |= (uint32_t)TR[((cw >> (8 * s)) & 0xFFu) * 8 + bit] << (8 * s);
+            Ybuf[ks][rt][ln] = Y;
+        }
+        __syncthreads();
+        // one instantiation only: two inlined copies sharing the accumulators
+        // exhaust the register file, and byte loads cost little next to the MFMAs
+        mf_tile<false>(g, k0, nks, Ybuf, acc, wave, lane);
+    }
+    if (tid == 0) {
+        __threadfence();
+        if (atomicAdd(&counters[1], 1u) == gridDim.x - 1) {
+            atomicExch(&counters[0], 0u);
+            atomicExch(&counters[1], 0u);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ invert
 
 // Gauss-Jordan inversion of one N x N matrix (N <= MAXN) in LDS, in place:
@@ -945,6 +1194,25 @@ hipError_t launch_status_gather(int *const *metas, int n, int4 *out, hipStream_t
         return hipSuccess;
     hipLaunchKernelGGL(k_status_gather, dim3((n + 255) / 256), dim3(256), 0, s, metas, n, out);
     return hipGetLastError();
+}
+
+hipError_t launch_encode_mfma(const DevGen *gens, const DevTile *tiles, int ntiles, unsigned *counters, int grid,
+                              const uint8_t *rows_field, hipStream_t s)
+{
+    if (ntiles <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_encode_mfma, dim3(grid), dim3(256), 0, s, gens, tiles, ntiles, counters, rows_field);
+    return hipGetLastError();
+}
+
+int encode_mfma_blocks_per_cu()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_encode_mfma), 256, 0) !=
+            hipSuccess ||
+        nb < 1)
+        return 1;
+    return nb;
 }
 
 }  // namespace gfnc

@@ -69,6 +69,13 @@ struct Builder {
             }
             for (int v = 0; v < 4; v++)
                 d[4] |= prodbyte(v << 6) << (8 * v);
+            // bit-matrix rows: column j is the product with the byte 1 << j
+            for (int j = 0; j < 8; j++) {
+                const uint32_t col = prodbyte(1 << j);
+                for (int i = 0; i < 8; i++)
+                    if ((col >> i) & 1u)
+                        t.rows[f][c][i] |= (uint8_t)(1u << j);
+            }
         }
     }
 };

@@ -125,10 +125,10 @@ def test_encode(gf, n, K, N, L):
 
 
 @pytest.mark.parametrize("n", FIELDS)
-@pytest.mark.parametrize("bpl", [0, 4, 8, 16])
+@pytest.mark.parametrize("form,bpl", [(1, 0), (1, 4), (1, 8), (1, 16), (2, 0)])
 @pytest.mark.parametrize("grid", [0, 1, 7])
-def test_encode_every_variant(gf, n, bpl, grid):
-    """Every schedule of the table kernel gives the same bytes (batched path, 30 generations)."""
+def test_encode_every_variant(gf, n, form, bpl, grid):
+    """Every schedule of both kernel forms gives the same bytes (batched path, 30 generations)."""
     torch = torch_cuda()
     gens, keep, wants = [], [], []
     for i in range(30):
@@ -141,8 +141,8 @@ def test_encode_every_variant(gf, n, bpl, grid):
         _, Sd = padded_rows(g.S, synth.padded(L))
         _, Yd = padded_rows(np.zeros((K, L), np.uint8), synth.padded(L))
         keep.append((Cd, Sd, Yd))
-    plan = gf.gf_plan_encode(n, keep, tune={"bytes_per_lane": bpl, "grid_blocks": grid})
-    assert plan.tuning()["bytes_per_lane"] == bpl
+    plan = gf.gf_plan_encode(n, keep, tune={"form": form, "bytes_per_lane": bpl, "grid_blocks": grid})
+    assert plan.tuning()["bytes_per_lane"] == bpl and plan.tuning()["form"] == form
     assert grid == 0 or plan.tuning()["grid_blocks"] == grid
     for rep in range(2):      # the work counter resets itself between launches
         for _, _, Yd in keep:
@@ -158,6 +158,36 @@ def test_encode_every_variant(gf, n, bpl, grid):
     torch.cuda.synchronize()
     for (Cd, Sd, Yd), w in zip(keep, wants):
         assert (host(Yd) == w).all()
+
+
+@pytest.mark.parametrize("n", FIELDS)
+@pytest.mark.parametrize("form", [0, 2])
+def test_batched_encode_odd_rows(gf, n, form):
+    """Odd row pitch and offset (byte paths of both forms), and the autotuned plan."""
+    torch = torch_cuda()
+    items, wants = [], []
+    for i in range(12):
+        N = [1, 7, 8, 9, 16, 17, 33, 100, 255, 256, 40, 3][i]
+        K = [1, 9, 16, 17, 31, 64, 5, 100, 3, 256, 48, 2][i]
+        L = [1, 2, 3, 255, 256, 257, 511, 1000, 77, 300, 2049, 4096][i]
+        g = synth.generation(synth.key(15, n, i), n, N, K, L)
+        wants.append(oracle.encode(n, g.C, g.S))
+        _, Sd = padded_rows(g.S, L + 3, 1)
+        yb, Yd = padded_rows(np.zeros((K, L), np.uint8), L + 5, 3, fill=0x5A)
+        items.append((dev(g.C), Sd, Yd, yb, K, L))
+    plan = gf.gf_plan_encode(n, [(C, S, Y) for C, S, Y, _, _, _ in items], tune={"form": form})
+    assert plan.tuning()["form"] in (1, 2)
+    for _, _, Yd, _, _, _ in items:
+        Yd.zero_()
+    gf.gf_encode_batched(plan)
+    torch.cuda.synchronize()
+    for (C, S, Yd, yb, K, L), w in zip(items, wants):
+        assert (host(Yd) == w).all()
+        raw = host(yb)
+        mask = np.ones(raw.size, bool)
+        for k in range(K):
+            mask[3 + k * (L + 5): 3 + k * (L + 5) + L] = False
+        assert (raw[mask] == 0x5A).all()
 
 
 def test_encode_single_generation_workload(gf):
