@@ -144,6 +144,7 @@ struct gf_plan {
     int count = 0;
     int fixed_D = 0;   // 0: lane width chosen per tile
     int form = 1;      // 1 table (VALU byte-select), 2 bit-matrix on the matrix cores
+    bool src_aligned4 = false;   // every generation's source rows start 4-byte aligned
     double tune_ms[3] = {0, 0, 0};   // autotuning trial times per form (0: not timed)
     int grid = 0;
     int ntiles = 0;
@@ -479,7 +480,8 @@ static int launch_schedule(gf_plan *p, DevState *d, hipStream_t s)
     const int f = p->field;
     hipError_t e;
     if (p->form == 2)
-        e = launch_encode_mfma(p->d_gens, p->d_tiles, p->ntiles, p->d_ctr, p->grid, field_rows(d, f), s);
+        e = launch_encode_mfma(p->d_gens, p->d_tiles, p->ntiles, p->d_ctr, p->grid, field_rows(d, f),
+                               p->src_aligned4, s);
     else
         e = launch_encode_persistent(p->d_gens, p->d_tiles, p->ntiles, p->d_ctr, p->grid, field_ptab(d, f), s);
     return dev_err(e);
@@ -500,7 +502,7 @@ static int make_schedule(gf_plan *p, DevState *d, const std::vector<DevGen> &g, 
     int rc = upload(&p->d_tiles, tl);
     if (rc)
         return rc;
-    int grid = d->cus * (form == 2 ? encode_mfma_blocks_per_cu() : encode_blocks_per_cu());
+    int grid = d->cus * (form == 2 ? encode_mfma_blocks_per_cu(p->src_aligned4) : encode_blocks_per_cu());
     if (tune && tune->grid_blocks > 0)
         grid = tune->grid_blocks;
     const int per_block = form == 2 ? 1 : 4;
@@ -545,8 +547,12 @@ static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, co
     if (form < 0 || form > 2)
         return GF_EINVAL;
     std::vector<DevGen> g = gens;
-    for (DevGen &x : g)
+    p->src_aligned4 = true;
+    for (DevGen &x : g) {
         x.align = row_align(x.S, x.N > 1 ? x.ld_s : 0, x.Y, x.K > 1 ? x.ld_y : 0);
+        if ((((uintptr_t)x.S) | (x.N > 1 ? x.ld_s : 0)) % 4 != 0)
+            p->src_aligned4 = false;
+    }
     if ((rc = upload(&p->d_gens, g)))
         return rc;
     if (hipMalloc(reinterpret_cast<void **>(&p->d_ctr), 2 * sizeof(unsigned)) != hipSuccess)

@@ -119,9 +119,10 @@ hipError_t launch_encode_persistent(const DevGen *gens, const DevTile *tiles, in
 // MF_STRIP payload bytes (DevTile.D unused).
 constexpr int MF_ROWS = 16;
 constexpr int MF_STRIP = 256;
+// aligned4: every generation's source rows start 4-byte aligned.
 hipError_t launch_encode_mfma(const DevGen *gens, const DevTile *tiles, int ntiles, unsigned *counters, int grid,
-                              const uint8_t *rows_field, hipStream_t s);
-int encode_mfma_blocks_per_cu();
+                              const uint8_t *rows_field, bool aligned4, hipStream_t s);
+int encode_mfma_blocks_per_cu(bool aligned4);
 hipError_t launch_invert(const DevSys *sys, int count, const uint8_t *C, int N, uint8_t *Cinv, int *rank,
                          const uint32_t *ptab_field, const uint8_t *inv_field, hipStream_t s);
 int encode_blocks_per_cu();

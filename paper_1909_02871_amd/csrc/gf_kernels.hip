@@ -484,24 +484,46 @@ __global__ __launch_bounds__(256, GF_ENC_WAVES_PER_SIMD) void k_encode_waves(con
 typedef int gf_v8i __attribute__((ext_vector_type(8)));
 typedef float gf_v16f __attribute__((ext_vector_type(16)));
 
-// Bits m and m + 4 of every byte of x as FP4 nibbles (0 or 1.0 = 0b0010): the
-// low nibble of byte s holds bit m, the high nibble bit m + 4.  Both operands
-// of an MFMA use this packing, so their reduction indices line up.
-__device__ __forceinline__ uint32_t fp4_bits(uint32_t x, int m)
-{
-    const uint32_t t = m == 0 ? (x << 1) : (x >> (m - 1));
-    return t & 0x22222222u;
-}
-
-__device__ __forceinline__ gf_v8i fp4_operand(uint32_t x)
+// FP4 (E2M1) operands whose values are 0 or a power of two.  A nibble with
+// only bit 0, 1 or 2 set is 0.5, 1.0 or 2.0, so an operand register is a plain
+// mask of the packed bits; bit 3 would be the sign, so bits 3 and 7 of a byte
+// are shifted down first.  Register m of both operands holds the same two input
+// bits of every byte (low nibble: bit j, high nibble: bit j + 4), and the two
+// operands put them at nibble positions whose values multiply to exactly 1:
+//   register   input bits   source operand   coefficient operand
+//      0          0, 4         bit 0: 0.5         bit 2: 2.0
+//      1          1, 5         bit 1: 1.0         bit 1: 1.0
+//      2          2, 6         bit 2: 2.0         bit 0: 0.5
+//      3          3, 7         bit 1: 1.0         bit 1: 1.0
+// The coefficient operand is stored with bits 0 and 2 (and 4 and 6) of each
+// byte swapped (coef_byte_order), so both sides are single masks; each
+// product is 1 and the FP32 sum is the exact count of common set bits.
+__device__ __forceinline__ gf_v8i fp4_source(uint32_t x)
 {
     gf_v8i v;
-    v[0] = (int)fp4_bits(x, 0);
-    v[1] = (int)fp4_bits(x, 1);
-    v[2] = (int)fp4_bits(x, 2);
-    v[3] = (int)fp4_bits(x, 3);
+    v[0] = (int)(x & 0x11111111u);
+    v[1] = (int)(x & 0x22222222u);
+    v[2] = (int)(x & 0x44444444u);
+    v[3] = (int)((x >> 2) & 0x22222222u);
     v[4] = v[5] = v[6] = v[7] = 0;
     return v;
+}
+
+__device__ __forceinline__ gf_v8i fp4_coef(uint32_t y)
+{
+    gf_v8i v;
+    v[0] = (int)(y & 0x44444444u);
+    v[1] = (int)(y & 0x22222222u);
+    v[2] = (int)(y & 0x11111111u);
+    v[3] = (int)((y >> 2) & 0x22222222u);
+    v[4] = v[5] = v[6] = v[7] = 0;
+    return v;
+}
+
+// A bit-matrix row byte with bits 0 <-> 2 and 4 <-> 6 exchanged (see fp4_coef).
+__device__ __forceinline__ uint8_t coef_byte_order(uint32_t b)
+{
+    return (uint8_t)((b & 0xAAu) | ((b & 0x11u) << 2) | ((b & 0x44u) >> 2));
 }
 
 // Bytes col and col + 1 of a row of len >= 1 bytes (zero past the end),
@@ -552,6 +574,87 @@ __device__ __forceinline__ uint32_t parity_byte(const gf_v16f &v, int base)
     return lo | (hi << 4);
 }
 
+// Tile set-up shared by the bit-matrix kernels: stage the tile's coefficient
+// rows, then build the coefficient-bit operand for every step.  For lane
+// (rr, hh) of row tile rt at step ks, byte s of Ybuf[ks][rt][lane] is row
+// mf_row_bit(rr) of the bit matrix of C[k0 + 4 rt + mf_row_packet(rr)][8 ks +
+// 4 hh + s], in coef_byte_order (TR holds the rows in that order).  Ends with
+// a barrier.
+__device__ __forceinline__ void mf_tile_setup(const DevGen &g, int k0, int nks, uint32_t (*Cl)[64],
+                                              uint32_t (*Ybuf)[4][64], const uint8_t *TR, int tid)
+{
+    const int K = (int)g.K, N = (int)g.N, NP = nks * 8;
+    uint8_t *Cb = reinterpret_cast<uint8_t *>(Cl);
+    for (int e = tid; e < MF_ROWS * NP; e += 256) {
+        const int pr = e / NP, n = e - pr * NP;
+        Cb[pr * 256 + n] = (k0 + pr < K && n < N) ? g.C[(uint64_t)(k0 + pr) * N + n] : 0;
+    }
+    __syncthreads();
+    for (int e = tid; e < nks * 256; e += 256) {
+        const int ks = e >> 8, rt = (e >> 6) & 3, ln = e & 63;
+        const int rr = ln & 31, hh = ln >> 5;
+        const int pk = rt * 4 + mf_row_packet(rr), bit = mf_row_bit(rr);
+        const uint32_t cw = Cl[pk][(ks * 8 + 4 * hh) >> 2];
+        uint32_t Y = 0;
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+            Y |= (uint32_t)TR[((cw >> (8 * s)) & 0xFFu) * 8 + bit] << (8 * s);
+        Ybuf[ks][rt][ln] = Y;
+    }
+    __syncthreads();
+}
+
+// Output bytes of one strip column pair (col, col + 1) of a wave: packets
+// 2j + h of every row tile.
+__device__ __forceinline__ void mf_store(const DevGen &g, int k0, uint64_t col, gf_v16f (&acc)[4][2], int h)
+{
+    const int K = (int)g.K;
+    if (col >= g.len)
+        return;
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            const int row = k0 + 4 * rt + 2 * j + h;
+            if (row >= K)
+                continue;
+            const uint32_t v0 = parity_byte(acc[rt][0], 8 * j);
+            const uint32_t v1 = parity_byte(acc[rt][1], 8 * j);
+            uint8_t *yp = g.Y + (uint64_t)row * g.ld_y + col;
+            if (col + 1 < g.len && ((((uintptr_t)yp) & 1u) == 0)) {
+                *reinterpret_cast<uint16_t *>(yp) = (uint16_t)(v0 | (v1 << 8));
+            } else {
+                yp[0] = (uint8_t)v0;
+                if (col + 1 < g.len)
+                    yp[1] = (uint8_t)v1;
+            }
+        }
+}
+
+// Step ks of the product for one wave: 8 MFMAs over the 4 row tiles and 2
+// column tiles; the first step of a strip starts from zero.
+__device__ __forceinline__ void mf_step(const uint32_t (*Ybuf)[4][64], int ks, int lane, uint32_t X0, uint32_t X1,
+                                        gf_v16f (&acc)[4][2])
+{
+    const gf_v8i b0 = fp4_source(X0), b1 = fp4_source(X1);
+    if (ks == 0) {
+        const gf_v16f zero = {};
+#pragma unroll
+        for (int rt = 0; rt < 4; rt++) {
+            const gf_v8i a = fp4_coef(Ybuf[ks][rt][lane]);
+            acc[rt][0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b0, zero, 4, 4, 0, 127, 0, 127);
+            acc[rt][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b1, zero, 4, 4, 0, 127, 0, 127);
+        }
+    } else {
+#pragma unroll
+        for (int rt = 0; rt < 4; rt++) {
+            const gf_v8i a = fp4_coef(Ybuf[ks][rt][lane]);
+            acc[rt][0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b0, acc[rt][0], 4, 4, 0, 127, 0, 127);
+            acc[rt][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b1, acc[rt][1], 4, 4, 0, 127, 0, 127);
+        }
+    }
+}
+
 // The strips of one tile for one wave: 64 payload bytes of every strip,
 // all MF_ROWS coded rows, accumulating over the generation's sources 8 at a
 // time; the source bytes of a step are loaded two steps ahead.
@@ -590,54 +693,16 @@ __device__ __forceinline__ void mf_tile(const DevGen &g, int k0, int nks, const 
         for (int ks = 0; ks < nks; ks++) {
             const uint32_t t01 = __builtin_amdgcn_perm(cur[1], cur[0], 0x05010400u);
             const uint32_t t23 = __builtin_amdgcn_perm(cur[3], cur[2], 0x05010400u);
-            const gf_v8i b0 = fp4_operand(__builtin_amdgcn_perm(t23, t01, 0x05040100u));
-            const gf_v8i b1 = fp4_operand(__builtin_amdgcn_perm(t23, t01, 0x07060302u));
+            const uint32_t X0 = __builtin_amdgcn_perm(t23, t01, 0x05040100u);
+            const uint32_t X1 = __builtin_amdgcn_perm(t23, t01, 0x07060302u);
 #pragma unroll
             for (int s = 0; s < 4; s++)
                 cur[s] = nxt[s];
             load_src(ps, pk, nxt);
             advance();
-            if (ks == 0) {
-                const gf_v16f zero = {};
-#pragma unroll
-                for (int rt = 0; rt < 4; rt++) {
-                    const gf_v8i a = fp4_operand(Ybuf[ks][rt][lane]);
-                    acc[rt][0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b0, zero, 4, 4, 0, 127, 0, 127);
-                    acc[rt][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b1, zero, 4, 4, 0, 127, 0, 127);
-                }
-            } else {
-#pragma unroll
-                for (int rt = 0; rt < 4; rt++) {
-                    const gf_v8i a = fp4_operand(Ybuf[ks][rt][lane]);
-                    acc[rt][0] =
-                        __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b0, acc[rt][0], 4, 4, 0, 127, 0, 127);
-                    acc[rt][1] =
-                        __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b1, acc[rt][1], 4, 4, 0, 127, 0, 127);
-                }
-            }
+            mf_step(Ybuf, ks, lane, X0, X1, acc);
         }
-        // output bytes of this strip: packets 2j + h of every row tile
-        const uint64_t col = strip * MF_STRIP + lane_col;
-        if (col < g.len) {
-#pragma unroll
-            for (int rt = 0; rt < 4; rt++)
-#pragma unroll
-                for (int j = 0; j < 2; j++) {
-                    const int row = k0 + 4 * rt + 2 * j + h;
-                    if (row >= K)
-                        continue;
-                    const uint32_t v0 = parity_byte(acc[rt][0], 8 * j);
-                    const uint32_t v1 = parity_byte(acc[rt][1], 8 * j);
-                    uint8_t *yp = g.Y + (uint64_t)row * g.ld_y + col;
-                    if (col + 1 < g.len && ((((uintptr_t)yp) & 1u) == 0)) {
-                        *reinterpret_cast<uint16_t *>(yp) = (uint16_t)(v0 | (v1 << 8));
-                    } else {
-                        yp[0] = (uint8_t)v0;
-                        if (col + 1 < g.len)
-                            yp[1] = (uint8_t)v1;
-                    }
-                }
-        }
+        mf_store(g, k0, strip * MF_STRIP + lane_col, acc, h);
     }
 }
 
@@ -654,10 +719,8 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma(const
     __shared__ uint32_t Cl[MF_ROWS][64];
     __shared__ int s_tile;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int r = lane & 31, h = lane >> 5;
-    uint8_t *Cb = reinterpret_cast<uint8_t *>(Cl);
     for (int i = tid; i < 256 * 8; i += 256)
-        TR[i] = rows_f[i];
+        TR[i] = coef_byte_order(rows_f[i]);
     gf_v16f acc[4][2];
 #pragma unroll
     for (int a = 0; a < 4; a++)
@@ -679,32 +742,168 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma(const
         const DevGen g = gens[tl.gen];
         if (g.status && *g.status != g.need)
             continue;
-        const int K = (int)g.K, N = (int)g.N, k0 = (int)tl.k0;
-        const int NP = (N + 7) & ~7;
-        const int nks = NP >> 3;
-        for (int e = tid; e < MF_ROWS * NP; e += 256) {
-            const int pr = e / NP, n = e - pr * NP;
-            Cb[pr * 256 + n] = (k0 + pr < K && n < N) ? g.C[(uint64_t)(k0 + pr) * N + n] : 0;
-        }
-        __syncthreads();
-        // Coefficient bit rows of the whole tile: for lane (rr, hh) of row tile
-        // rt at step ks, byte s is row mf_row_bit(rr) of the bit matrix of
-        // C[k0 + 4 rt + mf_row_packet(rr)][8 ks + 4 hh + s].
-        for (int e = tid; e < nks * 256; e += 256) {
-            const int ks = e >> 8, rt = (e >> 6) & 3, ln = e & 63;
-            const int rr = ln & 31, hh = ln >> 5;
-            const int pk = rt * 4 + mf_row_packet(rr), bit = mf_row_bit(rr);
-            const uint32_t cw = Cl[pk][(ks * 8 + 4 * hh) >> 2];
-            uint32_t Y = 0;
-#pragma unroll
-            for (int s = 0; s < 4; s++)
-                Y |= (uint32_t)TR[((cw >> (8 * s)) & 0xFFu) * 8 + bit] << (8 * s);
-            Ybuf[ks][rt][ln] = Y;
-        }
-        __syncthreads();
+        const int N = (int)g.N, k0 = (int)tl.k0;
+        const int nks = (N + 7) >> 3;
+        mf_tile_setup(g, k0, nks, Cl, Ybuf, TR, tid);
         // one instantiation only: two inlined copies sharing the accumulators
         // exhaust the register file, and byte loads cost little next to the MFMAs
         mf_tile<false>(g, k0, nks, Ybuf, acc, wave, lane);
+    }
+    if (tid == 0) {
+        __threadfence();
+        if (atomicAdd(&counters[1], 1u) == gridDim.x - 1) {
+            atomicExch(&counters[0], 0u);
+            atomicExch(&counters[1], 0u);
+        }
+    }
+}
+
+// Variant for sources whose row starts are 4-byte aligned: each wave copies
+// its own source bytes of a step (8 rows x 64 bytes) into LDS through the load
+// unit's direct-to-LDS path (4 bytes per lane, no registers), MF_STAGES - 1
+// steps ahead of their use, so the waves of a workgroup never wait for one
+// another inside a tile.
+#ifndef GF_MF_STAGES
+#define GF_MF_STAGES 6
+#endif
+constexpr int MF_STAGES = GF_MF_STAGES;
+// s_waitcnt immediate (gfx9 layout): vmcnt = 2 (MF_STAGES - 2) in bits 3:0 and
+// 15:14, expcnt and lgkmcnt left at their maxima (no wait).
+constexpr int kWaitVm = 2 * (MF_STAGES - 2);
+constexpr int kWaitCopies = (kWaitVm & 0xF) | ((kWaitVm >> 4) << 14) | (0x7 << 4) | (0xF << 8);
+constexpr int kWaitAll = (0x7 << 4) | (0xF << 8);
+static_assert(kWaitVm < 64, "vmcnt field is 6 bits");
+
+__global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(const DevGen *__restrict__ gens,
+                                                                             const DevTile *__restrict__ tiles,
+                                                                             int ntiles, unsigned *counters,
+                                                                             const uint8_t *__restrict__ rows_f)
+{
+    __shared__ uint8_t TR[256 * 8];
+    __shared__ uint32_t Ybuf[256 / 8][4][64];
+    __shared__ uint32_t Cl[MF_ROWS][64];
+    __shared__ uint32_t Sw[4][MF_STAGES][8][16];   // [wave][stage][source row][64 bytes]
+    __shared__ int s_tile;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 31, h = lane >> 5;
+    for (int i = tid; i < 256 * 8; i += 256)
+        TR[i] = coef_byte_order(rows_f[i]);
+    gf_v16f acc[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++)
+#pragma unroll
+            for (int v = 0; v < 16; v++)
+                acc[a][b][v] = 0.0f;
+
+    for (;;) {
+        if (tid == 0)
+            s_tile = (int)atomicAdd(&counters[0], 1u);
+        __syncthreads();
+        const int t = s_tile;
+        __syncthreads();
+        if (t >= ntiles)
+            break;
+        const DevTile tl = tiles[t];
+        const DevGen g = gens[tl.gen];
+        if (g.status && *g.status != g.need)
+            continue;
+        const int N = (int)g.N, k0 = (int)tl.k0;
+        const int nks = (N + 7) >> 3;
+        mf_tile_setup(g, k0, nks, Cl, Ybuf, TR, tid);
+        const uint64_t nstrips = (g.len + MF_STRIP - 1) / MF_STRIP;
+        const uint64_t Z = nstrips * (uint64_t)nks;
+        // Copy position (cs, ck) = flat step cz: lane l copies 4 bytes of source
+        // row l / 16 (+ 4) at byte (l % 16) * 4 of this wave's 64.  Every step
+        // below Z issues exactly two copy instructions, each from at least 60
+        // lanes, so the count of copies in flight is known.  Inside the packet
+        // and the generation (the common case, decided per wave) a copy is a
+        // wave-uniform base plus a fixed per-lane offset.  Otherwise lanes for
+        // rows past N or chunks past the packet end copy a zero word (row 0 of
+        // the table, the bit matrix of 0; those bytes meet zero coefficient
+        // bits or are never stored), and only the lanes whose chunk straddles
+        // the packet end assemble it byte by byte.
+        const uint64_t ld = g.ld_s;
+        const bool narrow = ld <= (1u << 26);
+        const uint32_t loff = (uint32_t)(lane >> 4) * (uint32_t)ld + (uint32_t)wave * 64u + (uint32_t)(lane & 15) * 4u;
+        const uint32_t loff4 = loff + 4u * (uint32_t)ld;
+        uint64_t cs = 0, cz = 0;
+        int ck = 0, cslot = 0;
+        auto copy_step = [&]() {
+            if (cz < Z) {
+                uint32_t *dst0 = &Sw[wave][cslot][0][0];
+                uint32_t *dst4 = &Sw[wave][cslot][4][0];
+                if (narrow && ck * 8 + 8 <= N && (cs + 1) * MF_STRIP <= g.len) {
+                    const uint8_t *base = g.S + (uint64_t)ck * 8u * ld + cs * MF_STRIP;
+                    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(base + loff),
+                                                     (__attribute__((address_space(3))) void *)dst0, 4, 0, 0);
+                    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(base + loff4),
+                                                     (__attribute__((address_space(3))) void *)dst4, 4, 0, 0);
+                } else {
+#pragma unroll
+                    for (int half = 0; half < 2; half++) {
+                        const int n = ck * 8 + 4 * half + (lane >> 4);
+                        const uint64_t col = cs * MF_STRIP + (uint64_t)wave * 64u + (uint64_t)(lane & 15) * 4u;
+                        const uint8_t *row = g.S + (uint64_t)n * ld;
+                        uint32_t *dst = half ? dst4 : dst0;
+                        const bool full = n < N && col + 4 <= g.len;
+                        const bool straddle = n < N && col < g.len && !full;
+                        if (!straddle) {
+                            __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(full ? row + col : rows_f),
+                                                             (__attribute__((address_space(3))) void *)dst, 4, 0, 0);
+                        } else {
+                            uint32_t v = 0;
+                            for (int b = 0; b < 4; b++)
+                                if (col + b < g.len)
+                                    v |= (uint32_t)row[col + b] << (8 * b);
+                            dst[lane] = v;
+                        }
+                    }
+                }
+            }
+            cz++;
+            if (++cslot == MF_STAGES)
+                cslot = 0;
+            if (++ck == nks) {
+                ck = 0;
+                cs++;
+            }
+        };
+        for (int j = 0; j < MF_STAGES - 1; j++)
+            copy_step();
+        uint64_t z = 0;
+        int rslot = 0;
+        for (uint64_t strip = 0; strip < nstrips; strip++) {
+            for (int ks = 0; ks < nks; ks++, z++) {
+                // This wave's copy of step z has landed once at most 2 (MF_STAGES - 2)
+                // newer vector-memory operations are outstanding; near the end of
+                // the tile fewer copies follow it, so wait for all.
+                if (z + (MF_STAGES - 2) < Z)
+                    __builtin_amdgcn_s_waitcnt(kWaitCopies);
+                else
+                    __builtin_amdgcn_s_waitcnt(kWaitAll);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const uint16_t *rows = reinterpret_cast<const uint16_t *>(&Sw[wave][rslot][4 * h][0]);
+                if (++rslot == MF_STAGES)
+                    rslot = 0;
+                // bytes of rows past N meet zero coefficient bits and bytes past
+                // the packet end are never stored, so they need no masking
+                uint32_t u[4];
+#pragma unroll
+                for (int s = 0; s < 4; s++)
+                    u[s] = rows[s * 32 + r];
+                const uint32_t t01 = __builtin_amdgcn_perm(u[1], u[0], 0x05010400u);
+                const uint32_t t23 = __builtin_amdgcn_perm(u[3], u[2], 0x05010400u);
+                const uint32_t X0 = __builtin_amdgcn_perm(t23, t01, 0x05040100u);
+                const uint32_t X1 = __builtin_amdgcn_perm(t23, t01, 0x07060302u);
+                // the slot of step z - 1 is free: its bytes are in registers already
+                copy_step();
+                mf_step(Ybuf, ks, lane, X0, X1, acc);
+            }
+        mf_store(g, k0, strip * MF_STRIP + (uint64_t)wave * 64u + 2u * (uint64_t)r, acc, h);
+        }
+        __syncthreads();   // every wave is done with Cl and Ybuf before the next tile
     }
     if (tid == 0) {
         __threadfence();
@@ -1197,18 +1396,23 @@ hipError_t launch_status_gather(int *const *metas, int n, int4 *out, hipStream_t
 }
 
 hipError_t launch_encode_mfma(const DevGen *gens, const DevTile *tiles, int ntiles, unsigned *counters, int grid,
-                              const uint8_t *rows_field, hipStream_t s)
+                              const uint8_t *rows_field, bool aligned4, hipStream_t s)
 {
     if (ntiles <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_encode_mfma, dim3(grid), dim3(256), 0, s, gens, tiles, ntiles, counters, rows_field);
+    if (aligned4)
+        hipLaunchKernelGGL(k_encode_mfma_dma, dim3(grid), dim3(256), 0, s, gens, tiles, ntiles, counters, rows_field);
+    else
+        hipLaunchKernelGGL(k_encode_mfma, dim3(grid), dim3(256), 0, s, gens, tiles, ntiles, counters, rows_field);
     return hipGetLastError();
 }
 
-int encode_mfma_blocks_per_cu()
+int encode_mfma_blocks_per_cu(bool aligned4)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_encode_mfma), 256, 0) !=
+    const void *k = aligned4 ? reinterpret_cast<const void *>(&k_encode_mfma_dma)
+                              : reinterpret_cast<const void *>(&k_encode_mfma);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, 0) !=
             hipSuccess ||
         nb < 1)
         return 1;

@@ -162,8 +162,10 @@ def test_encode_every_variant(gf, n, form, bpl, grid):
 
 @pytest.mark.parametrize("n", FIELDS)
 @pytest.mark.parametrize("form", [0, 2])
-def test_batched_encode_odd_rows(gf, n, form):
-    """Odd row pitch and offset (byte paths of both forms), and the autotuned plan."""
+@pytest.mark.parametrize("pitch,off", [(3, 1), (4, 4)])
+def test_batched_encode_odd_rows(gf, n, form, pitch, off):
+    """Row pitch and offset off the 16-byte grid: odd (byte paths of both forms)
+    and word-aligned (word copies of the bit-matrix form); the autotuned plan."""
     torch = torch_cuda()
     items, wants = [], []
     for i in range(12):
@@ -172,7 +174,7 @@ def test_batched_encode_odd_rows(gf, n, form):
         L = [1, 2, 3, 255, 256, 257, 511, 1000, 77, 300, 2049, 4096][i]
         g = synth.generation(synth.key(15, n, i), n, N, K, L)
         wants.append(oracle.encode(n, g.C, g.S))
-        _, Sd = padded_rows(g.S, L + 3, 1)
+        _, Sd = padded_rows(g.S, (L + 3) // 4 * 4 + pitch, off)
         yb, Yd = padded_rows(np.zeros((K, L), np.uint8), L + 5, 3, fill=0x5A)
         items.append((dev(g.C), Sd, Yd, yb, K, L))
     plan = gf.gf_plan_encode(n, [(C, S, Y) for C, S, Y, _, _, _ in items], tune={"form": form})
