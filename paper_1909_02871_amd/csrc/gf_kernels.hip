@@ -559,13 +559,17 @@ __device__ __forceinline__ uint32_t load_pair(const uint8_t *row, uint64_t col, 
 __device__ __forceinline__ int mf_row_packet(int r) { return 2 * (r >> 4) + ((r >> 2) & 1); }
 __device__ __forceinline__ int mf_row_bit(int r) { return 4 * ((r >> 3) & 1) + (r & 3); }
 
-// Parities of 8 exact integer counts (as floats) -> one byte, bit u from v[base + u].
+// Accumulators start at 2^23: a count c < 2^23 added to it is exact and sits in
+// the low mantissa bits, so the count's parity is bit 0 of the float's bits.
+constexpr float kParityBias = 8388608.0f;
+
+// Parities of 8 biased counts -> one byte, bit u from v[base + u].
 __device__ __forceinline__ uint32_t parity_byte(const gf_v16f &v, int base)
 {
     uint32_t f[8];
 #pragma unroll
     for (int u = 0; u < 8; u++)
-        f[u] = __float_as_uint(v[base + u] + 8388608.0f);   // 2^23: the count's lowest bit is bit 0
+        f[u] = __float_as_uint(v[base + u]);
     // low bytes of four floats side by side, then bit 0 of byte k moved to bit 24 + k
     const uint32_t w0 = __builtin_amdgcn_perm(f[1], f[0], 0x0c0c0400u) | __builtin_amdgcn_perm(f[3], f[2], 0x04000c0cu);
     const uint32_t w1 = __builtin_amdgcn_perm(f[5], f[4], 0x0c0c0400u) | __builtin_amdgcn_perm(f[7], f[6], 0x04000c0cu);
@@ -605,45 +609,59 @@ __device__ __forceinline__ void mf_tile_setup(const DevGen &g, int k0, int nks, 
 }
 
 // Output bytes of one strip column pair (col, col + 1) of a wave: packets
-// 2j + h of every row tile.
-__device__ __forceinline__ void mf_store(const DevGen &g, int k0, uint64_t col, gf_v16f (&acc)[4][2], int h)
+// 2j + h of every row tile.  RUNNING: the accumulators hold a running total
+// over the tile's strips, so this strip's parities are those of the total
+// XOR those of the previous total, kept per lane in prev (two bytes per
+// packet: prev[rt] holds j = 0 in bits 0..15 and j = 1 in bits 16..31).
+// Stores go through the global address space (no LDS counter traffic).
+template <bool RUNNING>
+__device__ __forceinline__ void mf_store(const DevGen &g, int k0, uint64_t col, gf_v16f (&acc)[4][2], int h,
+                                         uint32_t (&prev)[4])
 {
     const int K = (int)g.K;
-    if (col >= g.len)
-        return;
 #pragma unroll
-    for (int rt = 0; rt < 4; rt++)
+    for (int rt = 0; rt < 4; rt++) {
+        uint32_t pr = 0;
 #pragma unroll
         for (int j = 0; j < 2; j++) {
+            uint32_t v = parity_byte(acc[rt][0], 8 * j) | (parity_byte(acc[rt][1], 8 * j) << 8);
+            pr |= v << (16 * j);
+            if (RUNNING)
+                v ^= (prev[rt] >> (16 * j)) & 0xFFFFu;
             const int row = k0 + 4 * rt + 2 * j + h;
-            if (row >= K)
+            if (row >= K || col >= g.len)
                 continue;
-            const uint32_t v0 = parity_byte(acc[rt][0], 8 * j);
-            const uint32_t v1 = parity_byte(acc[rt][1], 8 * j);
-            uint8_t *yp = g.Y + (uint64_t)row * g.ld_y + col;
-            if (col + 1 < g.len && ((((uintptr_t)yp) & 1u) == 0)) {
-                *reinterpret_cast<uint16_t *>(yp) = (uint16_t)(v0 | (v1 << 8));
+            auto *yp = reinterpret_cast<__attribute__((address_space(1))) uint8_t *>(
+                reinterpret_cast<uintptr_t>(g.Y + (uint64_t)row * g.ld_y + col));
+            if (col + 1 < g.len && ((reinterpret_cast<uintptr_t>(yp) & 1u) == 0)) {
+                *reinterpret_cast<__attribute__((address_space(1))) uint16_t *>(yp) = (uint16_t)v;
             } else {
-                yp[0] = (uint8_t)v0;
+                yp[0] = (uint8_t)v;
                 if (col + 1 < g.len)
-                    yp[1] = (uint8_t)v1;
+                    yp[1] = (uint8_t)(v >> 8);
             }
         }
+        if (RUNNING)
+            prev[rt] = pr;
+    }
 }
 
 // Step ks of the product for one wave: 8 MFMAs over the 4 row tiles and 2
-// column tiles; the first step of a strip starts from zero.
+// column tiles; the first step of a strip starts from kParityBias.
 __device__ __forceinline__ void mf_step(const uint32_t (*Ybuf)[4][64], int ks, int lane, uint32_t X0, uint32_t X1,
                                         gf_v16f (&acc)[4][2])
 {
     const gf_v8i b0 = fp4_source(X0), b1 = fp4_source(X1);
     if (ks == 0) {
-        const gf_v16f zero = {};
+        gf_v16f bias;
+#pragma unroll
+        for (int v = 0; v < 16; v++)
+            bias[v] = kParityBias;
 #pragma unroll
         for (int rt = 0; rt < 4; rt++) {
             const gf_v8i a = fp4_coef(Ybuf[ks][rt][lane]);
-            acc[rt][0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b0, zero, 4, 4, 0, 127, 0, 127);
-            acc[rt][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b1, zero, 4, 4, 0, 127, 0, 127);
+            acc[rt][0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b0, bias, 4, 4, 0, 127, 0, 127);
+            acc[rt][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b1, bias, 4, 4, 0, 127, 0, 127);
         }
     } else {
 #pragma unroll
@@ -684,7 +702,7 @@ __device__ __forceinline__ void mf_tile(const DevGen &g, int k0, int nks, const 
             ps++;
         }
     };
-    uint32_t cur[4], nxt[4];
+    uint32_t cur[4], nxt[4], unused[4] = {};
     load_src(ps, pk, cur);
     advance();
     load_src(ps, pk, nxt);
@@ -702,7 +720,7 @@ __device__ __forceinline__ void mf_tile(const DevGen &g, int k0, int nks, const 
             advance();
             mf_step(Ybuf, ks, lane, X0, X1, acc);
         }
-        mf_store(g, k0, strip * MF_STRIP + lane_col, acc, h);
+        mf_store<false>(g, k0, strip * MF_STRIP + lane_col, acc, h, unused);
     }
 }
 
@@ -762,17 +780,57 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma(const
 // its own source bytes of a step (8 rows x 64 bytes) into LDS through the load
 // unit's direct-to-LDS path (4 bytes per lane, no registers), MF_STAGES - 1
 // steps ahead of their use, so the waves of a workgroup never wait for one
-// another inside a tile.
+// another inside a tile.  The steps of a tile (all strips, all source groups)
+// form one software pipeline: while the matrix cores work on step z, the wave
+// reads and unpacks the operands of step z + 1.
 #ifndef GF_MF_STAGES
-#define GF_MF_STAGES 6
+#define GF_MF_STAGES 8
 #endif
 constexpr int MF_STAGES = GF_MF_STAGES;
-// s_waitcnt immediate (gfx9 layout): vmcnt = 2 (MF_STAGES - 2) in bits 3:0 and
-// 15:14, expcnt and lgkmcnt left at their maxima (no wait).
+static_assert((MF_STAGES & (MF_STAGES - 1)) == 0 && MF_STAGES >= 2, "stages: a power of two");
+// Every copy step issues exactly two copy instructions (past the tile's last
+// step they copy a zero word into a slot that is no longer read), so when the
+// operands of step z are read, the copies of steps z + 1 .. z + MF_STAGES - 2
+// are the only newer vector-memory loads: s_waitcnt vmcnt(2 (MF_STAGES - 2)),
+// in the gfx9 encoding (vmcnt in bits 3:0 and 15:14; expcnt and lgkmcnt at
+// their maxima, i.e. not waited for).  Stores issued in between only make the
+// wait stricter: loads complete in order, so the count cannot drop that low
+// while the awaited copy is outstanding.
 constexpr int kWaitVm = 2 * (MF_STAGES - 2);
 constexpr int kWaitCopies = (kWaitVm & 0xF) | ((kWaitVm >> 4) << 14) | (0x7 << 4) | (0xF << 8);
 constexpr int kWaitAll = (0x7 << 4) | (0xF << 8);
 static_assert(kWaitVm < 64, "vmcnt field is 6 bits");
+
+typedef unsigned short gf_u16x2 __attribute__((ext_vector_type(2)));
+
+// The operands of one step: the coefficient bits of the 4 row tiles and the
+// source bits of the wave's 2 column tiles.
+struct MfOperands {
+    gf_v8i a[4];
+    gf_v8i b[2];
+};
+
+__device__ __forceinline__ void mf_mma(const MfOperands &o, gf_v16f (&acc)[4][2])
+{
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++) {
+        acc[rt][0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(o.a[rt], o.b[0], acc[rt][0], 4, 4, 0, 127, 0, 127);
+        acc[rt][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(o.a[rt], o.b[1], acc[rt][1], 4, 4, 0, 127, 0, 127);
+    }
+}
+
+constexpr int kMfRestart = 2048;
+
+__device__ __forceinline__ void mf_acc_reset(gf_v16f (&acc)[4][2])
+{
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++)
+#pragma unroll
+            for (int v = 0; v < 16; v++)
+                acc[a][b][v] = kParityBias;
+}
 
 __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(const DevGen *__restrict__ gens,
                                                                              const DevTile *__restrict__ tiles,
@@ -784,18 +842,12 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
     __shared__ uint32_t Cl[MF_ROWS][64];
     __shared__ uint32_t Sw[4][MF_STAGES][8][16];   // [wave][stage][source row][64 bytes]
     __shared__ int s_tile;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int r = lane & 31, h = lane >> 5;
     for (int i = tid; i < 256 * 8; i += 256)
         TR[i] = coef_byte_order(rows_f[i]);
     gf_v16f acc[4][2];
-#pragma unroll
-    for (int a = 0; a < 4; a++)
-#pragma unroll
-        for (int b = 0; b < 2; b++)
-#pragma unroll
-            for (int v = 0; v < 16; v++)
-                acc[a][b][v] = 0.0f;
 
     for (;;) {
         if (tid == 0)
@@ -812,97 +864,114 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
         const int N = (int)g.N, k0 = (int)tl.k0;
         const int nks = (N + 7) >> 3;
         mf_tile_setup(g, k0, nks, Cl, Ybuf, TR, tid);
-        const uint64_t nstrips = (g.len + MF_STRIP - 1) / MF_STRIP;
-        const uint64_t Z = nstrips * (uint64_t)nks;
-        // Copy position (cs, ck) = flat step cz: lane l copies 4 bytes of source
-        // row l / 16 (+ 4) at byte (l % 16) * 4 of this wave's 64.  Every step
-        // below Z issues exactly two copy instructions, each from at least 60
-        // lanes, so the count of copies in flight is known.  Inside the packet
-        // and the generation (the common case, decided per wave) a copy is a
-        // wave-uniform base plus a fixed per-lane offset.  Otherwise lanes for
-        // rows past N or chunks past the packet end copy a zero word (row 0 of
-        // the table, the bit matrix of 0; those bytes meet zero coefficient
-        // bits or are never stored), and only the lanes whose chunk straddles
-        // the packet end assemble it byte by byte.
         const uint64_t ld = g.ld_s;
-        const bool narrow = ld <= (1u << 26);
-        const uint32_t loff = (uint32_t)(lane >> 4) * (uint32_t)ld + (uint32_t)wave * 64u + (uint32_t)(lane & 15) * 4u;
+        const int nstrips = (int)((g.len + MF_STRIP - 1) / MF_STRIP);
+        const int Z = nstrips * nks;            // the plan keeps this below 2^31
+        // Copies of whole 8-row groups inside whole strips are a wave-uniform
+        // base plus a fixed per-lane offset (when the offsets fit 32 bits).
+        const int ks_full = N >> 3;
+        const int strips_full = ld <= (1u << 26) ? (int)(g.len / MF_STRIP) : 0;
+        const uint32_t lcol = (uint32_t)wave * 64u + (uint32_t)(lane & 15) * 4u;
+        const uint32_t loff = (uint32_t)(lane >> 4) * (uint32_t)ld + lcol;
         const uint32_t loff4 = loff + 4u * (uint32_t)ld;
-        uint64_t cs = 0, cz = 0;
-        int ck = 0, cslot = 0;
+        // Copy cursor: step cz = (strip cs, group ck); lane l copies 4 bytes of
+        // source row 8 ck + l / 16 (+ 4) at byte (l % 16) * 4 of this wave's 64.
+        // Outside the generation or the packet a lane copies a zero word (row 0
+        // of the table, the bit matrix of 0): such bytes meet zero coefficient
+        // bits or are never stored.  A chunk that straddles the packet end is
+        // assembled byte by byte (at most 4 lanes per instruction).
+        int cz = 0, ck = 0, cs = 0;
+        const uint8_t *cbase = g.S;
         auto copy_step = [&]() {
-            if (cz < Z) {
-                uint32_t *dst0 = &Sw[wave][cslot][0][0];
-                uint32_t *dst4 = &Sw[wave][cslot][4][0];
-                if (narrow && ck * 8 + 8 <= N && (cs + 1) * MF_STRIP <= g.len) {
-                    const uint8_t *base = g.S + (uint64_t)ck * 8u * ld + cs * MF_STRIP;
-                    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(base + loff),
-                                                     (__attribute__((address_space(3))) void *)dst0, 4, 0, 0);
-                    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(base + loff4),
-                                                     (__attribute__((address_space(3))) void *)dst4, 4, 0, 0);
-                } else {
+            const int slot = cz & (MF_STAGES - 1);
+            uint32_t *dst0 = &Sw[wave][slot][0][0];
+            uint32_t *dst4 = &Sw[wave][slot][4][0];
+            if (ck < ks_full && cs < strips_full) {
+                __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(cbase + loff),
+                                                 (__attribute__((address_space(3))) void *)dst0, 4, 0, 0);
+                __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(cbase + loff4),
+                                                 (__attribute__((address_space(3))) void *)dst4, 4, 0, 0);
+            } else {
+                const bool live = cz < Z;
+                const uint64_t rem = live ? g.len - (uint64_t)cs * MF_STRIP : 0;
+                const int remrows = live ? N - ck * 8 : 0;
 #pragma unroll
-                    for (int half = 0; half < 2; half++) {
-                        const int n = ck * 8 + 4 * half + (lane >> 4);
-                        const uint64_t col = cs * MF_STRIP + (uint64_t)wave * 64u + (uint64_t)(lane & 15) * 4u;
-                        const uint8_t *row = g.S + (uint64_t)n * ld;
-                        uint32_t *dst = half ? dst4 : dst0;
-                        const bool full = n < N && col + 4 <= g.len;
-                        const bool straddle = n < N && col < g.len && !full;
-                        if (!straddle) {
-                            __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(full ? row + col : rows_f),
-                                                             (__attribute__((address_space(3))) void *)dst, 4, 0, 0);
-                        } else {
-                            uint32_t v = 0;
-                            for (int b = 0; b < 4; b++)
-                                if (col + b < g.len)
-                                    v |= (uint32_t)row[col + b] << (8 * b);
-                            dst[lane] = v;
-                        }
+                for (int half = 0; half < 2; half++) {
+                    const int rr = 4 * half + (lane >> 4);
+                    const uint8_t *src = cbase + (uint64_t)rr * ld + lcol;
+                    uint32_t *dst = half ? dst4 : dst0;
+                    const bool rowok = rr < remrows;
+                    const bool full = rowok && lcol + 4 <= rem;
+                    const bool straddle = rowok && lcol < rem && !full;
+                    if (!straddle) {
+                        __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(full ? src : rows_f),
+                                                         (__attribute__((address_space(3))) void *)dst, 4, 0, 0);
+                    } else {
+                        uint32_t v = 0;
+                        for (uint32_t b = 0; lcol + b < rem; b++)
+                            v |= (uint32_t)src[b] << (8 * b);
+                        dst[lane] = v;
                     }
                 }
             }
             cz++;
-            if (++cslot == MF_STAGES)
-                cslot = 0;
+            cbase += 8u * ld;
             if (++ck == nks) {
                 ck = 0;
                 cs++;
+                cbase = g.S + (uint64_t)cs * MF_STRIP;
             }
         };
+        // Operands of step zf (source group ksf): its copy has landed once the
+        // newer copies alone are outstanding.  Bytes of rows past N and past the
+        // packet end need no masking (see copy_step).
+        auto fetch = [&](int zf, int ksf, MfOperands &o) {
+            __builtin_amdgcn_s_waitcnt(kWaitCopies);
+            asm volatile("" ::: "memory");
+            const uint16_t *rows = reinterpret_cast<const uint16_t *>(&Sw[wave][zf & (MF_STAGES - 1)][4 * h][0]);
+            gf_u16x2 p01, p23;
+            p01.x = rows[0 * 32 + r];
+            p01.y = rows[1 * 32 + r];
+            p23.x = rows[2 * 32 + r];
+            p23.y = rows[3 * 32 + r];
+            const uint32_t t01 = __builtin_bit_cast(uint32_t, p01);   // r0c0 r0c1 r1c0 r1c1
+            const uint32_t t23 = __builtin_bit_cast(uint32_t, p23);   // r2c0 r2c1 r3c0 r3c1
+            o.b[0] = fp4_source(__builtin_amdgcn_perm(t23, t01, 0x06040200u));   // column 2r of rows 0..3
+            o.b[1] = fp4_source(__builtin_amdgcn_perm(t23, t01, 0x07050301u));   // column 2r + 1
+#pragma unroll
+            for (int rt = 0; rt < 4; rt++)
+                o.a[rt] = fp4_coef(Ybuf[ksf][rt][lane]);
+        };
+
         for (int j = 0; j < MF_STAGES - 1; j++)
             copy_step();
-        uint64_t z = 0;
-        int rslot = 0;
-        for (uint64_t strip = 0; strip < nstrips; strip++) {
+        mf_acc_reset(acc);
+        MfOperands cur;
+        fetch(0, 0, cur);
+        // The accumulators run over all strips of the tile and restart every
+        // kMfRestart strips: a strip adds at most 64 nks <= 2048 to a count, so
+        // the total stays below 2^23 + 2^22, exact in FP32.
+        uint32_t prev[4] = {0u, 0u, 0u, 0u};
+        int z = 0;
+        for (int strip = 0; strip < nstrips; strip++) {
             for (int ks = 0; ks < nks; ks++, z++) {
-                // This wave's copy of step z has landed once at most 2 (MF_STAGES - 2)
-                // newer vector-memory operations are outstanding; near the end of
-                // the tile fewer copies follow it, so wait for all.
-                if (z + (MF_STAGES - 2) < Z)
-                    __builtin_amdgcn_s_waitcnt(kWaitCopies);
-                else
-                    __builtin_amdgcn_s_waitcnt(kWaitAll);
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                const uint16_t *rows = reinterpret_cast<const uint16_t *>(&Sw[wave][rslot][4 * h][0]);
-                if (++rslot == MF_STAGES)
-                    rslot = 0;
-                // bytes of rows past N meet zero coefficient bits and bytes past
-                // the packet end are never stored, so they need no masking
-                uint32_t u[4];
-#pragma unroll
-                for (int s = 0; s < 4; s++)
-                    u[s] = rows[s * 32 + r];
-                const uint32_t t01 = __builtin_amdgcn_perm(u[1], u[0], 0x05010400u);
-                const uint32_t t23 = __builtin_amdgcn_perm(u[3], u[2], 0x05010400u);
-                const uint32_t X0 = __builtin_amdgcn_perm(t23, t01, 0x05040100u);
-                const uint32_t X1 = __builtin_amdgcn_perm(t23, t01, 0x07060302u);
-                // the slot of step z - 1 is free: its bytes are in registers already
-                copy_step();
-                mf_step(Ybuf, ks, lane, X0, X1, acc);
+                copy_step();              // step z + MF_STAGES - 1, into the slot of step z - 1
+                MfOperands nxt;           // the next step: this strip's next group or the next strip's first
+                fetch(z + 1, ks + 1 == nks ? 0 : ks + 1, nxt);   // past the last step: a zero slot, never used
+                mf_mma(cur, acc);         // independent of the fetch: the two interleave
+                cur = nxt;
             }
-        mf_store(g, k0, strip * MF_STRIP + (uint64_t)wave * 64u + 2u * (uint64_t)r, acc, h);
+            mf_store<true>(g, k0, (uint64_t)strip * MF_STRIP + (uint64_t)wave * 64u + 2u * (uint64_t)r, acc, h,
+                           prev);
+            if ((strip & (kMfRestart - 1)) == kMfRestart - 1) {
+                mf_acc_reset(acc);
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+                    prev[i] = 0u;
+            }
         }
+        // the copies past the last step land before the slots are reused
+        __builtin_amdgcn_s_waitcnt(kWaitAll);
         __syncthreads();   // every wave is done with Cl and Ybuf before the next tile
     }
     if (tid == 0) {

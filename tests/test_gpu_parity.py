@@ -192,6 +192,24 @@ def test_batched_encode_odd_rows(gf, n, form, pitch, off):
         assert (raw[mask] == 0x5A).all()
 
 
+@pytest.mark.parametrize("form", [1, 2])
+def test_encode_long_packet(gf, form):
+    """Packets longer than 2048 strips of 256 bytes: the bit-matrix kernel's running
+    accumulators restart on the way (GF(256), 20 x 9, ragged length)."""
+    torch = torch_cuda()
+    L = 2048 * 256 + 777
+    g = synth.generation(synth.key(16, 8, 1), 8, 9, 20, L)
+    want = oracle.encode(8, g.C, g.S)
+    Cd, Sd = dev(g.C), dev(g.S)
+    Yd = torch.zeros((20, L), dtype=torch.uint8, device="cuda")
+    plan = gf.gf_plan_encode(8, [(Cd, Sd, Yd)], tune={"form": form})
+    gf.gf_encode_batched(plan)
+    torch.cuda.synchronize()
+    got = host(Yd)
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, bad[:5]
+
+
 def test_encode_single_generation_workload(gf):
     """GF(256), 16 packets of 1500 B, 16 x 16 nonzero coefficients; then decode back."""
     torch = torch_cuda()
