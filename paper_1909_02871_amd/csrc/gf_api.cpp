@@ -150,6 +150,7 @@ struct gf_plan {
     int ntiles = 0;
     DevGen *d_gens = nullptr;
     DevTile *d_tiles = nullptr;
+    unsigned *d_runs = nullptr;   // bit-matrix form: first tile of each run
     unsigned *d_ctr = nullptr;
     // decode
     DevSys *d_sys = nullptr;
@@ -390,6 +391,7 @@ static void plan_free_device(gf_plan *p)
         (void)hipStreamDestroy(p->cap);
     (void)hipFree(p->d_gens);
     (void)hipFree(p->d_tiles);
+    (void)hipFree(p->d_runs);
     (void)hipFree(p->d_ctr);
     (void)hipFree(p->d_sys);
     (void)hipFree(p->d_cinv);
@@ -453,26 +455,62 @@ void build_tiles(const DevGen *g, size_t n, int fixed_D, std::vector<DevTile> &o
 
 }  // namespace gfnc
 
-// Workgroup tiles of the bit-matrix form: MF_ROWS coded rows over the whole
-// packet length, longest first.
-static void build_tiles_mfma(const DevGen *g, size_t n, std::vector<DevTile> &out)
+// Bit-matrix tiles: MF_ROWS coded rows of one generation over its whole
+// length, cost ~ source groups x (strips + 1).  Generations go to the
+// MF_QUEUES queues longest first, each to the least loaded queue; inside a
+// queue the tiles run longest first with a generation's tiles adjacent, and
+// consecutive tiles are grouped into runs of cost >= kMfRunCost (one claim
+// each).  runs[r] .. runs[r + 1] are run r's tiles; bounds[i] .. bounds[i + 1]
+// are queue i's runs.
+static const double kMfRunCost = 48.0;
+
+static void build_tiles_mfma(const DevGen *g, size_t n, std::vector<DevTile> &out, std::vector<unsigned> &runs,
+                             unsigned bounds[MF_QUEUES + 1])
 {
-    std::vector<std::pair<DevTile, double>> tiles;
+    struct Gen {
+        uint32_t idx, ntiles;
+        double tile_cost;
+    };
+    std::vector<Gen> gens;
     for (size_t i = 0; i < n; i++) {
         const DevGen &x = g[i];
         if (x.K == 0 || x.len == 0)
             continue;
         const double strips = (double)((x.len + MF_STRIP - 1) / MF_STRIP);
-        for (uint32_t k0 = 0; k0 < x.K; k0 += MF_ROWS)
-            tiles.push_back({DevTile{(uint32_t)i, (uint16_t)k0, 0, 0}, (double)((x.N + 7) / 8) * (strips + 1.0)});
+        gens.push_back({(uint32_t)i, (uint32_t)((x.K + MF_ROWS - 1) / MF_ROWS), (double)((x.N + 7) / 8) * (strips + 1.0)});
     }
-    std::stable_sort(tiles.begin(), tiles.end(),
-                     [](const std::pair<DevTile, double> &a, const std::pair<DevTile, double> &b) {
-                         return a.second > b.second;
-                     });
-    out.resize(tiles.size());
-    for (size_t i = 0; i < tiles.size(); i++)
-        out[i] = tiles[i].first;
+    std::stable_sort(gens.begin(), gens.end(), [](const Gen &a, const Gen &b) {
+        return a.tile_cost * a.ntiles > b.tile_cost * b.ntiles;
+    });
+    std::vector<Gen> queue[MF_QUEUES];
+    double load[MF_QUEUES] = {};
+    for (const Gen &x : gens) {
+        int best = 0;
+        for (int q = 1; q < MF_QUEUES; q++)
+            if (load[q] < load[best])
+                best = q;
+        queue[best].push_back(x);
+        load[best] += x.tile_cost * x.ntiles;
+    }
+    out.clear();
+    runs.clear();
+    for (int q = 0; q < MF_QUEUES; q++) {
+        bounds[q] = (unsigned)runs.size();
+        std::stable_sort(queue[q].begin(), queue[q].end(),
+                         [](const Gen &a, const Gen &b) { return a.tile_cost > b.tile_cost; });
+        double run_cost = 0;
+        for (const Gen &x : queue[q])
+            for (uint32_t t = 0; t < x.ntiles; t++) {
+                if (run_cost == 0)
+                    runs.push_back((unsigned)out.size());
+                out.push_back(DevTile{x.idx, (uint16_t)(t * MF_ROWS), 0, 0});
+                run_cost += x.tile_cost;
+                if (run_cost >= kMfRunCost)
+                    run_cost = 0;
+            }
+    }
+    bounds[MF_QUEUES] = (unsigned)runs.size();
+    runs.push_back((unsigned)out.size());
 }
 
 static int launch_schedule(gf_plan *p, DevState *d, hipStream_t s)
@@ -480,7 +518,7 @@ static int launch_schedule(gf_plan *p, DevState *d, hipStream_t s)
     const int f = p->field;
     hipError_t e;
     if (p->form == 2)
-        e = launch_encode_mfma(p->d_gens, p->d_tiles, p->ntiles, p->d_ctr, p->grid, field_rows(d, f),
+        e = launch_encode_mfma(p->d_gens, p->d_tiles, p->d_runs, p->ntiles, p->d_ctr, p->grid, field_rows(d, f),
                                p->src_aligned4, s);
     else
         e = launch_encode_persistent(p->d_gens, p->d_tiles, p->ntiles, p->d_ctr, p->grid, field_ptab(d, f), s);
@@ -491,10 +529,20 @@ static int launch_schedule(gf_plan *p, DevState *d, hipStream_t s)
 static int make_schedule(gf_plan *p, DevState *d, const std::vector<DevGen> &g, int form, const gf_tuning *tune)
 {
     std::vector<DevTile> tl;
-    if (form == 2)
-        build_tiles_mfma(g.data(), g.size(), tl);
-    else
+    (void)hipFree(p->d_runs);
+    p->d_runs = nullptr;
+    if (form == 2) {
+        unsigned bounds[MF_QUEUES + 1];
+        std::vector<unsigned> runs;
+        build_tiles_mfma(g.data(), g.size(), tl, runs, bounds);
+        if (hipMemcpy(p->d_ctr + MF_CTR_BOUNDS, bounds, sizeof bounds, hipMemcpyHostToDevice) != hipSuccess)
+            return GF_EDEVICE;
+        int rc = upload(&p->d_runs, runs);
+        if (rc)
+            return rc;
+    } else {
         build_tiles(g.data(), g.size(), p->fixed_D, tl);
+    }
     (void)hipFree(p->d_tiles);
     p->d_tiles = nullptr;
     p->form = form;
@@ -555,9 +603,9 @@ static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, co
     }
     if ((rc = upload(&p->d_gens, g)))
         return rc;
-    if (hipMalloc(reinterpret_cast<void **>(&p->d_ctr), 2 * sizeof(unsigned)) != hipSuccess)
+    if (hipMalloc(reinterpret_cast<void **>(&p->d_ctr), GF_PLAN_CTR_WORDS * sizeof(unsigned)) != hipSuccess)
         return GF_ENOMEM;
-    if (hipMemset(p->d_ctr, 0, 2 * sizeof(unsigned)) != hipSuccess)
+    if (hipMemset(p->d_ctr, 0, GF_PLAN_CTR_WORDS * sizeof(unsigned)) != hipSuccess)
         return GF_EDEVICE;
     if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
         return GF_EDEVICE;

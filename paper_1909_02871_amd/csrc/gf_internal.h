@@ -119,9 +119,23 @@ hipError_t launch_encode_persistent(const DevGen *gens, const DevTile *tiles, in
 // MF_STRIP payload bytes (DevTile.D unused).
 constexpr int MF_ROWS = 16;
 constexpr int MF_STRIP = 256;
+// Bit-matrix tiles sit in MF_QUEUES work queues, one per XCD (workgroups are
+// dealt to the 8 XCDs round robin, so workgroup b starts on queue b % 8); all
+// tiles of a generation share a queue so its source stays in one L2.  A
+// workgroup claims a run of consecutive tiles at a time (short tiles are
+// grouped so that claims stay rare).  Counter words, each head on its own
+// 256-byte line: MF_CTR_STRIDE * i for queue i's next run, MF_CTR_STRIDE *
+// MF_QUEUES for the retired workgroups (all of these return to zero at the end
+// of every launch), then MF_QUEUES + 1 queue bounds in runs (constant).
+constexpr int MF_QUEUES = 8;
+constexpr int MF_CTR_STRIDE = 64;
+constexpr int MF_CTR_RETIRED = MF_CTR_STRIDE * MF_QUEUES;
+constexpr int MF_CTR_BOUNDS = MF_CTR_STRIDE * (MF_QUEUES + 1);
+constexpr int GF_PLAN_CTR_WORDS = MF_CTR_BOUNDS + MF_QUEUES + 1;
 // aligned4: every generation's source rows start 4-byte aligned.
-hipError_t launch_encode_mfma(const DevGen *gens, const DevTile *tiles, int ntiles, unsigned *counters, int grid,
-                              const uint8_t *rows_field, bool aligned4, hipStream_t s);
+// runs[r] .. runs[r + 1] are the tiles of run r.
+hipError_t launch_encode_mfma(const DevGen *gens, const DevTile *tiles, const unsigned *runs, int ntiles,
+                              unsigned *counters, int grid, const uint8_t *rows_field, bool aligned4, hipStream_t s);
 int encode_mfma_blocks_per_cu(bool aligned4);
 hipError_t launch_invert(const DevSys *sys, int count, const uint8_t *C, int N, uint8_t *Cinv, int *rank,
                          const uint32_t *ptab_field, const uint8_t *inv_field, hipStream_t s);

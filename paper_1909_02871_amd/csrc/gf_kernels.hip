@@ -724,11 +724,61 @@ __device__ __forceinline__ void mf_tile(const DevGen &g, int k0, int nks, const 
     }
 }
 
+// Next run of bit-matrix tiles for this workgroup (thread 0 only), or -1
+// when every queue is empty: the home queue first, then the others in turn;
+// q counts the queues this workgroup has found empty.
+__device__ __forceinline__ int mf_take_run(unsigned *counters, int &q)
+{
+    const int home = (int)(blockIdx.x % MF_QUEUES);
+    while (q < MF_QUEUES) {
+        const int qi = (home + q) % MF_QUEUES;
+        const unsigned lo = counters[MF_CTR_BOUNDS + qi], hi = counters[MF_CTR_BOUNDS + qi + 1];
+        if (lo < hi) {
+            const unsigned t = atomicAdd(&counters[MF_CTR_STRIDE * qi], 1u);
+            if (t < hi - lo)
+                return (int)(lo + t);
+        }
+        q++;
+    }
+    return -1;
+}
+
+// The last workgroup to finish returns the queue heads and its own counter to zero.
+__device__ __forceinline__ void mf_retire(unsigned *counters)
+{
+    __threadfence();
+    if (atomicAdd(&counters[MF_CTR_RETIRED], 1u) == gridDim.x - 1) {
+        for (int i = 0; i < MF_QUEUES; i++)
+            atomicExch(&counters[MF_CTR_STRIDE * i], 0u);
+        atomicExch(&counters[MF_CTR_RETIRED], 0u);
+    }
+}
+
+// Tile cursor of a workgroup: the tiles of its current run, then the next run.
+struct MfCursor {
+    int q = 0;
+    unsigned next = 0, end = 0;
+};
+
+// Next tile index for the workgroup (thread 0 only), or -1 when done.
+__device__ __forceinline__ int mf_next_tile(unsigned *counters, const unsigned *runs, MfCursor &c)
+{
+    while (c.next == c.end) {
+        const int r = mf_take_run(counters, c.q);
+        if (r < 0)
+            return -1;
+        c.next = runs[r];
+        c.end = runs[r + 1];
+    }
+    return (int)c.next++;
+}
+
 // Persistent: each workgroup takes tiles of MF_ROWS coded rows of one
 // generation and runs over the whole packet length in strips of MF_STRIP
 // bytes, so the coefficient-bit operand is built once per tile.
 __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma(const DevGen *__restrict__ gens,
                                                                          const DevTile *__restrict__ tiles,
+                                                                         const unsigned *__restrict__ runs,
                                                                          int ntiles, unsigned *counters,
                                                                          const uint8_t *__restrict__ rows_f)
 {
@@ -748,13 +798,14 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma(const
             for (int v = 0; v < 16; v++)
                 acc[a][b][v] = 0.0f;
 
+    MfCursor cur_run;
     for (;;) {
         if (tid == 0)
-            s_tile = (int)atomicAdd(&counters[0], 1u);
+            s_tile = mf_next_tile(counters, runs, cur_run);
         __syncthreads();
         const int t = s_tile;
         __syncthreads();
-        if (t >= ntiles)
+        if (t < 0)
             break;
         const DevTile tl = tiles[t];
         const DevGen g = gens[tl.gen];
@@ -767,13 +818,8 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma(const
         // exhaust the register file, and byte loads cost little next to the MFMAs
         mf_tile<false>(g, k0, nks, Ybuf, acc, wave, lane);
     }
-    if (tid == 0) {
-        __threadfence();
-        if (atomicAdd(&counters[1], 1u) == gridDim.x - 1) {
-            atomicExch(&counters[0], 0u);
-            atomicExch(&counters[1], 0u);
-        }
-    }
+    if (tid == 0)
+        mf_retire(counters);
 }
 
 // Variant for sources whose row starts are 4-byte aligned: each wave copies
@@ -834,6 +880,7 @@ __device__ __forceinline__ void mf_acc_reset(gf_v16f (&acc)[4][2])
 
 __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(const DevGen *__restrict__ gens,
                                                                              const DevTile *__restrict__ tiles,
+                                                                             const unsigned *__restrict__ runs,
                                                                              int ntiles, unsigned *counters,
                                                                              const uint8_t *__restrict__ rows_f)
 {
@@ -849,13 +896,14 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
         TR[i] = coef_byte_order(rows_f[i]);
     gf_v16f acc[4][2];
 
+    MfCursor cur_run;
     for (;;) {
         if (tid == 0)
-            s_tile = (int)atomicAdd(&counters[0], 1u);
+            s_tile = mf_next_tile(counters, runs, cur_run);
         __syncthreads();
         const int t = s_tile;
         __syncthreads();
-        if (t >= ntiles)
+        if (t < 0)
             break;
         const DevTile tl = tiles[t];
         const DevGen g = gens[tl.gen];
@@ -974,13 +1022,8 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
         __builtin_amdgcn_s_waitcnt(kWaitAll);
         __syncthreads();   // every wave is done with Cl and Ybuf before the next tile
     }
-    if (tid == 0) {
-        __threadfence();
-        if (atomicAdd(&counters[1], 1u) == gridDim.x - 1) {
-            atomicExch(&counters[0], 0u);
-            atomicExch(&counters[1], 0u);
-        }
-    }
+    if (tid == 0)
+        mf_retire(counters);
 }
 
 // ------------------------------------------------------------------ invert
@@ -1464,15 +1507,17 @@ hipError_t launch_status_gather(int *const *metas, int n, int4 *out, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_encode_mfma(const DevGen *gens, const DevTile *tiles, int ntiles, unsigned *counters, int grid,
-                              const uint8_t *rows_field, bool aligned4, hipStream_t s)
+hipError_t launch_encode_mfma(const DevGen *gens, const DevTile *tiles, const unsigned *runs, int ntiles,
+                              unsigned *counters, int grid, const uint8_t *rows_field, bool aligned4, hipStream_t s)
 {
     if (ntiles <= 0)
         return hipSuccess;
     if (aligned4)
-        hipLaunchKernelGGL(k_encode_mfma_dma, dim3(grid), dim3(256), 0, s, gens, tiles, ntiles, counters, rows_field);
+        hipLaunchKernelGGL(k_encode_mfma_dma, dim3(grid), dim3(256), 0, s, gens, tiles, runs, ntiles, counters,
+                           rows_field);
     else
-        hipLaunchKernelGGL(k_encode_mfma, dim3(grid), dim3(256), 0, s, gens, tiles, ntiles, counters, rows_field);
+        hipLaunchKernelGGL(k_encode_mfma, dim3(grid), dim3(256), 0, s, gens, tiles, runs, ntiles, counters,
+                           rows_field);
     return hipGetLastError();
 }
 
