@@ -150,7 +150,8 @@ struct gf_plan {
     int ntiles = 0;
     DevGen *d_gens = nullptr;
     DevTile *d_tiles = nullptr;
-    unsigned *d_runs = nullptr;   // bit-matrix form: first tile of each run
+    unsigned *d_runs = nullptr;     // first tile of each run, then the queue bounds
+    unsigned *d_bounds = nullptr;   // inside d_runs
     unsigned *d_ctr = nullptr;
     // decode
     DevSys *d_sys = nullptr;
@@ -437,119 +438,118 @@ static void gen_tiles(uint32_t gi, const DevGen &x, int fixed_D, std::vector<std
     }
 }
 
-// Tiles of every generation, longest first (LPT order); ties keep a
-// generation's tiles together.
-void build_tiles(const DevGen *g, size_t n, int fixed_D, std::vector<DevTile> &out)
+// Work queues from the tiles of every generation (each generation's tiles
+// contiguous in `tiles`, with a cost each): generations go to the MF_QUEUES
+// queues largest first, each to the least loaded one; inside a queue the
+// tiles run longest first (LPT order; ties keep a generation's tiles
+// together), and consecutive tiles are grouped into runs of cost >= run_cost.
+static void build_queues(const std::vector<std::pair<DevTile, double>> &tiles, double run_cost, TileQueues &q)
+{
+    struct Span {
+        size_t first, count;
+        double cost;
+    };
+    std::vector<Span> gens;
+    for (size_t i = 0; i < tiles.size(); i++) {
+        if (gens.empty() || tiles[i].first.gen != tiles[gens.back().first].first.gen)
+            gens.push_back({i, 0, 0.0});
+        gens.back().count++;
+        gens.back().cost += tiles[i].second;
+    }
+    std::stable_sort(gens.begin(), gens.end(), [](const Span &a, const Span &b) { return a.cost > b.cost; });
+    std::vector<size_t> member[MF_QUEUES];
+    double load[MF_QUEUES] = {};
+    for (const Span &x : gens) {
+        int best = 0;
+        for (int i = 1; i < MF_QUEUES; i++)
+            if (load[i] < load[best])
+                best = i;
+        for (size_t k = 0; k < x.count; k++)
+            member[best].push_back(x.first + k);
+        load[best] += x.cost;
+    }
+    q.tiles.clear();
+    q.runs.clear();
+    for (int i = 0; i < MF_QUEUES; i++) {
+        q.bounds[i] = (unsigned)q.runs.size();
+        std::stable_sort(member[i].begin(), member[i].end(),
+                         [&](size_t a, size_t b) { return tiles[a].second > tiles[b].second; });
+        double acc = 0;
+        for (size_t k : member[i]) {
+            if (acc == 0)
+                q.runs.push_back((unsigned)q.tiles.size());
+            q.tiles.push_back(tiles[k].first);
+            acc += tiles[k].second;
+            if (acc >= run_cost)
+                acc = 0;
+        }
+    }
+    q.bounds[MF_QUEUES] = (unsigned)q.runs.size();
+    q.runs.push_back((unsigned)q.tiles.size());
+}
+
+// Table form; a tile's cost is its byte products, and runs hold >= 2^18.
+void build_tiles(const DevGen *g, size_t n, int fixed_D, TileQueues &q)
 {
     std::vector<std::pair<DevTile, double>> tiles;
     for (size_t i = 0; i < n; i++)
         gen_tiles((uint32_t)i, g[i], fixed_D, tiles);
-    std::stable_sort(tiles.begin(), tiles.end(),
-                     [](const std::pair<DevTile, double> &a, const std::pair<DevTile, double> &b) {
-                         return a.second > b.second;
-                     });
-    out.resize(tiles.size());
-    for (size_t i = 0; i < tiles.size(); i++)
-        out[i] = tiles[i].first;
+    build_queues(tiles, 262144.0, q);
 }
 
-}  // namespace gfnc
-
-// Bit-matrix tiles: MF_ROWS coded rows of one generation over its whole
-// length, cost ~ source groups x (strips + 1).  Generations go to the
-// MF_QUEUES queues longest first, each to the least loaded queue; inside a
-// queue the tiles run longest first with a generation's tiles adjacent, and
-// consecutive tiles are grouped into runs of cost >= kMfRunCost (one claim
-// each).  runs[r] .. runs[r + 1] are run r's tiles; bounds[i] .. bounds[i + 1]
-// are queue i's runs.
-static const double kMfRunCost = 48.0;
-
-static void build_tiles_mfma(const DevGen *g, size_t n, std::vector<DevTile> &out, std::vector<unsigned> &runs,
-                             unsigned bounds[MF_QUEUES + 1])
+// Bit-matrix form: one tile per MF_ROWS coded rows, cost ~ source groups x
+// (strips + 1); runs hold >= 48.
+void build_tiles_mfma(const DevGen *g, size_t n, TileQueues &q)
 {
-    struct Gen {
-        uint32_t idx, ntiles;
-        double tile_cost;
-    };
-    std::vector<Gen> gens;
+    std::vector<std::pair<DevTile, double>> tiles;
     for (size_t i = 0; i < n; i++) {
         const DevGen &x = g[i];
         if (x.K == 0 || x.len == 0)
             continue;
         const double strips = (double)((x.len + MF_STRIP - 1) / MF_STRIP);
-        gens.push_back({(uint32_t)i, (uint32_t)((x.K + MF_ROWS - 1) / MF_ROWS), (double)((x.N + 7) / 8) * (strips + 1.0)});
+        for (uint32_t k0 = 0; k0 < x.K; k0 += MF_ROWS)
+            tiles.push_back({DevTile{(uint32_t)i, (uint16_t)k0, 0, 0}, (double)((x.N + 7) / 8) * (strips + 1.0)});
     }
-    std::stable_sort(gens.begin(), gens.end(), [](const Gen &a, const Gen &b) {
-        return a.tile_cost * a.ntiles > b.tile_cost * b.ntiles;
-    });
-    std::vector<Gen> queue[MF_QUEUES];
-    double load[MF_QUEUES] = {};
-    for (const Gen &x : gens) {
-        int best = 0;
-        for (int q = 1; q < MF_QUEUES; q++)
-            if (load[q] < load[best])
-                best = q;
-        queue[best].push_back(x);
-        load[best] += x.tile_cost * x.ntiles;
-    }
-    out.clear();
-    runs.clear();
-    for (int q = 0; q < MF_QUEUES; q++) {
-        bounds[q] = (unsigned)runs.size();
-        std::stable_sort(queue[q].begin(), queue[q].end(),
-                         [](const Gen &a, const Gen &b) { return a.tile_cost > b.tile_cost; });
-        double run_cost = 0;
-        for (const Gen &x : queue[q])
-            for (uint32_t t = 0; t < x.ntiles; t++) {
-                if (run_cost == 0)
-                    runs.push_back((unsigned)out.size());
-                out.push_back(DevTile{x.idx, (uint16_t)(t * MF_ROWS), 0, 0});
-                run_cost += x.tile_cost;
-                if (run_cost >= kMfRunCost)
-                    run_cost = 0;
-            }
-    }
-    bounds[MF_QUEUES] = (unsigned)runs.size();
-    runs.push_back((unsigned)out.size());
+    build_queues(tiles, 48.0, q);
 }
+
+}  // namespace gfnc
 
 static int launch_schedule(gf_plan *p, DevState *d, hipStream_t s)
 {
     const int f = p->field;
     hipError_t e;
     if (p->form == 2)
-        e = launch_encode_mfma(p->d_gens, p->d_tiles, p->d_runs, p->ntiles, p->d_ctr, p->grid, field_rows(d, f),
-                               p->src_aligned4, s);
+        e = launch_encode_mfma(p->d_gens, p->d_tiles, p->d_runs, p->d_bounds, p->ntiles, p->d_ctr, p->grid,
+                               field_rows(d, f), p->src_aligned4, s);
     else
-        e = launch_encode_persistent(p->d_gens, p->d_tiles, p->ntiles, p->d_ctr, p->grid, field_ptab(d, f), s);
+        e = launch_encode_persistent(p->d_gens, p->d_tiles, p->d_runs, p->d_bounds, p->ntiles, p->d_ctr, p->grid,
+                                     field_ptab(d, f), s);
     return dev_err(e);
 }
 
 // Tile list, grid and device copies for one form.
 static int make_schedule(gf_plan *p, DevState *d, const std::vector<DevGen> &g, int form, const gf_tuning *tune)
 {
-    std::vector<DevTile> tl;
-    (void)hipFree(p->d_runs);
-    p->d_runs = nullptr;
-    if (form == 2) {
-        unsigned bounds[MF_QUEUES + 1];
-        std::vector<unsigned> runs;
-        build_tiles_mfma(g.data(), g.size(), tl, runs, bounds);
-        if (hipMemcpy(p->d_ctr + MF_CTR_BOUNDS, bounds, sizeof bounds, hipMemcpyHostToDevice) != hipSuccess)
-            return GF_EDEVICE;
-        int rc = upload(&p->d_runs, runs);
-        if (rc)
-            return rc;
-    } else {
-        build_tiles(g.data(), g.size(), p->fixed_D, tl);
-    }
+    TileQueues tq;
+    if (form == 2)
+        build_tiles_mfma(g.data(), g.size(), tq);
+    else
+        build_tiles(g.data(), g.size(), p->fixed_D, tq);
     (void)hipFree(p->d_tiles);
+    (void)hipFree(p->d_runs);
     p->d_tiles = nullptr;
+    p->d_runs = p->d_bounds = nullptr;
     p->form = form;
-    p->ntiles = (int)tl.size();
-    int rc = upload(&p->d_tiles, tl);
+    p->ntiles = (int)tq.tiles.size();
+    std::vector<unsigned> rb = tq.runs;   // runs, then the queue bounds
+    rb.insert(rb.end(), tq.bounds, tq.bounds + MF_QUEUES + 1);
+    int rc = upload(&p->d_tiles, tq.tiles);
+    if (!rc)
+        rc = upload(&p->d_runs, rb);
     if (rc)
         return rc;
+    p->d_bounds = p->d_runs + tq.runs.size();
     int grid = d->cus * (form == 2 ? encode_mfma_blocks_per_cu(p->src_aligned4) : encode_blocks_per_cu());
     if (tune && tune->grid_blocks > 0)
         grid = tune->grid_blocks;
@@ -603,9 +603,9 @@ static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, co
     }
     if ((rc = upload(&p->d_gens, g)))
         return rc;
-    if (hipMalloc(reinterpret_cast<void **>(&p->d_ctr), GF_PLAN_CTR_WORDS * sizeof(unsigned)) != hipSuccess)
+    if (hipMalloc(reinterpret_cast<void **>(&p->d_ctr), GF_QUEUE_CTR_WORDS * sizeof(unsigned)) != hipSuccess)
         return GF_ENOMEM;
-    if (hipMemset(p->d_ctr, 0, GF_PLAN_CTR_WORDS * sizeof(unsigned)) != hipSuccess)
+    if (hipMemset(p->d_ctr, 0, GF_QUEUE_CTR_WORDS * sizeof(unsigned)) != hipSuccess)
         return GF_EDEVICE;
     if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
         return GF_EDEVICE;

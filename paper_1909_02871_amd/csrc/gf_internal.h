@@ -113,29 +113,41 @@ hipError_t launch_region_batched(const void *d_regions, int count, uint64_t max_
 hipError_t launch_encode(int D, int nsplit, const uint8_t *C, int K, int N, const uint8_t *S, uint64_t ld_s,
                          uint8_t *Y, uint64_t ld_y, uint64_t len, const uint32_t *ptab_field, const int *status,
                          int need, bool aligned, hipStream_t s);
-hipError_t launch_encode_persistent(const DevGen *gens, const DevTile *tiles, int ntiles, unsigned *counters,
-                                    int grid, const uint32_t *ptab_field, hipStream_t s);
-// Bit-matrix form on the matrix cores: workgroup tiles of MF_ROWS coded rows x
-// MF_STRIP payload bytes (DevTile.D unused).
-constexpr int MF_ROWS = 16;
-constexpr int MF_STRIP = 256;
-// Bit-matrix tiles sit in MF_QUEUES work queues, one per XCD (workgroups are
-// dealt to the 8 XCDs round robin, so workgroup b starts on queue b % 8); all
-// tiles of a generation share a queue so its source stays in one L2.  A
-// workgroup claims a run of consecutive tiles at a time (short tiles are
-// grouped so that claims stay rare).  Counter words, each head on its own
-// 256-byte line: MF_CTR_STRIDE * i for queue i's next run, MF_CTR_STRIDE *
-// MF_QUEUES for the retired workgroups (all of these return to zero at the end
-// of every launch), then MF_QUEUES + 1 queue bounds in runs (constant).
+// Work queues of the persistent encode kernels.  Tiles sit in MF_QUEUES
+// queues, one per XCD (workgroups are dealt to the 8 XCDs round robin, so
+// workgroup b starts on queue b % 8 and moves on to the others when it is
+// empty); all tiles of a generation share a queue, so its source stays in one
+// L2.  A claim takes a run of consecutive tiles (short tiles are grouped, so
+// claims stay rare).  runs[r] .. runs[r + 1] are the tiles of run r and
+// bounds[i] .. bounds[i + 1] the runs of queue i.  Counter words, each on its
+// own 256-byte line: MF_CTR_STRIDE * i, the next run of queue i;
+// MF_CTR_RETIRED, the retired workgroups or waves.  The last to retire sets
+// them all back to zero, so a launch needs no clearing beforehand.
 constexpr int MF_QUEUES = 8;
 constexpr int MF_CTR_STRIDE = 64;
 constexpr int MF_CTR_RETIRED = MF_CTR_STRIDE * MF_QUEUES;
-constexpr int MF_CTR_BOUNDS = MF_CTR_STRIDE * (MF_QUEUES + 1);
-constexpr int GF_PLAN_CTR_WORDS = MF_CTR_BOUNDS + MF_QUEUES + 1;
+constexpr int GF_QUEUE_CTR_WORDS = MF_CTR_RETIRED + 1;
+
+struct TileQueues {
+    std::vector<DevTile> tiles;
+    std::vector<unsigned> runs;      // number of runs + 1 entries
+    unsigned bounds[MF_QUEUES + 1];
+};
+// Table form: wave tiles of ENC_ROWS coded rows x wave_strip(D) bytes.
+void build_tiles(const DevGen *g, size_t n, int fixed_D, TileQueues &q);
+// Bit-matrix form on the matrix cores: workgroup tiles of MF_ROWS coded rows
+// over the whole packet length in strips of MF_STRIP bytes (DevTile.D unused).
+constexpr int MF_ROWS = 16;
+constexpr int MF_STRIP = 256;
+void build_tiles_mfma(const DevGen *g, size_t n, TileQueues &q);
+
+hipError_t launch_encode_persistent(const DevGen *gens, const DevTile *tiles, const unsigned *runs,
+                                    const unsigned *bounds, int ntiles, unsigned *counters, int grid,
+                                    const uint32_t *ptab_field, hipStream_t s);
 // aligned4: every generation's source rows start 4-byte aligned.
-// runs[r] .. runs[r + 1] are the tiles of run r.
-hipError_t launch_encode_mfma(const DevGen *gens, const DevTile *tiles, const unsigned *runs, int ntiles,
-                              unsigned *counters, int grid, const uint8_t *rows_field, bool aligned4, hipStream_t s);
+hipError_t launch_encode_mfma(const DevGen *gens, const DevTile *tiles, const unsigned *runs, const unsigned *bounds,
+                              int ntiles, unsigned *counters, int grid, const uint8_t *rows_field, bool aligned4,
+                              hipStream_t s);
 int encode_mfma_blocks_per_cu(bool aligned4);
 hipError_t launch_invert(const DevSys *sys, int count, const uint8_t *C, int N, uint8_t *Cinv, int *rank,
                          const uint32_t *ptab_field, const uint8_t *inv_field, hipStream_t s);
@@ -144,7 +156,6 @@ uint32_t row_align(const void *S, uint64_t ld_s, const void *Y, uint64_t ld_y);
 // Device tables of `field` on the current device (initialising it if needed).
 int gfnc_field_tables(int field, const uint32_t **ptab, const uint8_t **inv);
 const uint8_t *gfnc_field_rows(int field);
-void build_tiles(const DevGen *g, size_t n, int fixed_D, std::vector<DevTile> &out);
 hipError_t launch_absorb(const DevAbsorb *items, int n, const DevPacket *pkts, const uint32_t *ptab_field,
                          const uint8_t *inv_field, hipStream_t s);
 hipError_t launch_meta_init(int *const *metas, int n, hipStream_t s);

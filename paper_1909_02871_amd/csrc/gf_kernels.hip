@@ -426,22 +426,74 @@ __global__ __launch_bounds__(256) void k_zero_rows(uint8_t *Y, uint64_t ld_y, ui
     }
 }
 
-// Persistent encode over a tile list; every wave takes tiles on its own.
-// counters[0] hands out tiles, counters[1] counts retired waves; the last
-// wave to retire resets both so the next launch (or graph replay) starts
-// from zero without a memset.
+// ---------------------------------------------------------------- work queues
+// (layout of runs, bounds and counters: see TileQueues)
+
+// Next run for a workgroup or wave (one lane calls), or -1 when every queue
+// is empty: the home queue of this workgroup's XCD first, then the others in
+// turn; q counts the queues found empty so far.
+__device__ __forceinline__ int queue_take_run(unsigned *counters, const unsigned *__restrict__ bounds, int &q)
+{
+    const int home = (int)(blockIdx.x % MF_QUEUES);
+    while (q < MF_QUEUES) {
+        const int qi = (home + q) % MF_QUEUES;
+        const unsigned lo = bounds[qi], hi = bounds[qi + 1];
+        if (lo < hi) {
+            const unsigned t = atomicAdd(&counters[MF_CTR_STRIDE * qi], 1u);
+            if (t < hi - lo)
+                return (int)(lo + t);
+        }
+        q++;
+    }
+    return -1;
+}
+
+// Tile cursor of a claimant: the rest of its current run, then the next run.
+struct QueueCursor {
+    int q = 0;
+    unsigned next = 0, end = 0;
+};
+
+__device__ __forceinline__ int queue_next_tile(unsigned *counters, const unsigned *__restrict__ runs,
+                                               const unsigned *__restrict__ bounds, QueueCursor &c)
+{
+    while (c.next == c.end) {
+        const int r = queue_take_run(counters, bounds, c.q);
+        if (r < 0)
+            return -1;
+        c.next = runs[r];
+        c.end = runs[r + 1];
+    }
+    return (int)c.next++;
+}
+
+// The last of `claimants` to finish sets every counter back to zero.
+__device__ __forceinline__ void queue_retire(unsigned *counters, unsigned claimants)
+{
+    __threadfence();
+    if (atomicAdd(&counters[MF_CTR_RETIRED], 1u) == claimants - 1) {
+        for (int i = 0; i < MF_QUEUES; i++)
+            atomicExch(&counters[MF_CTR_STRIDE * i], 0u);
+        atomicExch(&counters[MF_CTR_RETIRED], 0u);
+    }
+}
+
+// Persistent encode over the work queues; every wave claims tiles on its own.
 __global__ __launch_bounds__(256, GF_ENC_WAVES_PER_SIMD) void k_encode_waves(const DevGen *__restrict__ gens,
-                                                      const DevTile *__restrict__ tiles, int ntiles,
-                                                      unsigned *counters, const uint4 *__restrict__ ptab4)
+                                                      const DevTile *__restrict__ tiles,
+                                                      const unsigned *__restrict__ runs,
+                                                      const unsigned *__restrict__ bounds, unsigned *counters,
+                                                      const uint4 *__restrict__ ptab4)
 {
     __shared__ WaveStage stage[WAVES];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    QueueCursor cursor;
     for (;;) {
-        unsigned t = 0;
+        int t = 0;
         if (lane == 0)
-            t = atomicAdd(&counters[0], 1u);
+            t = queue_next_tile(counters, runs, bounds, cursor);
         t = __builtin_amdgcn_readlane(t, 0);
-        if (t >= (unsigned)ntiles)
+        if (t < 0)
             break;
         const DevTile tl = tiles[t];
         const DevGen g = gens[tl.gen];
@@ -457,13 +509,8 @@ __global__ __launch_bounds__(256, GF_ENC_WAVES_PER_SIMD) void k_encode_waves(con
             wave_tile<1>(g.C, (int)g.K, (int)g.N, g.S, g.ld_s, g.Y, g.ld_y, g.len, (int)tl.k0, tl.p0,
                          g.align >= 4, ptab4, stage[wave], lane, 0, (int)g.N, false);
     }
-    if (lane == 0) {
-        __threadfence();
-        if (atomicAdd(&counters[1], 1u) == gridDim.x * WAVES - 1) {
-            atomicExch(&counters[0], 0u);
-            atomicExch(&counters[1], 0u);
-        }
-    }
+    if (lane == 0)
+        queue_retire(counters, gridDim.x * WAVES);
 }
 
 // ------------------------------------------------------- encode, bit-matrix form
@@ -724,62 +771,14 @@ __device__ __forceinline__ void mf_tile(const DevGen &g, int k0, int nks, const 
     }
 }
 
-// Next run of bit-matrix tiles for this workgroup (thread 0 only), or -1
-// when every queue is empty: the home queue first, then the others in turn;
-// q counts the queues this workgroup has found empty.
-__device__ __forceinline__ int mf_take_run(unsigned *counters, int &q)
-{
-    const int home = (int)(blockIdx.x % MF_QUEUES);
-    while (q < MF_QUEUES) {
-        const int qi = (home + q) % MF_QUEUES;
-        const unsigned lo = counters[MF_CTR_BOUNDS + qi], hi = counters[MF_CTR_BOUNDS + qi + 1];
-        if (lo < hi) {
-            const unsigned t = atomicAdd(&counters[MF_CTR_STRIDE * qi], 1u);
-            if (t < hi - lo)
-                return (int)(lo + t);
-        }
-        q++;
-    }
-    return -1;
-}
-
-// The last workgroup to finish returns the queue heads and its own counter to zero.
-__device__ __forceinline__ void mf_retire(unsigned *counters)
-{
-    __threadfence();
-    if (atomicAdd(&counters[MF_CTR_RETIRED], 1u) == gridDim.x - 1) {
-        for (int i = 0; i < MF_QUEUES; i++)
-            atomicExch(&counters[MF_CTR_STRIDE * i], 0u);
-        atomicExch(&counters[MF_CTR_RETIRED], 0u);
-    }
-}
-
-// Tile cursor of a workgroup: the tiles of its current run, then the next run.
-struct MfCursor {
-    int q = 0;
-    unsigned next = 0, end = 0;
-};
-
-// Next tile index for the workgroup (thread 0 only), or -1 when done.
-__device__ __forceinline__ int mf_next_tile(unsigned *counters, const unsigned *runs, MfCursor &c)
-{
-    while (c.next == c.end) {
-        const int r = mf_take_run(counters, c.q);
-        if (r < 0)
-            return -1;
-        c.next = runs[r];
-        c.end = runs[r + 1];
-    }
-    return (int)c.next++;
-}
-
 // Persistent: each workgroup takes tiles of MF_ROWS coded rows of one
 // generation and runs over the whole packet length in strips of MF_STRIP
 // bytes, so the coefficient-bit operand is built once per tile.
 __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma(const DevGen *__restrict__ gens,
                                                                          const DevTile *__restrict__ tiles,
                                                                          const unsigned *__restrict__ runs,
-                                                                         int ntiles, unsigned *counters,
+                                                                         const unsigned *__restrict__ bounds,
+                                                                         unsigned *counters,
                                                                          const uint8_t *__restrict__ rows_f)
 {
     __shared__ uint8_t TR[256 * 8];
@@ -798,10 +797,10 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma(const
             for (int v = 0; v < 16; v++)
                 acc[a][b][v] = 0.0f;
 
-    MfCursor cur_run;
+    QueueCursor cursor;
     for (;;) {
         if (tid == 0)
-            s_tile = mf_next_tile(counters, runs, cur_run);
+            s_tile = queue_next_tile(counters, runs, bounds, cursor);
         __syncthreads();
         const int t = s_tile;
         __syncthreads();
@@ -819,7 +818,7 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma(const
         mf_tile<false>(g, k0, nks, Ybuf, acc, wave, lane);
     }
     if (tid == 0)
-        mf_retire(counters);
+        queue_retire(counters, gridDim.x);
 }
 
 // Variant for sources whose row starts are 4-byte aligned: each wave copies
@@ -881,7 +880,8 @@ __device__ __forceinline__ void mf_acc_reset(gf_v16f (&acc)[4][2])
 __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(const DevGen *__restrict__ gens,
                                                                              const DevTile *__restrict__ tiles,
                                                                              const unsigned *__restrict__ runs,
-                                                                             int ntiles, unsigned *counters,
+                                                                             const unsigned *__restrict__ bounds,
+                                                                             unsigned *counters,
                                                                              const uint8_t *__restrict__ rows_f)
 {
     __shared__ uint8_t TR[256 * 8];
@@ -896,10 +896,10 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
         TR[i] = coef_byte_order(rows_f[i]);
     gf_v16f acc[4][2];
 
-    MfCursor cur_run;
+    QueueCursor cursor;
     for (;;) {
         if (tid == 0)
-            s_tile = mf_next_tile(counters, runs, cur_run);
+            s_tile = queue_next_tile(counters, runs, bounds, cursor);
         __syncthreads();
         const int t = s_tile;
         __syncthreads();
@@ -1023,7 +1023,7 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
         __syncthreads();   // every wave is done with Cl and Ybuf before the next tile
     }
     if (tid == 0)
-        mf_retire(counters);
+        queue_retire(counters, gridDim.x);
 }
 
 // ------------------------------------------------------------------ invert
@@ -1436,12 +1436,13 @@ hipError_t launch_encode(int D, int nsplit, const uint8_t *C, int K, int N, cons
     return hipGetLastError();
 }
 
-hipError_t launch_encode_persistent(const DevGen *gens, const DevTile *tiles, int ntiles, unsigned *counters,
-                                    int grid, const uint32_t *ptab_field, hipStream_t s)
+hipError_t launch_encode_persistent(const DevGen *gens, const DevTile *tiles, const unsigned *runs,
+                                    const unsigned *bounds, int ntiles, unsigned *counters, int grid,
+                                    const uint32_t *ptab_field, hipStream_t s)
 {
     if (ntiles <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_encode_waves, dim3(grid), dim3(256), 0, s, gens, tiles, ntiles, counters,
+    hipLaunchKernelGGL(k_encode_waves, dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters,
                        reinterpret_cast<const uint4 *>(ptab_field));
     return hipGetLastError();
 }
@@ -1507,16 +1508,17 @@ hipError_t launch_status_gather(int *const *metas, int n, int4 *out, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_encode_mfma(const DevGen *gens, const DevTile *tiles, const unsigned *runs, int ntiles,
-                              unsigned *counters, int grid, const uint8_t *rows_field, bool aligned4, hipStream_t s)
+hipError_t launch_encode_mfma(const DevGen *gens, const DevTile *tiles, const unsigned *runs, const unsigned *bounds,
+                              int ntiles, unsigned *counters, int grid, const uint8_t *rows_field, bool aligned4,
+                              hipStream_t s)
 {
     if (ntiles <= 0)
         return hipSuccess;
     if (aligned4)
-        hipLaunchKernelGGL(k_encode_mfma_dma, dim3(grid), dim3(256), 0, s, gens, tiles, runs, ntiles, counters,
+        hipLaunchKernelGGL(k_encode_mfma_dma, dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters,
                            rows_field);
     else
-        hipLaunchKernelGGL(k_encode_mfma, dim3(grid), dim3(256), 0, s, gens, tiles, runs, ntiles, counters,
+        hipLaunchKernelGGL(k_encode_mfma, dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters,
                            rows_field);
     return hipGetLastError();
 }

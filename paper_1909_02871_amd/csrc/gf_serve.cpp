@@ -341,8 +341,8 @@ int gf_serve_create(const gf_serve_config *cfg, gf_server **out)
         delete sv;
         return GF_ENOMEM;
     }
-    if (hipMalloc(reinterpret_cast<void **>(&sv->ctr), 2 * sizeof(unsigned)) != hipSuccess ||
-        hipMemset(sv->ctr, 0, 2 * sizeof(unsigned)) != hipSuccess ||
+    if (hipMalloc(reinterpret_cast<void **>(&sv->ctr), GF_QUEUE_CTR_WORDS * sizeof(unsigned)) != hipSuccess ||
+        hipMemset(sv->ctr, 0, GF_QUEUE_CTR_WORDS * sizeof(unsigned)) != hipSuccess ||
         hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking) != hipSuccess) {
         gf_serve_destroy(sv);
         return GF_EDEVICE;
@@ -557,8 +557,11 @@ int gf_serve_step(gf_server *sv, double now)
 
     for (DevGen &g : gens)
         g.align = row_align(g.S, g.N > 1 ? g.ld_s : 0, g.Y, g.K > 1 ? g.ld_y : 0);
-    std::vector<DevTile> tiles;
-    build_tiles(gens.data(), gens.size(), 0, tiles);
+    TileQueues tq;
+    build_tiles(gens.data(), gens.size(), 0, tq);
+    const std::vector<DevTile> &tiles = tq.tiles;
+    std::vector<unsigned> rb = tq.runs;   // runs, then the queue bounds
+    rb.insert(rb.end(), tq.bounds, tq.bounds + MF_QUEUES + 1);
     sv->st.steps++;
     sv->st.encode_tiles += tiles.size();
     sv->st.absorb_items += absorb.size();
@@ -572,7 +575,8 @@ int gf_serve_step(gf_server *sv, double now)
         const size_t o_pk = align16(o_abs + absorb.size() * sizeof(DevAbsorb));
         const size_t o_gen = align16(o_pk + pk.size() * sizeof(DevPacket));
         const size_t o_tile = align16(o_gen + gens.size() * sizeof(DevGen));
-        const size_t o_init = align16(o_tile + tiles.size() * sizeof(DevTile));
+        const size_t o_runs = align16(o_tile + tiles.size() * sizeof(DevTile));
+        const size_t o_init = align16(o_runs + rb.size() * sizeof(unsigned));
         const size_t o_stat = align16(o_init + init_meta.size() * sizeof(int *));
         const size_t total = align16(o_stat + status_meta.size() * sizeof(int *));
         // the buffer of this ring slot was last used kInflight + 1 steps ago; that step has retired
@@ -582,6 +586,7 @@ int gf_serve_step(gf_server *sv, double now)
         memcpy(b.host + o_pk, pk.data(), pk.size() * sizeof(DevPacket));
         memcpy(b.host + o_gen, gens.data(), gens.size() * sizeof(DevGen));
         memcpy(b.host + o_tile, tiles.data(), tiles.size() * sizeof(DevTile));
+        memcpy(b.host + o_runs, rb.data(), rb.size() * sizeof(unsigned));
         memcpy(b.host + o_init, init_meta.data(), init_meta.size() * sizeof(int *));
         memcpy(b.host + o_stat, status_meta.data(), status_meta.size() * sizeof(int *));
         hipStream_t s = sv->stream;
@@ -593,9 +598,10 @@ int gf_serve_step(gf_server *sv, double now)
                               reinterpret_cast<const DevPacket *>(b.dev + o_pk), sv->ptab, sv->inv, s);
         if (e == hipSuccess && !tiles.empty()) {
             const int grid = std::max(1, std::min<int>(sv->grid_max, ((int)tiles.size() + 3) / 4));
+            const unsigned *runs = reinterpret_cast<const unsigned *>(b.dev + o_runs);
             e = launch_encode_persistent(reinterpret_cast<const DevGen *>(b.dev + o_gen),
-                                         reinterpret_cast<const DevTile *>(b.dev + o_tile), (int)tiles.size(),
-                                         sv->ctr, grid, sv->ptab, s);
+                                         reinterpret_cast<const DevTile *>(b.dev + o_tile), runs,
+                                         runs + tq.runs.size(), (int)tiles.size(), sv->ctr, grid, sv->ptab, s);
         }
         if (e == hipSuccess && !status_meta.empty()) {
             e = launch_status_gather(reinterpret_cast<int *const *>(b.dev + o_stat), (int)status_meta.size(),
