@@ -519,14 +519,17 @@ __global__ __launch_bounds__(256, GF_ENC_WAVES_PER_SIMD) void k_encode_waves(con
 // 8 x 8 bit matrix M_c, so a generation's encode is one GF(2) matrix product:
 // (8K x 8N coefficient bits) x (8N x L source bits), each output bit the parity
 // of a dot product of 0/1 values.  The matrix cores compute those dot products
-// exactly: operands are FP4 (E2M1) values 0 or 1.0, accumulation is FP32
-// (counts <= 8N <= 2048 are exact), and the parity is the count's lowest bit.
+// exactly: both operands are FP4 (E2M1) nibbles whose products are 0 or 1
+// (fp4_source, fp4_coef), accumulation is FP32 from a bias of 2^23 (counts are
+// exact integers in the low mantissa bits), and the parity is the lowest bit.
+// The MFMA is the plain FP4 x FP4 form: zero scale arguments select the
+// unscaled instruction.
 //
 // One MFMA 32x32x64: rows = 32 output bits (4 coded packets x 8 bits), columns
 // = 32 payload bytes, reduction = 64 input bits (8 source packets x 8 bits).
-// A workgroup tile is 16 coded packets (4 row tiles) x 256 payload bytes; wave
-// w covers 64 bytes (2 column tiles) and builds row tile w's operand for the
-// whole workgroup in LDS each step.
+// A workgroup tile is 16 coded packets (4 row tiles) over the whole packet in
+// strips of 256 payload bytes; wave w covers 64 bytes of a strip (2 column
+// tiles).  The coefficient operand of every step is built once per tile in LDS.
 
 typedef int gf_v8i __attribute__((ext_vector_type(8)));
 typedef float gf_v16f __attribute__((ext_vector_type(16)));
@@ -707,15 +710,15 @@ __device__ __forceinline__ void mf_step(const uint32_t (*Ybuf)[4][64], int ks, i
 #pragma unroll
         for (int rt = 0; rt < 4; rt++) {
             const gf_v8i a = fp4_coef(Ybuf[ks][rt][lane]);
-            acc[rt][0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b0, bias, 4, 4, 0, 127, 0, 127);
-            acc[rt][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b1, bias, 4, 4, 0, 127, 0, 127);
+            acc[rt][0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b0, bias, 4, 4, 0, 0, 0, 0);
+            acc[rt][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b1, bias, 4, 4, 0, 0, 0, 0);
         }
     } else {
 #pragma unroll
         for (int rt = 0; rt < 4; rt++) {
             const gf_v8i a = fp4_coef(Ybuf[ks][rt][lane]);
-            acc[rt][0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b0, acc[rt][0], 4, 4, 0, 127, 0, 127);
-            acc[rt][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b1, acc[rt][1], 4, 4, 0, 127, 0, 127);
+            acc[rt][0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b0, acc[rt][0], 4, 4, 0, 0, 0, 0);
+            acc[rt][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b1, acc[rt][1], 4, 4, 0, 0, 0, 0);
         }
     }
 }
@@ -859,8 +862,8 @@ __device__ __forceinline__ void mf_mma(const MfOperands &o, gf_v16f (&acc)[4][2]
 {
 #pragma unroll
     for (int rt = 0; rt < 4; rt++) {
-        acc[rt][0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(o.a[rt], o.b[0], acc[rt][0], 4, 4, 0, 127, 0, 127);
-        acc[rt][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(o.a[rt], o.b[1], acc[rt][1], 4, 4, 0, 127, 0, 127);
+        acc[rt][0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(o.a[rt], o.b[0], acc[rt][0], 4, 4, 0, 0, 0, 0);
+        acc[rt][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(o.a[rt], o.b[1], acc[rt][1], 4, 4, 0, 0, 0, 0);
     }
 }
 
