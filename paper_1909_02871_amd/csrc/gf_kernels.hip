@@ -997,20 +997,31 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
         for (int j = 0; j < MF_STAGES - 1; j++)
             copy_step();
         mf_acc_reset(acc);
-        MfOperands cur;
-        fetch(0, 0, cur);
+        // Two operand sets take turns (steps z and z + 1), so no registers are
+        // copied between steps; an odd group count hands over once per strip.
+        MfOperands opa, opb;
+        fetch(0, 0, opa);
         // The accumulators run over all strips of the tile and restart every
         // kMfRestart strips: a strip adds at most 64 nks <= 2048 to a count, so
         // the total stays below 2^23 + 2^22, exact in FP32.
         uint32_t prev[4] = {0u, 0u, 0u, 0u};
         int z = 0;
         for (int strip = 0; strip < nstrips; strip++) {
-            for (int ks = 0; ks < nks; ks++, z++) {
+            int ks = 0;
+            for (; ks + 2 <= nks; ks += 2, z += 2) {
                 copy_step();              // step z + MF_STAGES - 1, into the slot of step z - 1
-                MfOperands nxt;           // the next step: this strip's next group or the next strip's first
-                fetch(z + 1, ks + 1 == nks ? 0 : ks + 1, nxt);   // past the last step: a zero slot, never used
-                mf_mma(cur, acc);         // independent of the fetch: the two interleave
-                cur = nxt;
+                fetch(z + 1, ks + 1, opb);
+                mf_mma(opa, acc);         // independent of the fetch: the two interleave
+                copy_step();
+                fetch(z + 2, ks + 2 == nks ? 0 : ks + 2, opa);   // past the last step: a zero slot, never used
+                mf_mma(opb, acc);
+            }
+            if (ks < nks) {
+                copy_step();
+                fetch(z + 1, 0, opb);
+                mf_mma(opa, acc);
+                opa = opb;
+                z++;
             }
             mf_store<true>(g, k0, (uint64_t)strip * MF_STRIP + (uint64_t)wave * 64u + 2u * (uint64_t)r, acc, h,
                            prev);
