@@ -45,7 +45,10 @@ MFMA_FP4_TFLOPS = 10100.0
 # (calibrated against a 1 GiB copy: fetch x 2.000, write x 1.000), valid only for the kernel
 # source they were taken with (sha256 of csrc/gf_kernels.hip); otherwise reported as null.
 MEASURED_TRAFFIC = {
-    ("14d2e6f58585212c738f649aa0729171021f4fdf89aad0996bab7777c4207171", 1): 8126270 * 1024 * 2.0 + 2409897 * 1024,
+    # kernel source hash, form -> HBM bytes per launch: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB, averages over
+    # the profiled launches; the factors come from a 1 GiB device copy read by the same counters)
+    ("5b6c46f3e081554fda186a6619a2e1b155f98adb2ce7d4692dfd2802413f9ebf", 2): 1453292 * 1024 * 2.0 + 2457752 * 1024,
+    ("5b6c46f3e081554fda186a6619a2e1b155f98adb2ce7d4692dfd2802413f9ebf", 1): 2948703 * 1024 * 2.0 + 2411031 * 1024,
 }
 
 
@@ -203,7 +206,7 @@ def main():
         # against the dense FP4 matrix-core peak
         achieved = 128.0 * madds / (kern_ms * 1e-3) / 1e12
         roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": MFMA_FP4_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / MFMA_FP4_TFLOPS, 4), "kernel": "k_encode_mfma"}
+                    "frac": round(achieved / MFMA_FP4_TFLOPS, 4), "kernel": "k_encode_mfma_dma"}
     else:
         achieved = madds / (kern_ms * 1e-3) / 1e12
         peak = VALU_LANE_OPS / TABLE_OPS_PER_MADD / 1e12
