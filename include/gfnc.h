@@ -147,10 +147,12 @@ typedef struct {
 
 /* Kernel schedule knobs.  Zero fields mean "chosen by the library".
  * form 1: byte-select table lookups on the vector ALUs.
- * form 2: the product as a GF(2) bit-matrix multiply on the matrix cores.
+ * form 2: the product as a GF(2) bit-matrix multiply on the matrix cores;
+ *         packets longer than 2^34 bytes are rejected with GF_ERANGE.
  * form 0 on an encode plan: both forms are timed on the plan's own batch
  * while the plan is created (which writes the plan's outputs) and the faster
- * is kept; on a decode plan form 0 means form 1. */
+ * is kept (form 1 alone if a packet is too long for form 2); on a decode plan
+ * form 0 means form 1. */
 typedef struct {
     int form;           /* 0 auto, 1 table, 2 bit-matrix */
     int bytes_per_lane; /* 0 = per tile; else 4, 8 or 16 payload bytes per lane everywhere */

@@ -596,7 +596,10 @@ static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, co
         return GF_EINVAL;
     std::vector<DevGen> g = gens;
     p->src_aligned4 = true;
+    bool mf_ok = true;   // the bit-matrix kernels count a tile's steps in 32 bits
     for (DevGen &x : g) {
+        if (x.len > (1ull << 34))
+            mf_ok = false;
         x.align = row_align(x.S, x.N > 1 ? x.ld_s : 0, x.Y, x.K > 1 ? x.ld_y : 0);
         if ((((uintptr_t)x.S) | (x.N > 1 ? x.ld_s : 0)) % 4 != 0)
             p->src_aligned4 = false;
@@ -611,7 +614,9 @@ static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, co
         return GF_EDEVICE;
     if (hipDeviceSynchronize() != hipSuccess)
         return GF_EDEVICE;
-    if (form == 0 && !may_run)
+    if (form == 2 && !mf_ok)
+        return GF_ERANGE;
+    if (form == 0 && (!may_run || !mf_ok))
         form = 1;
     if (form != 0)
         return make_schedule(p, d, g, form, tune);

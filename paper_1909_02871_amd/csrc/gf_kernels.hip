@@ -17,6 +17,7 @@
 // the per-(row, source) tables are staged in LDS and read with wave-uniform
 // addresses (broadcast, no bank conflicts).
 #include <algorithm>
+#include <type_traits>
 
 #include "gf_internal.h"
 
@@ -836,18 +837,25 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma(const
 #endif
 constexpr int MF_STAGES = GF_MF_STAGES;
 static_assert((MF_STAGES & (MF_STAGES - 1)) == 0 && MF_STAGES >= 2, "stages: a power of two");
-// Every copy step issues exactly two copy instructions (past the tile's last
-// step they copy a zero word into a slot that is no longer read), so when the
-// operands of step z are read, the copies of steps z + 1 .. z + MF_STAGES - 2
-// are the only newer vector-memory loads: s_waitcnt vmcnt(2 (MF_STAGES - 2)),
-// in the gfx9 encoding (vmcnt in bits 3:0 and 15:14; expcnt and lgkmcnt at
-// their maxima, i.e. not waited for).  Stores issued in between only make the
-// wait stricter: loads complete in order, so the count cannot drop that low
-// while the awaited copy is outstanding.
-constexpr int kWaitVm = 2 * (MF_STAGES - 2);
-constexpr int kWaitCopies = (kWaitVm & 0xF) | ((kWaitVm >> 4) << 14) | (0x7 << 4) | (0xF << 8);
-constexpr int kWaitAll = (0x7 << 4) | (0xF << 8);
-static_assert(kWaitVm < 64, "vmcnt field is 6 bits");
+// Steps come in pairs (two source groups of the same strip; a generation with
+// an odd group count gets one zero group per strip), and a pair's sources are
+// copied by four copy instructions, MF_PAIRS_AHEAD pairs ahead of the reads.
+// A copy then only ever overwrites the slots of the previous pair, whose
+// operands are in registers and used.  Every pair issues exactly four copies
+// (past the tile's last step they copy a zero word), so when a step's operands
+// are read the number of newer vector-memory loads in flight is known and one
+// s_waitcnt vmcnt(n) is exact; in the gfx9 encoding vmcnt is bits 3:0 and 15:14,
+// expcnt and lgkmcnt stay at their maxima (not waited for).  Stores issued in
+// between only make a wait stricter: loads complete in order, so the count
+// cannot drop that low while the awaited copy is pending.
+constexpr int MF_PAIRS_AHEAD = MF_STAGES / 2 - 1;
+static_assert(MF_PAIRS_AHEAD >= 1, "at least 4 stages");
+constexpr int vm_wait(int newer_loads)
+{
+    return (newer_loads & 0xF) | ((newer_loads >> 4) << 14) | (0x7 << 4) | (0xF << 8);
+}
+constexpr int kWaitAll = vm_wait(0);
+static_assert(4 * MF_PAIRS_AHEAD < 64, "vmcnt field is 6 bits");
 
 typedef unsigned short gf_u16x2 __attribute__((ext_vector_type(2)));
 
@@ -868,6 +876,19 @@ __device__ __forceinline__ void mf_mma(const MfOperands &o, gf_v16f (&acc)[4][2]
 }
 
 constexpr int kMfRestart = 2048;
+
+// Instruction order for a step's products and the unpacking of the next
+// step's operands (whose LDS reads are already issued): two MFMAs while the
+// reads are in flight, then the unpacking spread between the remaining six.
+__device__ __forceinline__ void mf_step_schedule()
+{
+    __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);   // MFMA
+#pragma unroll
+    for (int i = 0; i < 6; i++) {
+        __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);   // VALU
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+    }
+}
 
 __device__ __forceinline__ void mf_acc_reset(gf_v16f (&acc)[4][2])
 {
@@ -913,44 +934,45 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
         if (g.status && *g.status != g.need)
             continue;
         const int N = (int)g.N, k0 = (int)tl.k0;
-        const int nks = (N + 7) >> 3;
+        const int npairs = (N + 15) >> 4;       // pairs of 8-packet source groups
+        const int nks = 2 * npairs;
         mf_tile_setup(g, k0, nks, Cl, Ybuf, TR, tid);
         const uint64_t ld = g.ld_s;
         const int nstrips = (int)((g.len + MF_STRIP - 1) / MF_STRIP);
-        const int Z = nstrips * nks;            // the plan keeps this below 2^31
-        // Copies of whole 8-row groups inside whole strips are a wave-uniform
+        const int Zp = nstrips * npairs;        // the plan keeps this below 2^30
+        // Copies of whole 16-row pairs inside whole strips are a wave-uniform
         // base plus a fixed per-lane offset (when the offsets fit 32 bits).
-        const int ks_full = N >> 3;
+        const int kp_full = N >> 4;
         const int strips_full = ld <= (1u << 26) ? (int)(g.len / MF_STRIP) : 0;
         const uint32_t lcol = (uint32_t)wave * 64u + (uint32_t)(lane & 15) * 4u;
         const uint32_t loff = (uint32_t)(lane >> 4) * (uint32_t)ld + lcol;
-        const uint32_t loff4 = loff + 4u * (uint32_t)ld;
-        // Copy cursor: step cz = (strip cs, group ck); lane l copies 4 bytes of
-        // source row 8 ck + l / 16 (+ 4) at byte (l % 16) * 4 of this wave's 64.
-        // Outside the generation or the packet a lane copies a zero word (row 0
-        // of the table, the bit matrix of 0): such bytes meet zero coefficient
-        // bits or are never stored.  A chunk that straddles the packet end is
-        // assembled byte by byte (at most 4 lanes per instruction).
-        int cz = 0, ck = 0, cs = 0;
+        const uint32_t ld4 = 4u * (uint32_t)ld;
+        // Copy cursor: pair cq = (strip cs, pair cp).  Lane l copies 4 bytes of
+        // source rows 16 cp + l / 16 + {0, 4, 8, 12} at byte (l % 16) * 4 of this
+        // wave's 64.  Outside the generation or the packet a lane copies a zero
+        // word (row 0 of the table, the bit matrix of 0): such bytes meet zero
+        // coefficient bits or are never stored.  A chunk that straddles the
+        // packet end is assembled byte by byte (at most 4 lanes per instruction).
+        int cq = 0, cp = 0, cs = 0;
         const uint8_t *cbase = g.S;
-        auto copy_step = [&]() {
-            const int slot = cz & (MF_STAGES - 1);
-            uint32_t *dst0 = &Sw[wave][slot][0][0];
-            uint32_t *dst4 = &Sw[wave][slot][4][0];
-            if (ck < ks_full && cs < strips_full) {
-                __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(cbase + loff),
-                                                 (__attribute__((address_space(3))) void *)dst0, 4, 0, 0);
-                __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(cbase + loff4),
-                                                 (__attribute__((address_space(3))) void *)dst4, 4, 0, 0);
-            } else {
-                const bool live = cz < Z;
-                const uint64_t rem = live ? g.len - (uint64_t)cs * MF_STRIP : 0;
-                const int remrows = live ? N - ck * 8 : 0;
+        auto copy_pair = [&]() {
+            const int slot = (2 * cq) & (MF_STAGES - 1);
+            if (cp < kp_full && cs < strips_full) {
 #pragma unroll
-                for (int half = 0; half < 2; half++) {
-                    const int rr = 4 * half + (lane >> 4);
+                for (int q4 = 0; q4 < 4; q4++)
+                    __builtin_amdgcn_global_load_lds(
+                        reinterpret_cast<const void *>(cbase + loff + (uint32_t)q4 * ld4),
+                        (__attribute__((address_space(3))) void *)&Sw[wave][slot + (q4 >> 1)][4 * (q4 & 1)][0], 4,
+                        0, 0);
+            } else {
+                const bool live = cq < Zp;
+                const uint64_t rem = live ? g.len - (uint64_t)cs * MF_STRIP : 0;
+                const int remrows = live ? N - cp * 16 : 0;
+#pragma unroll
+                for (int q4 = 0; q4 < 4; q4++) {
+                    const int rr = 4 * q4 + (lane >> 4);
                     const uint8_t *src = cbase + (uint64_t)rr * ld + lcol;
-                    uint32_t *dst = half ? dst4 : dst0;
+                    uint32_t *dst = &Sw[wave][slot + (q4 >> 1)][4 * (q4 & 1)][0];
                     const bool rowok = rr < remrows;
                     const bool full = rowok && lcol + 4 <= rem;
                     const bool straddle = rowok && lcol < rem && !full;
@@ -965,63 +987,77 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
                     }
                 }
             }
-            cz++;
-            cbase += 8u * ld;
-            if (++ck == nks) {
-                ck = 0;
+            cq++;
+            cbase += 16u * ld;
+            if (++cp == npairs) {
+                cp = 0;
                 cs++;
                 cbase = g.S + (uint64_t)cs * MF_STRIP;
             }
         };
-        // Operands of step zf (source group ksf): its copy has landed once the
-        // newer copies alone are outstanding.  Bytes of rows past N and past the
-        // packet end need no masking (see copy_step).
-        auto fetch = [&](int zf, int ksf, MfOperands &o) {
-            __builtin_amdgcn_s_waitcnt(kWaitCopies);
+        // Operands of step zf (source group ksf), in two parts: fetch_issue
+        // waits until the step's copy has landed (once the newer copies alone
+        // are outstanding) and issues the LDS reads; fetch_unpack builds the
+        // MFMA operands.  Bytes of rows past N and past the packet end need no
+        // masking (see copy_pair).
+        struct Raw {
+            gf_u16x2 p01, p23;
+            uint32_t y[4];
+        };
+        auto fetch_issue = [&](int zf, int ksf, auto wait_imm) {
+            __builtin_amdgcn_s_waitcnt(decltype(wait_imm)::value);
             asm volatile("" ::: "memory");
             const uint16_t *rows = reinterpret_cast<const uint16_t *>(&Sw[wave][zf & (MF_STAGES - 1)][4 * h][0]);
-            gf_u16x2 p01, p23;
-            p01.x = rows[0 * 32 + r];
-            p01.y = rows[1 * 32 + r];
-            p23.x = rows[2 * 32 + r];
-            p23.y = rows[3 * 32 + r];
-            const uint32_t t01 = __builtin_bit_cast(uint32_t, p01);   // r0c0 r0c1 r1c0 r1c1
-            const uint32_t t23 = __builtin_bit_cast(uint32_t, p23);   // r2c0 r2c1 r3c0 r3c1
+            Raw w;
+            w.p01.x = rows[0 * 32 + r];
+            w.p01.y = rows[1 * 32 + r];
+            w.p23.x = rows[2 * 32 + r];
+            w.p23.y = rows[3 * 32 + r];
+#pragma unroll
+            for (int rt = 0; rt < 4; rt++)
+                w.y[rt] = Ybuf[ksf][rt][lane];
+            return w;
+        };
+        auto fetch_unpack = [&](const Raw &w, MfOperands &o) {
+            const uint32_t t01 = __builtin_bit_cast(uint32_t, w.p01);   // r0c0 r0c1 r1c0 r1c1
+            const uint32_t t23 = __builtin_bit_cast(uint32_t, w.p23);   // r2c0 r2c1 r3c0 r3c1
             o.b[0] = fp4_source(__builtin_amdgcn_perm(t23, t01, 0x06040200u));   // column 2r of rows 0..3
             o.b[1] = fp4_source(__builtin_amdgcn_perm(t23, t01, 0x07050301u));   // column 2r + 1
 #pragma unroll
             for (int rt = 0; rt < 4; rt++)
-                o.a[rt] = fp4_coef(Ybuf[ksf][rt][lane]);
+                o.a[rt] = fp4_coef(w.y[rt]);
+        };
+        // One step: the next operands are read and unpacked while this step's
+        // products run (the scheduling fence keeps the reads ahead of them).
+        auto step = [&](int zn, int ksn, const MfOperands &cur, MfOperands &nxt, auto wait_imm) {
+            const Raw w = fetch_issue(zn, ksn, wait_imm);
+            __builtin_amdgcn_sched_barrier(0);
+            fetch_unpack(w, nxt);
+            mf_mma(cur, acc);
+            mf_step_schedule();
         };
 
-        for (int j = 0; j < MF_STAGES - 1; j++)
-            copy_step();
+        // Before the pair starting at step z = 2q, copies are issued through
+        // pair q + MF_PAIRS_AHEAD - 1.  Reading step 2q + 1 (after this pair's
+        // copies): 4 MF_PAIRS_AHEAD newer loads; reading step 2q + 2: 2 fewer.
+        using WaitOdd = std::integral_constant<int, vm_wait(4 * MF_PAIRS_AHEAD)>;
+        using WaitEven = std::integral_constant<int, vm_wait(4 * MF_PAIRS_AHEAD - 2)>;
+        for (int j = 0; j < MF_PAIRS_AHEAD; j++)
+            copy_pair();
         mf_acc_reset(acc);
-        // Two operand sets take turns (steps z and z + 1), so no registers are
-        // copied between steps; an odd group count hands over once per strip.
+        // Two operand sets take turns, so no registers are copied between steps.
         MfOperands opa, opb;
-        fetch(0, 0, opa);
+        fetch_unpack(fetch_issue(0, 0, WaitEven{}), opa);
         // The accumulators run over all strips of the tile and restart every
         // kMfRestart strips: a strip adds at most 64 nks <= 2048 to a count, so
         // the total stays below 2^23 + 2^22, exact in FP32.
         uint32_t prev[4] = {0u, 0u, 0u, 0u};
         int z = 0;
         for (int strip = 0; strip < nstrips; strip++) {
-            int ks = 0;
-            for (; ks + 2 <= nks; ks += 2, z += 2) {
-                copy_step();              // step z + MF_STAGES - 1, into the slot of step z - 1
-                fetch(z + 1, ks + 1, opb);
-                mf_mma(opa, acc);         // independent of the fetch: the two interleave
-                copy_step();
-                fetch(z + 2, ks + 2 == nks ? 0 : ks + 2, opa);   // past the last step: a zero slot, never used
-                mf_mma(opb, acc);
-            }
-            if (ks < nks) {
-                copy_step();
-                fetch(z + 1, 0, opb);
-                mf_mma(opa, acc);
-                opa = opb;
-                z++;
+            for (int kp = 0; kp < npairs; kp++, z += 2) {
+                copy_pair();              // pair q + MF_PAIRS_AHEAD, into the slots of pair q - 1
+                step(z + 1, 2 * kp + 1, opa, opb, WaitOdd{});
+                step(z + 2, kp + 1 == npairs ? 0 : 2 * kp + 2, opb, opa, WaitEven{});   // past the end: a zero slot
             }
             mf_store<true>(g, k0, (uint64_t)strip * MF_STRIP + (uint64_t)wave * 64u + 2u * (uint64_t)r, acc, h,
                            prev);
