@@ -940,20 +940,25 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
         const uint64_t ld = g.ld_s;
         const int nstrips = (int)((g.len + MF_STRIP - 1) / MF_STRIP);
         const int Zp = nstrips * npairs;        // the plan keeps this below 2^30
-        // Copies of whole 16-row pairs inside whole strips are a wave-uniform
-        // base plus a fixed per-lane offset (when the offsets fit 32 bits).
+        // Copies of whole 16-row pairs inside whole strips are the generation's
+        // source pointer plus a wave-uniform 32-bit offset plus a fixed per-lane
+        // offset, when the generation's source span fits 31 bits.
         const int kp_full = N >> 4;
-        const int strips_full = ld <= (1u << 26) ? (int)(g.len / MF_STRIP) : 0;
+        const bool narrow = (uint64_t)N * ld + g.len < (1ull << 31);
+        const int strips_full = narrow ? (int)(g.len / MF_STRIP) : 0;
         const uint32_t lcol = (uint32_t)wave * 64u + (uint32_t)(lane & 15) * 4u;
-        const uint32_t loff = (uint32_t)(lane >> 4) * (uint32_t)ld + lcol;
         const uint32_t ld4 = 4u * (uint32_t)ld;
-        // Copy cursor: pair cq = (strip cs, pair cp).  Lane l copies 4 bytes of
-        // source rows 16 cp + l / 16 + {0, 4, 8, 12} at byte (l % 16) * 4 of this
-        // wave's 64.  Outside the generation or the packet a lane copies a zero
-        // word (row 0 of the table, the bit matrix of 0): such bytes meet zero
-        // coefficient bits or are never stored.  A chunk that straddles the
-        // packet end is assembled byte by byte (at most 4 lanes per instruction).
+        const uint32_t loff = (uint32_t)(lane >> 4) * (uint32_t)ld + lcol;
+        // Copy cursor: pair cq = (strip cs, pair cp), whose first row starts
+        // `coff` bytes into the source (valid while narrow; cbase for the rest).
+        // Lane l copies 4 bytes of source rows 16 cp + l / 16 + {0, 4, 8, 12} at
+        // byte (l % 16) * 4 of this wave's 64.  Outside the generation or the
+        // packet a lane copies a zero word (row 0 of the table, the bit matrix
+        // of 0): such bytes meet zero coefficient bits or are never stored.  A
+        // chunk that straddles the packet end is assembled byte by byte (at most
+        // 4 lanes per instruction).
         int cq = 0, cp = 0, cs = 0;
+        uint32_t coff = 0, soff = 0;
         const uint8_t *cbase = g.S;
         auto copy_pair = [&]() {
             const int slot = (2 * cq) & (MF_STAGES - 1);
@@ -961,7 +966,7 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
 #pragma unroll
                 for (int q4 = 0; q4 < 4; q4++)
                     __builtin_amdgcn_global_load_lds(
-                        reinterpret_cast<const void *>(cbase + loff + (uint32_t)q4 * ld4),
+                        reinterpret_cast<const void *>(g.S + (coff + loff + (uint32_t)q4 * ld4)),
                         (__attribute__((address_space(3))) void *)&Sw[wave][slot + (q4 >> 1)][4 * (q4 & 1)][0], 4,
                         0, 0);
             } else {
@@ -988,11 +993,15 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
                 }
             }
             cq++;
-            cbase += 16u * ld;
             if (++cp == npairs) {
                 cp = 0;
                 cs++;
+                soff += MF_STRIP;
+                coff = soff;
                 cbase = g.S + (uint64_t)cs * MF_STRIP;
+            } else {
+                coff += 16u * (uint32_t)ld;
+                cbase += 16u * ld;
             }
         };
         // Operands of step zf (source group ksf), in two parts: fetch_issue
