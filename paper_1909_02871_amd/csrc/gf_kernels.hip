@@ -664,12 +664,15 @@ __device__ __forceinline__ void mf_tile_setup(const DevGen &g, int k0, int nks, 
 // over the tile's strips, so this strip's parities are those of the total
 // XOR those of the previous total, kept per lane in prev (two bytes per
 // packet: prev[rt] holds j = 0 in bits 0..15 and j = 1 in bits 16..31).
+// whole (wave-uniform): both columns of every lane lie inside the packet and
+// the output rows are 2-byte aligned, so each packet's pair is one 16-bit store.
 // Stores go through the global address space (no LDS counter traffic).
 template <bool RUNNING>
 __device__ __forceinline__ void mf_store(const DevGen &g, int k0, uint64_t col, gf_v16f (&acc)[4][2], int h,
-                                         uint32_t (&prev)[4])
+                                         uint32_t (&prev)[4], bool whole)
 {
     const int K = (int)g.K;
+    uint32_t out[4][2];
 #pragma unroll
     for (int rt = 0; rt < 4; rt++) {
         uint32_t pr = 0;
@@ -679,6 +682,28 @@ __device__ __forceinline__ void mf_store(const DevGen &g, int k0, uint64_t col, 
             pr |= v << (16 * j);
             if (RUNNING)
                 v ^= (prev[rt] >> (16 * j)) & 0xFFFFu;
+            out[rt][j] = v;
+        }
+        if (RUNNING)
+            prev[rt] = pr;
+    }
+    if (whole) {
+        const uint8_t *base = g.Y + (uint64_t)(k0 + h) * g.ld_y + col;
+#pragma unroll
+        for (int rt = 0; rt < 4; rt++)
+#pragma unroll
+            for (int j = 0; j < 2; j++)
+                if (k0 + 4 * rt + 2 * j + h < K)
+                    *reinterpret_cast<__attribute__((address_space(1))) uint16_t *>(
+                        reinterpret_cast<uintptr_t>(base + (uint64_t)(4 * rt + 2 * j) * g.ld_y)) =
+                        (uint16_t)out[rt][j];
+        return;
+    }
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            const uint32_t v = out[rt][j];
             const int row = k0 + 4 * rt + 2 * j + h;
             if (row >= K || col >= g.len)
                 continue;
@@ -692,9 +717,6 @@ __device__ __forceinline__ void mf_store(const DevGen &g, int k0, uint64_t col, 
                     yp[1] = (uint8_t)(v >> 8);
             }
         }
-        if (RUNNING)
-            prev[rt] = pr;
-    }
 }
 
 // Step ks of the product for one wave: 8 MFMAs over the 4 row tiles and 2
@@ -771,7 +793,7 @@ __device__ __forceinline__ void mf_tile(const DevGen &g, int k0, int nks, const 
             advance();
             mf_step(Ybuf, ks, lane, X0, X1, acc);
         }
-        mf_store<false>(g, k0, strip * MF_STRIP + lane_col, acc, h, unused);
+        mf_store<false>(g, k0, strip * MF_STRIP + lane_col, acc, h, unused, false);
     }
 }
 
@@ -945,6 +967,7 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
         // offset, when the generation's source span fits 31 bits.
         const int kp_full = N >> 4;
         const bool narrow = (uint64_t)N * ld + g.len < (1ull << 31);
+        const bool y_even = ((reinterpret_cast<uintptr_t>(g.Y) | g.ld_y) & 1u) == 0;
         const int strips_full = narrow ? (int)(g.len / MF_STRIP) : 0;
         const uint32_t lcol = (uint32_t)wave * 64u + (uint32_t)(lane & 15) * 4u;
         const uint32_t ld4 = 4u * (uint32_t)ld;
@@ -1069,7 +1092,7 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
                 step(z + 2, kp + 1 == npairs ? 0 : 2 * kp + 2, opb, opa, WaitEven{});   // past the end: a zero slot
             }
             mf_store<true>(g, k0, (uint64_t)strip * MF_STRIP + (uint64_t)wave * 64u + 2u * (uint64_t)r, acc, h,
-                           prev);
+                           prev, y_even && (uint64_t)(strip + 1) * MF_STRIP <= g.len);
             if ((strip & (kMfRestart - 1)) == kMfRestart - 1) {
                 mf_acc_reset(acc);
 #pragma unroll
