@@ -78,6 +78,9 @@ def main():
     ap.add_argument("--form", type=int, default=0, help="0 autotune, 1 table, 2 bit-matrix MFMA")
     ap.add_argument("--serve-requests", type=int, default=4000, help="requests per serving run (0: skip)")
     ap.add_argument("--serve-budget-gib", type=float, default=4.0)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other workloads (single generation, field/length sweep, GF(16) batch, "
+                         "batched decode, K sweep)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (to calibrate HBM counters) and exit")
     args = ap.parse_args()
@@ -248,12 +251,17 @@ def main():
                "sample": "%d of %d generations (%.3g byte-madds, %.1f MB of source), plain C oracle, one thread"
                          % (len(picked), args.count, acc, src / 1e6),
                "seconds": round(dt, 2), "gpu_output_bit_exact_on_sample": ok}
+        cpu["single_generation"] = single_generation_oracle(gf, torch, oracle)
         log("cpu oracle: %.4f GB/s over %d generations; GPU bit-exact on sample: %s" % (cpu["value"], len(picked), ok))
+
+    del S_dev, C_dev, Y_dev, plan
+    torch.cuda.empty_cache()
+    extra = None
+    if not args.no_extra:
+        extra = extra_workloads(gf, torch, args)
 
     serve = None
     if args.serve_requests > 0:
-        del S_dev, C_dev, Y_dev, plan
-        torch.cuda.empty_cache()
         serve = serve_bench(gf, torch, args)
 
     out = {
@@ -268,8 +276,223 @@ def main():
         "speedup_vs_plain": round(value / plain["value"], 3) if plain else None,
         "hbm_roofline_gbs": round(hbm_roof_src, 1), "hbm_roofline_frac": round(value / hbm_roof_src, 4),
         "roofline": roofline, "forms": forms, "cpu_baseline": cpu, "tuning": tuning, "serve": serve,
+        "other_workloads": extra,
     }
     print(json.dumps(out), flush=True)
+
+
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def time_ms(torch, fn, reps=5, warm=2) -> float:
+    """Mean milliseconds of fn() on torch's current stream (after warm-up calls)."""
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def device_bytes(torch, nbytes: int, seed: int, hi: int = 256):
+    """Seeded uniform bytes in [0, hi), generated on the device (large sweep inputs)."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    return torch.randint(0, hi, (nbytes,), dtype=torch.uint8, device="cuda", generator=g)
+
+
+def uniform_plan(gf, torch, n: int, K: int, N: int, L: int, count: int, seed: int, tune=None):
+    """count generations of K x N coefficients and N packets of L bytes, back to back on the device."""
+    ld = synth.padded(L)
+    S = device_bytes(torch, count * N * ld, seed)
+    Cm = device_bytes(torch, count * K * N, seed + 1, 1 << n)
+    Y = torch.empty(count * K * ld, dtype=torch.uint8, device="cuda")
+    descs = (gf.gf_gen * count)()
+    s0, c0, y0 = S.data_ptr(), Cm.data_ptr(), Y.data_ptr()
+    for i in range(count):
+        descs[i] = gf.gf_gen(c0 + i * K * N, s0 + i * N * ld, y0 + i * K * ld, K, N, L, ld, ld)
+    plan = gf.gf_plan_encode_desc(n, descs, count, tune=tune if tune is not None else {"form": 0},
+                                  keep=(S, Cm, Y))
+    return plan, S, Cm, Y, ld
+
+
+def extra_workloads(gf, torch, args) -> dict:
+    """The other measured workloads: one generation (latency), the plain field/length sweep,
+    the uneven batch over GF(16), the batched decode and a K sweep at fixed packet length."""
+    out = {}
+    # ---- one generation: GF(256), 16 x 16 x 1500 B, encode and decode back (latency, one launch each)
+    g = synth.single_generation()
+    Cd = torch.from_numpy(g.C).to("cuda")
+    Sd = torch.from_numpy(g.S).to("cuda")
+    Yd = torch.empty_like(Sd)
+    Rd = torch.empty_like(Sd)
+    ws = torch.empty(gf.gf_decode_workspace(16), dtype=torch.uint8, device="cuda")
+    rank = torch.zeros(1, dtype=torch.int32, device="cuda")
+    enc_ms = time_ms(torch, lambda: gf.gf_encode(8, Cd, Sd, Yd), reps=200, warm=5)
+    dec_ms = time_ms(torch, lambda: gf.gf_decode(8, Cd, Yd, Rd, ws, rank), reps=200, warm=5)
+    torch.cuda.synchronize()
+    out["single_generation"] = {"field": "GF(2^8)", "N": 16, "K": 16, "packet_bytes": 1500,
+                                "encode_us": round(enc_ms * 1e3, 2), "decode_us": round(dec_ms * 1e3, 2),
+                                "decoded_equals_source": bool(torch.equal(Rd, Sd)) and int(rank.item()) == 16,
+                                "timing": "mean of 200 back-to-back launches, inputs in HBM"}
+    log("single generation: encode %.1f us, decode %.1f us" % (enc_ms * 1e3, dec_ms * 1e3))
+    del Cd, Sd, Yd, Rd, ws
+
+    # ---- plain sweep: 4096 generations, N = K = 64, every field and packet length
+    sweep = []
+    count = 4096
+    for n in (1, 2, 4, 8):
+        for L in (1500, 9000, 65536):
+            plan, S, Cm, Y, ld = uniform_plan(gf, torch, n, 64, 64, L, count, synth.BASE_SEED + 1 + 100 * n + L)
+            ms = time_ms(torch, lambda: gf.gf_plan_launch_graph(plan), reps=3, warm=1)
+            src = count * 64 * L
+            t = plan.tuning()
+            # region madd: one madd per (generation, source) into its own destination row
+            R = torch.empty_like(S)
+            nreg = count * 64
+            dt = np.dtype([("y", "<u8"), ("x", "<u8"), ("len", "<u8"), ("c", "<u4"), ("r", "<u4")])
+            regs = np.zeros(nreg, dtype=dt)
+            idx = np.arange(nreg, dtype=np.uint64)
+            regs["y"] = np.uint64(R.data_ptr()) + idx * np.uint64(ld)
+            regs["x"] = np.uint64(S.data_ptr()) + idx * np.uint64(ld)
+            regs["len"] = L
+            regs["c"] = (np.arange(nreg) % ((1 << n) - 1)) + 1
+            d_regs = torch.from_numpy(regs.view(np.uint8).copy()).to("cuda")
+            mms = time_ms(torch, lambda: gf.gf_region_madd_batched(n, d_regs, nreg, L), reps=3, warm=1)
+            hbm_enc = HBM_PEAK_GBS * (64 * L) / (64 * L + 64 * L + 64 * 64)
+            sweep.append({"field": "GF(2^%d)" % n, "packet_bytes": L, "generations": count,
+                          "encode_gbs": round(src / ms / 1e6, 2), "encode_ms": round(ms, 3),
+                          "encode_hbm_frac": round(src / ms / 1e6 / hbm_enc, 4), "form": t["form"],
+                          "madd_gbs": round(src / mms / 1e6, 2), "madd_ms": round(mms, 3),
+                          "madd_hbm_frac": round(3 * src / mms / 1e6 / HBM_PEAK_GBS, 4)})
+            log("sweep GF(2^%d) L=%d: encode %.1f GB/s (form %d), region madd %.1f GB/s"
+                % (n, L, src / ms / 1e6, t["form"], src / mms / 1e6))
+            plan.destroy()
+            del plan, S, Cm, Y, R, d_regs
+            torch.cuda.empty_cache()
+    out["sweep"] = sweep
+
+    # ---- the uneven batch over GF(16)
+    b = synth.uneven_batch(4, args.count)
+    S_dev = torch.from_numpy(b.source_blob()).to("cuda")
+    C_dev = torch.from_numpy(b.coef_blob()).to("cuda")
+    Y_dev = torch.empty(b.y_bytes, dtype=torch.uint8, device="cuda")
+    descs = (gf.gf_gen * args.count)()
+    s0, c0, y0 = S_dev.data_ptr(), C_dev.data_ptr(), Y_dev.data_ptr()
+    for i in range(args.count):
+        descs[i] = gf.gf_gen(c0 + int(b.c_off[i]), s0 + int(b.s_off[i]), y0 + int(b.y_off[i]), int(b.Ks[i]),
+                             int(b.Ns[i]), int(b.Ls[i]), int(b.lds[i]), int(b.lds[i]))
+    plan = gf.gf_plan_encode_desc(4, descs, args.count, tune={"form": 0}, keep=(S_dev, C_dev, Y_dev))
+    ms = time_ms(torch, lambda: gf.gf_plan_launch_graph(plan), reps=5, warm=2)
+    out["uneven_gf16"] = {"generations": args.count, "source_bytes": b.source_bytes,
+                          "gbs": round(b.source_bytes / ms / 1e6, 2), "ms": round(ms, 3),
+                          "form": plan.tuning()["form"]}
+    log("uneven GF(16): %.1f GB/s" % (b.source_bytes / ms / 1e6))
+    plan.destroy()
+    del plan, S_dev, C_dev, Y_dev
+    torch.cuda.empty_cache()
+
+    # ---- batched decode: 2048 systems, N in {32, 64, 128}, 1500 B, GF(256)
+    db = synth.decode_batch(2048, 1500)
+    count = len(db.Ns)
+    S_dev = torch.from_numpy(db.source_blob()).to("cuda")
+    B_dev = torch.empty_like(S_dev)
+    R_dev = torch.empty_like(S_dev)
+    attempt = np.zeros(count, dtype=np.int64)
+    C_host = np.zeros(db.c_bytes, dtype=np.uint8)
+
+    def fill(i):
+        N = int(db.Ns[i])
+        C_host[db.c_off[i]:db.c_off[i] + N * N] = synth.decode_candidate(i, int(attempt[i]), N).reshape(-1)
+
+    for i in range(count):
+        fill(i)
+    rank = torch.zeros(count, dtype=torch.int32, device="cuda")
+    eplan = dplan = None
+    for _ in range(8):    # redraw singular candidates (the device reports each system's rank)
+        if eplan is not None:
+            eplan.destroy()
+            dplan.destroy()
+        C_dev = torch.from_numpy(C_host).to("cuda")
+        sysd = (gf.gf_sys * count)()
+        encd = (gf.gf_gen * count)()
+        for i in range(count):
+            N, L, ld = int(db.Ns[i]), int(db.Ls[i]), int(db.lds[i])
+            cp = C_dev.data_ptr() + int(db.c_off[i])
+            sp = S_dev.data_ptr() + int(db.s_off[i])
+            bp = B_dev.data_ptr() + int(db.s_off[i])
+            rp = R_dev.data_ptr() + int(db.s_off[i])
+            encd[i] = gf.gf_gen(cp, sp, bp, N, N, L, ld, ld)
+            sysd[i] = gf.gf_sys(cp, bp, rp, N, 0, L, ld, ld)
+        eplan = gf.gf_plan_encode_desc(8, encd, count, tune={"form": 1}, keep=(C_dev, S_dev, B_dev))
+        gf.gf_encode_batched(eplan)
+        dplan = gf.gf_plan_decode_desc(8, sysd, count, keep=(C_dev, B_dev, R_dev))
+        gf.gf_decode_batched(dplan, rank)
+        torch.cuda.synchronize()
+        ranks = rank.cpu().numpy()
+        bad = np.nonzero(ranks != db.Ns)[0]
+        if len(bad) == 0:
+            break
+        for i in bad:
+            attempt[i] += 1
+            fill(int(i))
+    else:
+        raise RuntimeError("decode batch: singular systems left after 8 redraws")
+    ms = time_ms(torch, lambda: gf.gf_plan_launch_graph(dplan, rank), reps=5, warm=2)
+    src = int((db.Ns * db.Ls).sum())
+    out["decode_batched"] = {"systems": count, "N": "U{32,64,128}", "packet_bytes": 1500,
+                             "source_bytes": src, "gbs": round(src / ms / 1e6, 2), "ms": round(ms, 3),
+                             "redrawn": int((attempt > 0).sum()),
+                             "decoded_equals_source": bool(torch.equal(R_dev.view(-1, 1504)[:, :1500],
+                                                                       S_dev.view(-1, 1504)[:, :1500]))}
+    log("batched decode: %.1f GB/s, bit-exact %s" % (src / ms / 1e6, out["decode_batched"]["decoded_equals_source"]))
+    eplan.destroy()
+    dplan.destroy()
+    del S_dev, B_dev, R_dev, C_dev
+    torch.cuda.empty_cache()
+
+    # ---- K sweep at 9000 B: where encode meets the HBM roofline
+    ks = []
+    for K in (1, 2, 4, 8, 16, 32, 64, 128, 256):
+        count = int(np.ceil(1e9 / (K * 9000)))
+        plan, S, Cm, Y, ld = uniform_plan(gf, torch, 8, K, K, 9000, count, synth.BASE_SEED + 5 + K)
+        ms = time_ms(torch, lambda: gf.gf_plan_launch_graph(plan), reps=3, warm=1)
+        src = count * K * 9000
+        hbm = HBM_PEAK_GBS * (K * 9000) / (2 * K * 9000 + K * K)
+        ks.append({"K": K, "N": K, "generations": count, "gbs": round(src / ms / 1e6, 2),
+                   "hbm_roofline_gbs": round(hbm, 1), "hbm_frac": round(src / ms / 1e6 / hbm, 4),
+                   "byte_madds_per_s": round(K * src / ms * 1e3, 1), "form": plan.tuning()["form"]})
+        log("K sweep K=%d: %.1f GB/s (%.0f%% of HBM roofline, form %d)"
+            % (K, src / ms / 1e6, 100 * src / ms / 1e6 / hbm, plan.tuning()["form"]))
+        plan.destroy()
+        del plan, S, Cm, Y
+        torch.cuda.empty_cache()
+    out["k_sweep_gf256_9000B"] = ks
+    return out
+
+
+def single_generation_oracle(gf, torch, oracle) -> dict:
+    """The oracle's CPU seconds for the one-generation encode and decode (GF(256), 16 x 16 x 1500 B),
+    checked against the GPU's bytes."""
+    g = synth.single_generation()
+    t0 = time.perf_counter()
+    Y = oracle.encode(8, g.C, g.S)
+    t1 = time.perf_counter()
+    r, R = oracle.decode(8, g.C, Y)
+    t2 = time.perf_counter()
+    Cd = torch.from_numpy(g.C).to("cuda")
+    Sd = torch.from_numpy(g.S).to("cuda")
+    Yd = torch.empty_like(Sd)
+    gf.gf_encode(8, Cd, Sd, Yd)
+    torch.cuda.synchronize()
+    return {"encode_s": round(t1 - t0, 6), "decode_s": round(t2 - t1, 6),
+            "gpu_encode_bit_exact": bool((Yd.cpu().numpy() == Y).all()),
+            "decode_equals_source": bool(r == 16 and R is not None and (R == g.S).all())}
 
 
 def serve_bench(gf, torch, args) -> dict:

@@ -152,7 +152,7 @@ typedef struct {
  * form 0 on an encode plan: both forms are timed on the plan's own batch
  * while the plan is created (which writes the plan's outputs) and the faster
  * is kept (form 1 alone if a packet is too long for form 2); on a decode plan
- * form 0 means form 1. */
+ * form 0 means form 2 when every coded row starts 4-byte aligned, else 1. */
 typedef struct {
     int form;           /* 0 auto, 1 table, 2 bit-matrix */
     int bytes_per_lane; /* 0 = per tile; else 4, 8 or 16 payload bytes per lane everywhere */

@@ -616,8 +616,10 @@ static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, co
         return GF_EDEVICE;
     if (form == 2 && !mf_ok)
         return GF_ERANGE;
-    if (form == 0 && (!may_run || !mf_ok))
+    if (form == 0 && !mf_ok)
         form = 1;
+    if (form == 0 && !may_run)   // no trial launches: the bit-matrix form when its DMA path applies
+        form = p->src_aligned4 ? 2 : 1;
     if (form != 0)
         return make_schedule(p, d, g, form, tune);
     // autotune: both forms on the real batch

@@ -132,7 +132,9 @@ struct gf_server {
     unsigned *ctr = nullptr;
     const uint32_t *ptab = nullptr;
     const uint8_t *inv = nullptr;
-    int grid_max = 1;
+    const uint8_t *rows = nullptr;   // bit-matrix rows of the field
+    int grid_max = 1;                // table-form workgroups at once
+    int grid_max_mf = 1;             // bit-matrix workgroups at once
     int64_t next_step = 0;
     std::unordered_map<uint64_t, Req *> reqs;
     std::deque<Req *> queue;
@@ -335,6 +337,7 @@ int gf_serve_create(const gf_serve_config *cfg, gf_server **out)
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     sv->grid_max = std::max(1, cus) * encode_blocks_per_cu();
+    sv->grid_max_mf = std::max(1, cus) * encode_mfma_blocks_per_cu(true);
     const HostTables &h = host_tables();
     (void)h;
     if (hipMalloc(reinterpret_cast<void **>(&sv->base), cfg->budget_bytes) != hipSuccess) {
@@ -357,6 +360,7 @@ int gf_serve_create(const gf_serve_config *cfg, gf_server **out)
         gf_serve_destroy(sv);
         return rc;
     }
+    sv->rows = gfnc_field_rows(cfg->field);
     *out = sv;
     return GF_OK;
 }
@@ -555,10 +559,20 @@ int gf_serve_step(gf_server *sv, double now)
     if (absorb.empty() && gens.empty() && init_meta.empty())
         return (int)sv->inflight.size();
 
-    for (DevGen &g : gens)
+    // The step's products run on the matrix cores (bit-matrix form) when every
+    // source row starts 4-byte aligned and no packet is too long for it; the
+    // table form otherwise.
+    bool mf = sv->rows != nullptr;
+    for (DevGen &g : gens) {
         g.align = row_align(g.S, g.N > 1 ? g.ld_s : 0, g.Y, g.K > 1 ? g.ld_y : 0);
+        if ((((uintptr_t)g.S) | (g.N > 1 ? g.ld_s : 0)) % 4 != 0 || g.len > (1ull << 34))
+            mf = false;
+    }
     TileQueues tq;
-    build_tiles(gens.data(), gens.size(), 0, tq);
+    if (mf)
+        build_tiles_mfma(gens.data(), gens.size(), tq);
+    else
+        build_tiles(gens.data(), gens.size(), 0, tq);
     const std::vector<DevTile> &tiles = tq.tiles;
     std::vector<unsigned> rb = tq.runs;   // runs, then the queue bounds
     rb.insert(rb.end(), tq.bounds, tq.bounds + MF_QUEUES + 1);
@@ -597,11 +611,18 @@ int gf_serve_step(gf_server *sv, double now)
             e = launch_absorb(reinterpret_cast<const DevAbsorb *>(b.dev + o_abs), (int)absorb.size(),
                               reinterpret_cast<const DevPacket *>(b.dev + o_pk), sv->ptab, sv->inv, s);
         if (e == hipSuccess && !tiles.empty()) {
-            const int grid = std::max(1, std::min<int>(sv->grid_max, ((int)tiles.size() + 3) / 4));
             const unsigned *runs = reinterpret_cast<const unsigned *>(b.dev + o_runs);
-            e = launch_encode_persistent(reinterpret_cast<const DevGen *>(b.dev + o_gen),
-                                         reinterpret_cast<const DevTile *>(b.dev + o_tile), runs,
-                                         runs + tq.runs.size(), (int)tiles.size(), sv->ctr, grid, sv->ptab, s);
+            const DevGen *dg = reinterpret_cast<const DevGen *>(b.dev + o_gen);
+            const DevTile *dt = reinterpret_cast<const DevTile *>(b.dev + o_tile);
+            if (mf) {
+                const int grid = std::max(1, std::min<int>(sv->grid_max_mf, (int)tiles.size()));
+                e = launch_encode_mfma(dg, dt, runs, runs + tq.runs.size(), (int)tiles.size(), sv->ctr, grid,
+                                       sv->rows, true, s);
+            } else {
+                const int grid = std::max(1, std::min<int>(sv->grid_max, ((int)tiles.size() + 3) / 4));
+                e = launch_encode_persistent(dg, dt, runs, runs + tq.runs.size(), (int)tiles.size(), sv->ctr, grid,
+                                             sv->ptab, s);
+            }
         }
         if (e == hipSuccess && !status_meta.empty()) {
             e = launch_status_gather(reinterpret_cast<int *const *>(b.dev + o_stat), (int)status_meta.size(),

@@ -329,7 +329,10 @@ def test_batched_encode_and_graph(gf, n):
 
 
 @pytest.mark.parametrize("n", FIELDS)
-def test_batched_decode(gf, n):
+@pytest.mark.parametrize("layout", ["packed", "padded"])
+def test_batched_decode(gf, n, layout):
+    """Packed rows (any alignment: table-form apply) and 16-byte row pitch
+    (the bit-matrix apply that decode plans pick by default)."""
     torch = torch_cuda()
     count = 40
     systems, wants, ranks_or = [], [], []
@@ -346,9 +349,15 @@ def test_batched_decode(gf, n):
         r = oracle.rank(n, Cm)
         ranks_or.append(r)
         wants.append(S if r == N else None)
-        out = torch.full((N, L), 0x3C, dtype=torch.uint8, device="cuda")
-        systems.append((dev(Cm), dev(B), out))
+        if layout == "packed":
+            out = torch.full((N, L), 0x3C, dtype=torch.uint8, device="cuda")
+            Bd = dev(B)
+        else:
+            _, out = padded_rows(np.full((N, L), 0x3C, np.uint8), synth.padded(L))
+            _, Bd = padded_rows(B, synth.padded(L))
+        systems.append((dev(Cm), Bd, out))
     plan = gf.gf_plan_decode(n, systems)
+    assert plan.tuning()["form"] == (2 if layout == "padded" else 1)
     rank = torch.full((count,), -1, dtype=torch.int32, device="cuda")
     for mode in ("eager", "graph", "graph"):
         for _, _, out in systems:
