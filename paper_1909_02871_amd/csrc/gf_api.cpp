@@ -416,24 +416,34 @@ static int upload(T **dst, const std::vector<T> &src)
 
 namespace gfnc {
 
-// Wave tiles of one generation: blocks of ENC_ROWS coded rows times payload
-// strips.  Full strips use 16 bytes per lane (1024 B per wave); the last
-// partial strip uses the narrowest lane width that covers it, so at most a
-// few lanes idle.  `fixed_D` forces one width for every strip.
+// Wave tiles of one generation: per block of ENC_ROWS coded rows, strips of
+// 256*D bytes (D = 4 while more than 512 bytes remain; a packet's last partial
+// strip uses the narrowest lane width that covers it, so at most a few lanes
+// idle).  `fixed_D` forces one width for every strip.  Consecutive strips of
+// one width share a tile while the tile's byte products stay below 2^18
+// (short generations: fewer claims and descriptor loads per byte).
 static void gen_tiles(uint32_t gi, const DevGen &x, int fixed_D, std::vector<std::pair<DevTile, double>> &out)
 {
     if (x.K == 0 || x.len == 0)
         return;
+    auto width = [&](uint64_t rest) {
+        return fixed_D ? fixed_D : rest > wave_strip(2) ? 4 : rest > wave_strip(1) ? 2 : 1;
+    };
     for (uint32_t k0 = 0; k0 < x.K; k0 += ENC_ROWS) {
         const double rows = (double)std::min<uint32_t>(ENC_ROWS, x.K - k0);
         uint64_t p0 = 0;
         while (p0 < x.len) {
-            const uint64_t rest = x.len - p0;
-            int D = fixed_D;
-            if (!D)
-                D = rest > wave_strip(2) ? 4 : rest > wave_strip(1) ? 2 : 1;
-            out.push_back({DevTile{gi, (uint16_t)k0, (uint16_t)D, p0}, (double)x.N * rows * (double)wave_strip(D)});
-            p0 += wave_strip(D);
+            const int D = width(x.len - p0);
+            const double per = (double)x.N * rows * (double)wave_strip(D);
+            int strips = 1;
+            while (strips < 256 && per * (strips + 1) <= 262144.0) {
+                const uint64_t next = p0 + (uint64_t)strips * wave_strip(D);
+                if (next >= x.len || width(x.len - next) != D)
+                    break;
+                strips++;
+            }
+            out.push_back({DevTile{gi, (uint16_t)k0, (uint16_t)(D | ((strips - 1) << 8)), p0}, per * strips});
+            p0 += (uint64_t)strips * wave_strip(D);
         }
     }
 }

@@ -50,8 +50,11 @@ struct DevGen {
     uint32_t align;      // largest of 16, 8, 4, 1 dividing S, Y, ld_s and ld_y
 };
 
-// One wave tile of the persistent encode: up to ENC_ROWS coded rows from k0,
-// over the 256*D payload bytes starting at p0 (D dwords per lane).
+// One wave tile of the persistent (table-form) encode: up to ENC_ROWS coded
+// rows from k0, over `strips` consecutive strips of 256*d payload bytes from
+// p0 (d dwords per lane), where D = d | (strips - 1) << 8; short generations
+// take several strips per tile so that claims and descriptor loads amortise.
+// The bit-matrix form uses gen and k0 only.
 struct DevTile {
     uint32_t gen;
     uint16_t k0;

@@ -238,12 +238,14 @@ __device__ __forceinline__ void load_lane(const uint8_t *p, uint64_t avail, bool
 // bytes starting at p0 (4*D bytes per lane).  The N source rows stream
 // through in pairs; each coded row accumulates, per dword of 4 bytes, the
 // three byte-select products of both sources with two 3-input XORs.
+// staged: the wave's stage already holds the tables of sources nb .. ne-1
+// (ne - nb <= NCW, the same rows and sources as a previous call).
 template <int D>
 __device__ __forceinline__ void wave_tile(const uint8_t *__restrict__ C, int K, int N,
                                           const uint8_t *__restrict__ S, uint64_t ld_s, uint8_t *__restrict__ Y,
                                           uint64_t ld_y, uint64_t len, int k0, uint64_t p0, bool vec,
                                           const uint4 *__restrict__ ptab4, WaveStage &st, int lane, int nb, int ne,
-                                          bool atomic_out)
+                                          bool atomic_out, bool staged = false)
 {
     const uint64_t p = p0 + (uint64_t)lane * (4u * D);
     const uint64_t avail = p < len ? len - p : 0;
@@ -268,7 +270,7 @@ __device__ __forceinline__ void wave_tile(const uint8_t *__restrict__ C, int K, 
 
     for (int g = nb; g < ne; g += 2) {
         const int nn = (g - nb) & (NCW - 1);
-        if (nn == 0) {
+        if (nn == 0 && !staged) {
             wave_sync();
             const int nc = min(NCW, ne - g);
 #pragma unroll
@@ -500,15 +502,21 @@ __global__ __launch_bounds__(256, GF_ENC_WAVES_PER_SIMD) void k_encode_waves(con
         const DevGen g = gens[tl.gen];
         if (g.status && *g.status != g.need)
             continue;
-        if (tl.D == 4)
-            wave_tile<4>(g.C, (int)g.K, (int)g.N, g.S, g.ld_s, g.Y, g.ld_y, g.len, (int)tl.k0, tl.p0,
-                         g.align >= 16, ptab4, stage[wave], lane, 0, (int)g.N, false);
-        else if (tl.D == 2)
-            wave_tile<2>(g.C, (int)g.K, (int)g.N, g.S, g.ld_s, g.Y, g.ld_y, g.len, (int)tl.k0, tl.p0,
-                         g.align >= 8, ptab4, stage[wave], lane, 0, (int)g.N, false);
-        else
-            wave_tile<1>(g.C, (int)g.K, (int)g.N, g.S, g.ld_s, g.Y, g.ld_y, g.len, (int)tl.k0, tl.p0,
-                         g.align >= 4, ptab4, stage[wave], lane, 0, (int)g.N, false);
+        // strips after the first reuse the staged tables when one stage holds every source
+        const int d = tl.D & 0xFF, strips = (tl.D >> 8) + 1;
+        for (int q = 0; q < strips; q++) {
+            const uint64_t p0 = tl.p0 + (uint64_t)q * 256u * (uint64_t)d;
+            const bool staged = q > 0 && (int)g.N <= NCW;
+            if (d == 4)
+                wave_tile<4>(g.C, (int)g.K, (int)g.N, g.S, g.ld_s, g.Y, g.ld_y, g.len, (int)tl.k0, p0,
+                             g.align >= 16, ptab4, stage[wave], lane, 0, (int)g.N, false, staged);
+            else if (d == 2)
+                wave_tile<2>(g.C, (int)g.K, (int)g.N, g.S, g.ld_s, g.Y, g.ld_y, g.len, (int)tl.k0, p0,
+                             g.align >= 8, ptab4, stage[wave], lane, 0, (int)g.N, false, staged);
+            else
+                wave_tile<1>(g.C, (int)g.K, (int)g.N, g.S, g.ld_s, g.Y, g.ld_y, g.len, (int)tl.k0, p0,
+                             g.align >= 4, ptab4, stage[wave], lane, 0, (int)g.N, false, staged);
+        }
     }
     if (lane == 0)
         queue_retire(counters, gridDim.x * WAVES);
