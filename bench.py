@@ -47,8 +47,8 @@ MFMA_FP4_TFLOPS = 10100.0
 MEASURED_TRAFFIC = {
     # kernel source hash, form -> HBM bytes per launch: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB, averages over
     # the profiled launches; the factors come from a 1 GiB device copy read by the same counters)
-    ("5b6c46f3e081554fda186a6619a2e1b155f98adb2ce7d4692dfd2802413f9ebf", 2): 1453292 * 1024 * 2.0 + 2457752 * 1024,
-    ("5b6c46f3e081554fda186a6619a2e1b155f98adb2ce7d4692dfd2802413f9ebf", 1): 2948703 * 1024 * 2.0 + 2411031 * 1024,
+    ("99243ca088ccbad8211e30533fbf3786632f8d464f001c54cec9a1f929e29baf", 2): 1462628 * 1024 * 2.0 + 2469149 * 1024,
+    ("99243ca088ccbad8211e30533fbf3786632f8d464f001c54cec9a1f929e29baf", 1): 3100195 * 1024 * 2.0 + 2449758 * 1024,
 }
 
 
