@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--form", type=int, default=0, help="0 autotune, 1 table, 2 bit-matrix MFMA")
     ap.add_argument("--serve-requests", type=int, default=4000, help="requests per serving run (0: skip)")
     ap.add_argument("--serve-budget-gib", type=float, default=4.0)
+    ap.add_argument("--serve-burst", type=int, default=0,
+                    help="packets a decode request absorbs per step (0: the library default)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the other workloads (single generation, field/length sweep, GF(16) batch, "
                          "batched decode, K sweep)")
@@ -553,7 +555,7 @@ def serve_bench(gf, torch, args) -> dict:
     def run(rate):
         for tr, g in zip(trace, unit_gaps):
             tr.arrival = 0.0 if rate is None else float(g) / rate
-        srv = gf.Server(field=n, budget_bytes=budget)
+        srv = gf.Server(field=n, budget_bytes=budget, burst=args.serve_burst)
         t0 = time.perf_counter()
         done = replay(srv, trace, timeout_s=300)
         wall = time.perf_counter() - t0

@@ -1126,12 +1126,14 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
 // undone at the end as column swaps in reverse order.  Rows are stored with a
 // stride of MAXN bytes; a dword holds 4 consecutive entries, and each
 // row-times-constant update is one byte-permute product per dword.
-template <int MAXN>
-__device__ void invert_body(const uint8_t *__restrict__ Cg, int N, uint8_t *__restrict__ Cinv, int *rank_out,
+// A: the caller's LDS matrix of MAXN x MAXN bytes; row(r) gives the address
+// of the matrix's row r (N bytes, device memory written before this kernel or
+// read-only input).
+template <int MAXN, class RowOf>
+__device__ void invert_rows(uint32_t *A, RowOf row, int N, uint8_t *__restrict__ Cinv, int *rank_out,
                             const uint4 *__restrict__ ptab4, const uint8_t *__restrict__ invg)
 {
     constexpr int RW = MAXN / 4;   // dwords per row
-    __shared__ uint32_t A[MAXN * RW];
     __shared__ uint4 T[256][2];
     __shared__ uint8_t IV[256];
     __shared__ uint8_t fcol[MAXN];
@@ -1141,6 +1143,9 @@ __device__ void invert_body(const uint8_t *__restrict__ Cg, int N, uint8_t *__re
     uint8_t *Ab = reinterpret_cast<uint8_t *>(A);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int NW = (N + 3) >> 2;
+    // row updates: thread tid owns column dword cl of rows r0, r0 + RS, ...
+    constexpr int RS = 256 / RW;
+    const int cl = tid % RW, r0 = tid / RW;
 
     for (int i = tid; i < 512; i += 256)
         T[i >> 1][i & 1] = ptab4[i];
@@ -1149,11 +1154,12 @@ __device__ void invert_body(const uint8_t *__restrict__ Cg, int N, uint8_t *__re
     auto load_matrix = [&]() {
         for (int i = tid; i < N * RW; i += 256) {
             const int r = i / RW, w = i - r * RW;
+            const uint8_t *src = row(r);
             uint32_t v = 0;
             for (int b = 0; b < 4; b++) {
                 const int c = 4 * w + b;
                 if (c < N)
-                    v |= (uint32_t)Cg[(uint64_t)r * N + c] << (8 * b);
+                    v |= (uint32_t)src[c] << (8 * b);
             }
             A[r * RW + w] = v;
         }
@@ -1200,16 +1206,15 @@ __device__ void invert_body(const uint8_t *__restrict__ Cg, int N, uint8_t *__re
         if (tid < N)
             fcol[tid] = tid == j ? 0 : Ab[tid * MAXN + j];
         __syncthreads();
-        for (int it = tid; it < N * NW; it += 256) {
-            const int i = it / NW, l = it - i * NW;
-            const uint32_t f = fcol[i];
-            if (f == 0)
-                continue;
-            uint32_t a = A[i * RW + l];
-            if (l == (j >> 2))
-                a &= ~(0xFFu << (8 * (j & 3)));
-            a ^= prod4(T[f][0], T[f][1].x, A[j * RW + l]);
-            A[i * RW + l] = a;
+        if (cl < NW) {   // thread: column dword cl of rows r0, r0 + RS, ...
+            const uint32_t pj = A[j * RW + cl];
+            const uint32_t keep = cl == (j >> 2) ? ~(0xFFu << (8 * (j & 3))) : 0xFFFFFFFFu;
+#pragma unroll 4
+            for (int i = r0; i < N; i += RS) {
+                const uint32_t f = fcol[i];
+                if (f)
+                    A[i * RW + cl] = (A[i * RW + cl] & keep) ^ prod4(T[f][0], T[f][1].x, pj);
+            }
         }
         __syncthreads();
     }
@@ -1256,18 +1261,29 @@ __device__ void invert_body(const uint8_t *__restrict__ Cg, int N, uint8_t *__re
         if (tid < N)
             fcol[tid] = tid > prow ? Ab[tid * MAXN + j] : 0;
         __syncthreads();
-        for (int it = tid; it < N * NW; it += 256) {
-            const int i = it / NW, l = it - i * NW;
-            const uint32_t f = fcol[i];
-            if (f == 0)
-                continue;
-            A[i * RW + l] ^= prod4(T[f][0], T[f][1].x, A[prow * RW + l]);
+        if (cl < NW) {
+            const uint32_t pj = A[prow * RW + cl];
+#pragma unroll 4
+            for (int i = r0; i < N; i += RS) {
+                const uint32_t f = fcol[i];
+                if (f)
+                    A[i * RW + cl] ^= prod4(T[f][0], T[f][1].x, pj);
+            }
         }
         __syncthreads();
         prow++;
     }
     if (tid == 0 && rank_out)
         *rank_out = prow;
+}
+
+// Gauss-Jordan inversion of the row-major N x N matrix at Cg.
+template <int MAXN>
+__device__ void invert_body(const uint8_t *__restrict__ Cg, int N, uint8_t *__restrict__ Cinv, int *rank_out,
+                            const uint4 *__restrict__ ptab4, const uint8_t *__restrict__ invg)
+{
+    __shared__ uint32_t A[MAXN * (MAXN / 4)];
+    invert_rows<MAXN>(A, [&](int r) { return Cg + (uint64_t)r * N; }, N, Cinv, rank_out, ptab4, invg);
 }
 
 template <int MAXN>
@@ -1301,52 +1317,89 @@ __global__ __launch_bounds__(256) void k_invert_batched(const DevSys *__restrict
 // with its raw coefficients and payload.  At rank N the raw coefficient
 // matrix is inverted (Gauss-Jordan, as in gf_invert) and the completion step
 // is recorded, which releases the payload product S = Csel^-1 * Bsel.
+//
+// During a step R lives in LDS (the inversion's matrix buffer, free until
+// then); packet descriptors are cached 64 at a time and the next packet's
+// coefficients are fetched while the current one is reduced, so the loop over
+// packets touches device memory only for those prefetches.  The innovative
+// packets' raw coefficients and payloads are copied out after the loop.
+constexpr int ABSORB_PKC = 64;
+
 __global__ __launch_bounds__(256) void k_absorb(const DevAbsorb *__restrict__ items,
                                                 const DevPacket *__restrict__ pkts, const uint4 *__restrict__ ptab4,
                                                 const uint8_t *__restrict__ invg)
 {
+    __shared__ uint32_t Rl[256 * 64];   // row r at Rl + 64 r; later the inversion's matrix
     __shared__ uint32_t cw[64];
     __shared__ uint32_t part[4][64];
     __shared__ uint4 T[256][2];
     __shared__ uint8_t IV[256];
     __shared__ uint8_t fcol[256];
     __shared__ int pivc[256];
+    __shared__ const uint8_t *row_coef[256];   // raw coefficients of the rows added in this step
+    __shared__ const uint8_t *row_pay[256];
+    __shared__ DevPacket pkc[ABSORB_PKC];
     __shared__ int cand[4];
     __shared__ int inv_rank;
     const DevAbsorb it = items[blockIdx.x];
     const DevDecSlot &s = it.s;
     const int N = (int)s.N, NW = (N + 3) >> 2;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint8_t *Rb = reinterpret_cast<const uint8_t *>(Rl);
 
     int rank = s.meta[0];
     if (rank >= N || N > 256)
         return;
+    const int rank0 = rank;
     for (int i = tid; i < 512; i += 256)
         T[i >> 1][i & 1] = ptab4[i];
     IV[tid] = invg[tid];
     for (int i = tid; i < rank; i += 256)
         pivc[i] = s.meta[4 + i];
+    for (int i = tid; i < rank * NW; i += 256) {
+        const int r = i / NW, w = i - r * NW;
+        Rl[r * 64 + w] = reinterpret_cast<const uint32_t *>(s.R + (uint64_t)r * s.rs)[w];
+    }
+    // coefficient dword tid of a packet (lanes tid < NW)
+    auto coef_dword = [&](const uint8_t *c) {
+        uint32_t v = 0;
+        for (int b = 0; b < 4; b++)
+            if (4 * tid + b < N)
+                v |= (uint32_t)c[4 * tid + b] << (8 * b);
+        return v;
+    };
     int seen = 0, dropped = 0;
-    __syncthreads();
+    uint32_t nextv = 0;
+    bool have_next = false;
 
     for (uint32_t q = 0; q < it.npk && rank < N; q++) {
-        const DevPacket pk = pkts[it.pk0 + q];
-        if (tid < NW) {
-            uint32_t v = 0;
-            for (int b = 0; b < 4; b++)
-                if (4 * tid + b < N)
-                    v |= (uint32_t)pk.coef[4 * tid + b] << (8 * b);
-            cw[tid] = v;
+        const int slot = (int)(q % ABSORB_PKC);
+        if (slot == 0) {
+            __syncthreads();   // every lane is done with the previous descriptors
+            if (tid < ABSORB_PKC && q + tid < it.npk)
+                pkc[tid] = pkts[it.pk0 + q + tid];
+            __syncthreads();
+        }
+        const DevPacket pk = pkc[slot];
+        if (tid < NW)
+            cw[tid] = have_next ? nextv : coef_dword(pk.coef);
+        // the next packet's coefficients, if its descriptor is cached, land during this one
+        have_next = slot + 1 < ABSORB_PKC && q + 1 < it.npk;
+        if (have_next && tid < NW)
+            nextv = coef_dword(pkc[slot + 1].coef);
+        __syncthreads();
+        for (int r = tid; r < rank; r += 256) {   // the vector's entry in each row's pivot column
+            const int pc = pivc[r];
+            fcol[r] = (uint8_t)(cw[pc >> 2] >> (8 * (pc & 3)));
         }
         __syncthreads();
-        if (lane < NW) {
+        if (lane < NW) {   // wave w sums rows w, w + 4, ... of column dword `lane`
             uint32_t acc = 0;
+#pragma unroll 4
             for (int r = wave; r < rank; r += 4) {
-                const int pc = pivc[r];
-                const uint32_t f = (cw[pc >> 2] >> (8 * (pc & 3))) & 0xFFu;
+                const uint32_t f = fcol[r];
                 if (f)
-                    acc ^= prod4(T[f][0], T[f][1].x,
-                                 reinterpret_cast<const uint32_t *>(s.R + (uint64_t)r * s.rs)[lane]);
+                    acc ^= prod4(T[f][0], T[f][1].x, Rl[r * 64 + lane]);
             }
             part[wave][lane] = acc;
         }
@@ -1372,35 +1425,48 @@ __global__ __launch_bounds__(256) void k_absorb(const DevAbsorb *__restrict__ it
             cw[tid] = prod4(T[iv][0], T[iv][1].x, cw[tid]);
         }
         for (int r = tid; r < rank; r += 256)
-            fcol[r] = s.R[(uint64_t)r * s.rs + lead];
+            fcol[r] = Rb[r * 256 + lead];
         __syncthreads();
-        for (int e = tid; e < rank * NW; e += 256) {
-            const int r = e / NW, l = e - r * NW;
-            const uint32_t f = fcol[r];
-            if (f) {
-                uint32_t *rp = reinterpret_cast<uint32_t *>(s.R + (uint64_t)r * s.rs) + l;
-                *rp ^= prod4(T[f][0], T[f][1].x, cw[l]);
+        if (lane < NW) {   // wave w clears the new pivot column from rows w, w + 4, ...
+            const uint32_t c = cw[lane];
+#pragma unroll 4
+            for (int r = wave; r < rank; r += 4) {
+                const uint32_t f = fcol[r];
+                if (f)
+                    Rl[r * 64 + lane] ^= prod4(T[f][0], T[f][1].x, c);
             }
         }
         if (tid < NW)
-            reinterpret_cast<uint32_t *>(s.R + (uint64_t)rank * s.rs)[tid] = cw[tid];
-        for (int b = tid; b < N; b += 256)
-            s.Csel[(uint64_t)rank * N + b] = pk.coef[b];
-        uint8_t *dst = s.Bsel + (uint64_t)rank * s.ld;
-        if (((((uintptr_t)dst) | ((uintptr_t)pk.payload)) & 3u) == 0) {
-            const uint64_t words = s.len >> 2;
-            for (uint64_t w = tid; w < words; w += 256)
-                reinterpret_cast<uint32_t *>(dst)[w] = reinterpret_cast<const uint32_t *>(pk.payload)[w];
-            for (uint64_t b = (words << 2) + tid; b < s.len; b += 256)
-                dst[b] = pk.payload[b];
-        } else {
-            for (uint64_t b = tid; b < s.len; b += 256)
-                dst[b] = pk.payload[b];
-        }
-        if (tid == 0)
+            Rl[rank * 64 + tid] = cw[tid];
+        if (tid == 0) {
             pivc[rank] = lead;
+            row_coef[rank] = pk.coef;
+            row_pay[rank] = pk.payload;
+        }
         rank++;
         __syncthreads();
+    }
+    // R back to device memory; the new rows' raw coefficients and payloads
+    for (int i = tid; i < rank * NW; i += 256) {
+        const int r = i / NW, w = i - r * NW;
+        reinterpret_cast<uint32_t *>(s.R + (uint64_t)r * s.rs)[w] = Rl[r * 64 + w];
+    }
+    for (int rr = rank0; rr < rank; rr++) {
+        const uint8_t *pc = row_coef[rr];
+        for (int b = tid; b < N; b += 256)
+            s.Csel[(uint64_t)rr * N + b] = pc[b];
+        const uint8_t *src = row_pay[rr];
+        uint8_t *dst = s.Bsel + (uint64_t)rr * s.ld;
+        if (((((uintptr_t)dst) | ((uintptr_t)src)) & 3u) == 0) {
+            const uint64_t words = s.len >> 2;
+            for (uint64_t w = tid; w < words; w += 256)
+                reinterpret_cast<uint32_t *>(dst)[w] = reinterpret_cast<const uint32_t *>(src)[w];
+            for (uint64_t b = (words << 2) + tid; b < s.len; b += 256)
+                dst[b] = src[b];
+        } else {
+            for (uint64_t b = tid; b < s.len; b += 256)
+                dst[b] = src[b];
+        }
     }
     for (int i = tid; i < rank; i += 256)
         s.meta[4 + i] = pivc[i];
@@ -1410,8 +1476,12 @@ __global__ __launch_bounds__(256) void k_absorb(const DevAbsorb *__restrict__ it
         s.meta[3] += dropped;
     }
     if (rank == N) {
-        __syncthreads();
-        invert_body<256>(s.Csel, N, s.Cinv, &inv_rank, ptab4, invg);
+        __syncthreads();   // Rl is free: the inversion reads the raw rows from their sources
+        invert_rows<256>(Rl,
+                         [&](int r) {
+                             return r < rank0 ? s.Csel + (uint64_t)r * N : row_coef[r];
+                         },
+                         N, s.Cinv, &inv_rank, ptab4, invg);
         __syncthreads();
         if (tid == 0) {
             __threadfence();
