@@ -1126,14 +1126,15 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
 // undone at the end as column swaps in reverse order.  Rows are stored with a
 // stride of MAXN bytes; a dword holds 4 consecutive entries, and each
 // row-times-constant update is one byte-permute product per dword.
-// A: the caller's LDS matrix of MAXN x MAXN bytes; row(r) gives the address
+// A: the caller's LDS matrix, MAXN rows of MAXN / 4 + 1 dwords; row(r) gives the address
 // of the matrix's row r (N bytes, device memory written before this kernel or
 // read-only input).
 template <int MAXN, class RowOf>
 __device__ void invert_rows(uint32_t *A, RowOf row, int N, uint8_t *__restrict__ Cinv, int *rank_out,
                             const uint4 *__restrict__ ptab4, const uint8_t *__restrict__ invg)
 {
-    constexpr int RW = MAXN / 4;   // dwords per row
+    constexpr int RW = MAXN / 4;   // dwords of a row
+    constexpr int PRW = RW + 1;    // row stride in LDS (odd: a column's bytes spread over the banks)
     __shared__ uint4 T[256][2];
     __shared__ uint8_t IV[256];
     __shared__ uint8_t fcol[MAXN];
@@ -1161,12 +1162,12 @@ __device__ void invert_rows(uint32_t *A, RowOf row, int N, uint8_t *__restrict__
                 if (c < N)
                     v |= (uint32_t)src[c] << (8 * b);
             }
-            A[r * RW + w] = v;
+            A[r * PRW + w] = v;
         }
     };
     // lowest row index >= from with a nonzero entry in column j (>= N if none)
     auto find_pivot = [&](int j, int from) -> int {
-        const bool ok = tid < N && tid >= from && Ab[tid * MAXN + j] != 0;
+        const bool ok = tid < N && tid >= from && Ab[tid * (4 * PRW) + j] != 0;
         const uint64_t m = __ballot(ok);
         if (lane == 0)
             cand[wave] = m ? wave * 64 + __builtin_ctzll(m) : (1 << 30);
@@ -1176,9 +1177,9 @@ __device__ void invert_rows(uint32_t *A, RowOf row, int N, uint8_t *__restrict__
     };
     auto swap_rows = [&](int a, int b) {
         if (a != b && tid < NW) {
-            const uint32_t t = A[a * RW + tid];
-            A[a * RW + tid] = A[b * RW + tid];
-            A[b * RW + tid] = t;
+            const uint32_t t = A[a * PRW + tid];
+            A[a * PRW + tid] = A[b * PRW + tid];
+            A[b * PRW + tid] = t;
         }
     };
 
@@ -1197,23 +1198,25 @@ __device__ void invert_rows(uint32_t *A, RowOf row, int N, uint8_t *__restrict__
             piv[j] = pr;
         __syncthreads();
         if (tid < NW) {   // wave 0 only: reads below happen before the write
-            uint32_t a = A[j * RW + tid];
-            const uint32_t pinv = IV[Ab[j * MAXN + j]];
+            uint32_t a = A[j * PRW + tid];
+            const uint32_t pinv = IV[Ab[j * (4 * PRW) + j]];
             if (tid == (j >> 2))
                 a = (a & ~(0xFFu << (8 * (j & 3)))) | (1u << (8 * (j & 3)));
-            A[j * RW + tid] = prod4(T[pinv][0], T[pinv][1].x, a);
+            A[j * PRW + tid] = prod4(T[pinv][0], T[pinv][1].x, a);
         }
         if (tid < N)
-            fcol[tid] = tid == j ? 0 : Ab[tid * MAXN + j];
+            fcol[tid] = tid == j ? 0 : Ab[tid * (4 * PRW) + j];
         __syncthreads();
         if (cl < NW) {   // thread: column dword cl of rows r0, r0 + RS, ...
-            const uint32_t pj = A[j * RW + cl];
+            // branch-free: where fcol is 0 the row's byte j is 0 already and the
+            // product is 0 (row j itself, whose fcol is 0, keeps its leading 1)
+            const uint32_t pj = A[j * PRW + cl];
             const uint32_t keep = cl == (j >> 2) ? ~(0xFFu << (8 * (j & 3))) : 0xFFFFFFFFu;
 #pragma unroll 4
             for (int i = r0; i < N; i += RS) {
                 const uint32_t f = fcol[i];
-                if (f)
-                    A[i * RW + cl] = (A[i * RW + cl] & keep) ^ prod4(T[f][0], T[f][1].x, pj);
+                const uint32_t k = i == j ? 0xFFFFFFFFu : keep;
+                A[i * PRW + cl] = (A[i * PRW + cl] & k) ^ prod4(T[f][0], T[f][1].x, pj);
             }
         }
         __syncthreads();
@@ -1232,7 +1235,7 @@ __device__ void invert_rows(uint32_t *A, RowOf row, int N, uint8_t *__restrict__
         __syncthreads();
         for (int it = tid; it < N * N; it += 256) {
             const int i = it / N, c = it - i * N;
-            Cinv[it] = Ab[i * MAXN + src[c]];
+            Cinv[it] = Ab[i * (4 * PRW) + src[c]];
         }
         if (tid == 0 && rank_out)
             *rank_out = N;
@@ -1253,21 +1256,20 @@ __device__ void invert_rows(uint32_t *A, RowOf row, int N, uint8_t *__restrict__
         swap_rows(pr, prow);
         __syncthreads();
         if (tid < NW) {
-            const uint32_t pinv = IV[Ab[prow * MAXN + j]];
-            const uint32_t a = A[prow * RW + tid];
-            A[prow * RW + tid] = prod4(T[pinv][0], T[pinv][1].x, a);
+            const uint32_t pinv = IV[Ab[prow * (4 * PRW) + j]];
+            const uint32_t a = A[prow * PRW + tid];
+            A[prow * PRW + tid] = prod4(T[pinv][0], T[pinv][1].x, a);
         }
         __syncthreads();
         if (tid < N)
-            fcol[tid] = tid > prow ? Ab[tid * MAXN + j] : 0;
+            fcol[tid] = tid > prow ? Ab[tid * (4 * PRW) + j] : 0;
         __syncthreads();
         if (cl < NW) {
-            const uint32_t pj = A[prow * RW + cl];
+            const uint32_t pj = A[prow * PRW + cl];
 #pragma unroll 4
             for (int i = r0; i < N; i += RS) {
                 const uint32_t f = fcol[i];
-                if (f)
-                    A[i * RW + cl] ^= prod4(T[f][0], T[f][1].x, pj);
+                A[i * PRW + cl] ^= prod4(T[f][0], T[f][1].x, pj);
             }
         }
         __syncthreads();
@@ -1282,7 +1284,7 @@ template <int MAXN>
 __device__ void invert_body(const uint8_t *__restrict__ Cg, int N, uint8_t *__restrict__ Cinv, int *rank_out,
                             const uint4 *__restrict__ ptab4, const uint8_t *__restrict__ invg)
 {
-    __shared__ uint32_t A[MAXN * (MAXN / 4)];
+    __shared__ uint32_t A[MAXN * (MAXN / 4 + 1)];
     invert_rows<MAXN>(A, [&](int r) { return Cg + (uint64_t)r * N; }, N, Cinv, rank_out, ptab4, invg);
 }
 
@@ -1329,7 +1331,7 @@ __global__ __launch_bounds__(256) void k_absorb(const DevAbsorb *__restrict__ it
                                                 const DevPacket *__restrict__ pkts, const uint4 *__restrict__ ptab4,
                                                 const uint8_t *__restrict__ invg)
 {
-    __shared__ uint32_t Rl[256 * 64];   // row r at Rl + 64 r; later the inversion's matrix
+    __shared__ uint32_t Rl[256 * 65];   // row r at Rl + 65 r (odd stride); later the inversion's matrix
     __shared__ uint32_t cw[64];
     __shared__ uint32_t part[4][64];
     __shared__ uint4 T[256][2];
@@ -1345,7 +1347,7 @@ __global__ __launch_bounds__(256) void k_absorb(const DevAbsorb *__restrict__ it
     const DevDecSlot &s = it.s;
     const int N = (int)s.N, NW = (N + 3) >> 2;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint8_t *Rb = reinterpret_cast<const uint8_t *>(Rl);
+    const uint8_t *Rb = reinterpret_cast<const uint8_t *>(Rl);   // row r at byte 260 r
 
     int rank = s.meta[0];
     if (rank >= N || N > 256)
@@ -1358,7 +1360,7 @@ __global__ __launch_bounds__(256) void k_absorb(const DevAbsorb *__restrict__ it
         pivc[i] = s.meta[4 + i];
     for (int i = tid; i < rank * NW; i += 256) {
         const int r = i / NW, w = i - r * NW;
-        Rl[r * 64 + w] = reinterpret_cast<const uint32_t *>(s.R + (uint64_t)r * s.rs)[w];
+        Rl[r * 65 + w] = reinterpret_cast<const uint32_t *>(s.R + (uint64_t)r * s.rs)[w];
     }
     // coefficient dword tid of a packet (lanes tid < NW)
     auto coef_dword = [&](const uint8_t *c) {
@@ -1396,10 +1398,9 @@ __global__ __launch_bounds__(256) void k_absorb(const DevAbsorb *__restrict__ it
         if (lane < NW) {   // wave w sums rows w, w + 4, ... of column dword `lane`
             uint32_t acc = 0;
 #pragma unroll 4
-            for (int r = wave; r < rank; r += 4) {
+            for (int r = wave; r < rank; r += 4) {   // a zero factor adds a zero product
                 const uint32_t f = fcol[r];
-                if (f)
-                    acc ^= prod4(T[f][0], T[f][1].x, Rl[r * 64 + lane]);
+                acc ^= prod4(T[f][0], T[f][1].x, Rl[r * 65 + lane]);
             }
             part[wave][lane] = acc;
         }
@@ -1425,19 +1426,18 @@ __global__ __launch_bounds__(256) void k_absorb(const DevAbsorb *__restrict__ it
             cw[tid] = prod4(T[iv][0], T[iv][1].x, cw[tid]);
         }
         for (int r = tid; r < rank; r += 256)
-            fcol[r] = Rb[r * 256 + lead];
+            fcol[r] = Rb[r * 260 + lead];
         __syncthreads();
         if (lane < NW) {   // wave w clears the new pivot column from rows w, w + 4, ...
             const uint32_t c = cw[lane];
 #pragma unroll 4
             for (int r = wave; r < rank; r += 4) {
                 const uint32_t f = fcol[r];
-                if (f)
-                    Rl[r * 64 + lane] ^= prod4(T[f][0], T[f][1].x, c);
+                Rl[r * 65 + lane] ^= prod4(T[f][0], T[f][1].x, c);
             }
         }
         if (tid < NW)
-            Rl[rank * 64 + tid] = cw[tid];
+            Rl[rank * 65 + tid] = cw[tid];
         if (tid == 0) {
             pivc[rank] = lead;
             row_coef[rank] = pk.coef;
@@ -1449,7 +1449,7 @@ __global__ __launch_bounds__(256) void k_absorb(const DevAbsorb *__restrict__ it
     // R back to device memory; the new rows' raw coefficients and payloads
     for (int i = tid; i < rank * NW; i += 256) {
         const int r = i / NW, w = i - r * NW;
-        reinterpret_cast<uint32_t *>(s.R + (uint64_t)r * s.rs)[w] = Rl[r * 64 + w];
+        reinterpret_cast<uint32_t *>(s.R + (uint64_t)r * s.rs)[w] = Rl[r * 65 + w];
     }
     for (int rr = rank0; rr < rank; rr++) {
         const uint8_t *pc = row_coef[rr];
