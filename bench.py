@@ -226,7 +226,7 @@ def main():
         import oracle
         Y_host = Y_dev.cpu().numpy()
         order = np.argsort(synth.words(synth.key(synth.BASE_SEED + 2, 99), args.count))
-        budget = args.cpu_seconds * 4.0e7          # byte-madds the plain oracle does in about that time
+        budget = args.cpu_seconds * 1.2e8          # byte-madds the plain oracle does in about that time
         picked, acc = [], 0
         for i in order:
             w = int(b.Ks[i] * b.Ns[i] * b.Ls[i])
@@ -325,7 +325,8 @@ def uniform_plan(gf, torch, n: int, K: int, N: int, L: int, count: int, seed: in
 
 def extra_workloads(gf, torch, args) -> dict:
     """The other measured workloads: one generation (latency), the plain field/length sweep,
-    the uneven batch over GF(16), the batched decode and a K sweep at fixed packet length."""
+    the uneven batch over GF(16), recoding at a relay, the batched decode and a K sweep at fixed
+    packet length."""
     out = {}
     # ---- one generation: GF(256), 16 x 16 x 1500 B, encode and decode back (latency, one launch each)
     g = synth.single_generation()
@@ -397,6 +398,33 @@ def extra_workloads(gf, torch, args) -> dict:
     log("uneven GF(16): %.1f GB/s" % (b.source_bytes / ms / 1e6))
     plan.destroy()
     del plan, S_dev, C_dev, Y_dev
+    torch.cuda.empty_cache()
+
+    # ---- recoding at a relay: the uneven GF(256) shapes; each relay holds M = N received packets
+    # and sends Kout = N recoded ones.  Packets are rows [N coefficients | payload], 16-byte pitch.
+    b = synth.uneven_batch(8, args.count, seed_off=7)
+    Ns, Ls = b.Ns.astype(np.int64), b.Ls.astype(np.int64)
+    lds = np.array([synth.padded(int(N + L)) for N, L in zip(Ns, Ls)], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(Ns * lds)])
+    In_dev = torch.from_numpy(synth.random_bytes(synth.key(b.seed, 14), int(offs[-1]))).to("cuda")
+    Out_dev = torch.empty(int(offs[-1]), dtype=torch.uint8, device="cuda")
+    R_dev = torch.from_numpy(b.coef_blob()).to("cuda")
+    descs = (gf.gf_recode_desc * args.count)()
+    i0, o0, r0 = In_dev.data_ptr(), Out_dev.data_ptr(), R_dev.data_ptr()
+    for i in range(args.count):
+        N, L, ld, off = int(Ns[i]), int(Ls[i]), int(lds[i]), int(offs[i])
+        descs[i] = gf.gf_recode_desc(r0 + int(b.c_off[i]), i0 + off, i0 + off + N, o0 + off, o0 + off + N,
+                                     N, N, N, 0, L, ld, ld, ld, ld)
+    plan = gf.gf_plan_recode_desc(8, descs, args.count, keep=(In_dev, Out_dev, R_dev))
+    ms = time_ms(torch, lambda: gf.gf_plan_launch_graph(plan), reps=5, warm=2)
+    out["recode_uneven_gf256"] = {"relays": args.count, "received_payload_bytes": b.source_bytes,
+                                  "header_bytes": int((Ns * Ns).sum()), "layout": "packet rows [coefficients | payload]",
+                                  "gbs": round(b.source_bytes / ms / 1e6, 2), "ms": round(ms, 3),
+                                  "form": plan.tuning()["form"],
+                                  "launch": "hip graph, 1 persistent kernel (header and payload in one product)"}
+    log("recode, uneven GF(256): %.1f GB/s of received payload, %.3f ms" % (b.source_bytes / ms / 1e6, ms))
+    plan.destroy()
+    del plan, In_dev, Out_dev, R_dev
     torch.cuda.empty_cache()
 
     # ---- batched decode: 2048 systems, N in {32, 64, 128}, 1500 B, GF(256)

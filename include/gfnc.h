@@ -184,6 +184,46 @@ void gf_plan_destroy(gf_plan *plan);
  * gf_encode per descriptor, on `stream`.  gens is a HOST array. */
 int gf_encode_each(int field, const gf_gen *gens, int count, const gf_tuning *tune, void *stream);
 
+/* ------------------------------------------------------------ recoding
+ * A node in the network sends linear combinations of coded packets it has
+ * received (Sec. I), without decoding them first.  Its M received packets
+ * carry coefficient vectors Cin (M x N, over the generation's N source
+ * packets) and payloads Bin; with a local Kout x M matrix R it sends
+ *     Cout = R * Cin   (Kout x N: the new packets' coefficient vectors)
+ *     Yout = R * Bin   (Kout payloads of len bytes)
+ * so that Yout = Cout * S still holds for the generation's sources S, and a
+ * receiver decodes recoded packets exactly like encoded ones.
+ * R: device, Kout x M row-major.  Cin: M rows of N elements, ld_cin apart;
+ * Cout: Kout rows of N, ld_cout apart; Bin: M rows of len bytes, ld_b apart;
+ * Yout: Kout rows, ld_y apart (outputs overwritten).  Entries of R and Cin are
+ * field elements (< q).  Outputs must not overlap inputs or each other.
+ * 1 <= M <= GF_MAX_N, 1 <= N <= GF_MAX_N, Kout >= 0.
+ * Packet layout: when every packet is one row holding its coefficient vector
+ * followed by its payload (Bin == Cin + N, Yout == Cout + N, ld_b == ld_cin,
+ * ld_y == ld_cout), header and payload are one product over N + len bytes;
+ * otherwise the header product is enqueued first, then the payload's. */
+int gf_recode(int field, const uint8_t *R, int Kout, int M, int N, const uint8_t *Cin, size_t ld_cin,
+              const uint8_t *Bin, size_t ld_b, uint8_t *Cout, size_t ld_cout, uint8_t *Yout, size_t ld_y,
+              size_t len, void *stream);
+
+typedef struct {
+    const uint8_t *R;     /* device, Kout x M */
+    const uint8_t *Cin;   /* device, M coefficient rows, ld_cin apart */
+    const uint8_t *Bin;   /* device, M payload rows, ld_b apart */
+    uint8_t *Cout;        /* device, Kout coefficient rows, ld_cout apart */
+    uint8_t *Yout;        /* device, Kout payload rows, ld_y apart */
+    uint32_t Kout, M, N, reserved;   /* reserved must be 0 */
+    uint64_t len, ld_cin, ld_b, ld_cout, ld_y;
+} gf_recode_desc;
+
+/* Plan for many recodings at once (descs: HOST array).  Launched with
+ * gf_encode_batched or gf_plan_launch_graph: one persistent launch over the
+ * headers that are not stored in front of their payloads (if any), then one
+ * over the payloads (with the headers that are), each autotuned like
+ * gf_plan_encode (form 0 runs trials that write the outputs).
+ * gf_plan_tuning reports the payload launch's schedule. */
+int gf_plan_recode(int field, const gf_recode_desc *descs, int count, const gf_tuning *tune, gf_plan **out);
+
 /* ------------------------------------------------------------ serving
  * Continuous batching of encode and decode requests on one device.
  *

@@ -59,6 +59,8 @@ def lib():
             "gfo_encode": (C.c_int, [C.c_int, _u8p, C.c_int, C.c_int, _u8p, C.c_size_t,
                                      _u8p, C.c_size_t, C.c_size_t]),
             "gfo_matmul": (C.c_int, [C.c_int, _u8p, _u8p, _u8p, C.c_int, C.c_int, C.c_int]),
+            "gfo_recode": (C.c_int, [C.c_int, _u8p, C.c_int, C.c_int, C.c_int, _u8p, _u8p, C.c_size_t,
+                                     _u8p, _u8p, C.c_size_t, C.c_size_t]),
             "gfo_rank": (C.c_int, [C.c_int, _u8p, C.c_int, C.c_int]),
             "gfo_invert": (C.c_int, [C.c_int, _u8p, C.c_int, _u8p]),
             "gfo_decode": (C.c_int, [C.c_int, _u8p, _u8p, C.c_size_t, C.c_int, _u8p,
@@ -190,6 +192,23 @@ def matmul(n: int, P: np.ndarray, Q: np.ndarray) -> np.ndarray:
     R = np.zeros((a, c), np.uint8)
     lib().gfo_matmul(n, _p(P), _p(Q), _p(R), a, b, c)
     return R
+
+
+def recode(n: int, R: np.ndarray, Cin: np.ndarray, Bin: np.ndarray):
+    """(Cout, Yout) = (R * Cin, R * Bin): recoding M received coded packets with a
+    Kout x M matrix R (Sec. I)."""
+    R = _u8(R)
+    Cin = _u8(Cin)
+    Bin = _u8(Bin)
+    Kout, M = R.shape
+    assert Cin.shape[0] == M and Bin.shape[0] == M
+    N = Cin.shape[1]
+    length = Bin.shape[1]
+    Cout = np.zeros((Kout, N), np.uint8)
+    Yout = np.zeros((Kout, length), np.uint8)
+    rc = lib().gfo_recode(n, _p(R), Kout, M, N, _p(Cin), _p(Bin), length, _p(Cout), _p(Yout), length, length)
+    assert rc == 0
+    return Cout, Yout
 
 
 def rank(n: int, M: np.ndarray) -> int:

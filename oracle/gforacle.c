@@ -231,6 +231,21 @@ int gfo_matmul(int n, const uint8_t *P, const uint8_t *Q, uint8_t *R, int a, int
     return 0;
 }
 
+/* Recoding (Sec. I): a node combines M coded packets it received -- each a
+ * coefficient vector over the N source packets plus a payload -- with a
+ * local Kout x M matrix R.  The new coefficient vectors are the element
+ * product Cout = R * Cin; the new payloads are Eq. (1) applied to the
+ * received payloads, Yout = R * Bin. */
+int gfo_recode(int n, const uint8_t *R, int Kout, int M, int N, const uint8_t *Cin,
+               const uint8_t *Bin, size_t ld_b, uint8_t *Cout, uint8_t *Yout, size_t ld_y, size_t len)
+{
+    if (!gfo_valid_field(n) || Kout < 0 || M < 0 || N < 0)
+        return -1;
+    if (gfo_matmul(n, R, Cin, Cout, Kout, M, N) != 0)
+        return -1;
+    return gfo_encode(n, R, Kout, M, Bin, ld_b, Yout, ld_y, len);
+}
+
 /* ------------------------------------------------------ Gauss-Jordan core */
 
 /* Row-reduce the rows x cols matrix M in place, applying every row operation

@@ -55,6 +55,13 @@ class gf_sys(C.Structure):
                 ("reserved", C.c_uint32), ("len", C.c_uint64), ("ld_b", C.c_uint64), ("ld_s", C.c_uint64)]
 
 
+class gf_recode_desc(C.Structure):
+    _fields_ = [("R", C.c_void_p), ("Cin", C.c_void_p), ("Bin", C.c_void_p), ("Cout", C.c_void_p),
+                ("Yout", C.c_void_p), ("Kout", C.c_uint32), ("M", C.c_uint32), ("N", C.c_uint32),
+                ("reserved", C.c_uint32), ("len", C.c_uint64), ("ld_cin", C.c_uint64), ("ld_b", C.c_uint64),
+                ("ld_cout", C.c_uint64), ("ld_y", C.c_uint64)]
+
+
 class gf_tuning(C.Structure):
     _fields_ = [("form", C.c_int), ("bytes_per_lane", C.c_int), ("grid_blocks", C.c_int),
                 ("reserved", C.c_int)]
@@ -82,6 +89,10 @@ _SIGS = {
     "gf_plan_tuning": (C.c_int, [C.c_void_p, C.POINTER(gf_tuning)]),
     "gf_plan_destroy": (None, [C.c_void_p]),
     "gf_encode_each": (C.c_int, [C.c_int, C.POINTER(gf_gen), C.c_int, C.POINTER(gf_tuning), C.c_void_p]),
+    "gf_recode": (C.c_int, [C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p,
+                            C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t, C.c_size_t, C.c_void_p]),
+    "gf_plan_recode": (C.c_int, [C.c_int, C.POINTER(gf_recode_desc), C.c_int, C.POINTER(gf_tuning),
+                                 C.POINTER(C.c_void_p)]),
 }
 
 #: every symbol the header declares
@@ -338,6 +349,45 @@ def gf_encode_each(field: int, gens, count: Optional[int] = None, tune: Optional
 
 
 # ------------------------------------------------------------------ serving
+
+def _recode_desc(R, Cin, Bin, Cout, Yout, length=None) -> gf_recode_desc:
+    """Rows may be views into larger buffers (e.g. packets stored as [coefficients | payload] rows)."""
+    Kout, M, _ = _rows(R, "R")
+    M2, N, ld_cin = _rows(Cin, "Cin")
+    K2, N2, ld_cout = _rows(Cout, "Cout")
+    nB, lB, ld_b = _rows(Bin, "Bin")
+    nY, lY, ld_y = _rows(Yout, "Yout")
+    L = min(lB, lY) if length is None else length
+    if not R.is_contiguous():
+        raise ValueError("R must be contiguous")
+    if M2 < M or K2 < Kout or N2 != N or nB < M or nY < Kout or L > lB or L > lY:
+        raise ValueError("shape mismatch")
+    return gf_recode_desc(R.data_ptr(), Cin.data_ptr(), Bin.data_ptr(), Cout.data_ptr(), Yout.data_ptr(), Kout, M,
+                          N, 0, L, ld_cin, ld_b, ld_cout, ld_y)
+
+
+def gf_recode(field: int, R, Cin, Bin, Cout, Yout, length: Optional[int] = None, stream=None):
+    """Cout = R * Cin and Yout[:, :length] = R * Bin over GF(2^field) (recoding received packets)."""
+    d = _recode_desc(R, Cin, Bin, Cout, Yout, length)
+    _check(lib().gf_recode(field, d.R, d.Kout, d.M, d.N, d.Cin, d.ld_cin, d.Bin, d.ld_b, d.Cout, d.ld_cout, d.Yout,
+                           d.ld_y, d.len, _stream(stream)), "gf_recode")
+
+
+def gf_plan_recode(field: int, items: Sequence[tuple], tune: Optional[dict] = None) -> Plan:
+    """items: (R, Cin, Bin, Cout, Yout) or (..., length) tensors per recoding; run with
+    gf_encode_batched or gf_plan_launch_graph."""
+    arr = (gf_recode_desc * len(items))(*[_recode_desc(*it) for it in items])
+    h = C.c_void_p()
+    _check(lib().gf_plan_recode(field, arr, len(items), _tuning(tune), C.byref(h)), "gf_plan_recode")
+    return Plan(h.value, "recode", len(items), list(items))
+
+
+def gf_plan_recode_desc(field: int, arr, count: int, tune: Optional[dict] = None, keep=None) -> Plan:
+    """Recode plan from a ctypes array of gf_recode_desc built by the caller."""
+    h = C.c_void_p()
+    _check(lib().gf_plan_recode(field, arr, count, _tuning(tune), C.byref(h)), "gf_plan_recode")
+    return Plan(h.value, "recode", count, keep)
+
 
 class gf_serve_config(C.Structure):
     _fields_ = [("field", C.c_int), ("max_slots", C.c_int), ("burst", C.c_int), ("dry_run", C.c_int),

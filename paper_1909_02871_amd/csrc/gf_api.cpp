@@ -138,7 +138,7 @@ Single pick_single(int K, int N, uint64_t len, uint32_t align, int cus)
 // =========================================================================
 
 struct gf_plan {
-    int kind = 0;     // 0 encode, 1 decode
+    int kind = 0;     // 0 encode, 1 decode, 2 recode (payloads here, headers in `head`)
     int field = 8;
     int dev = 0;
     int count = 0;
@@ -167,6 +167,8 @@ struct gf_plan {
     int *graph_rank = nullptr;
     // host copy of the descriptors (for gf_encode_each-style diagnostics)
     std::vector<gf_gen> gens;
+    // recode: the encode plan of the coefficient headers, launched first
+    gf_plan *head = nullptr;
 };
 
 int gfnc::gfnc_field_tables(int field, const uint32_t **ptab, const uint8_t **inv)
@@ -397,6 +399,11 @@ static void plan_free_device(gf_plan *p)
     (void)hipFree(p->d_sys);
     (void)hipFree(p->d_cinv);
     (void)hipFree(p->d_rank);
+    if (p->head) {
+        plan_free_device(p->head);
+        delete p->head;
+        p->head = nullptr;
+    }
 }
 
 }  // extern "C"
@@ -650,9 +657,7 @@ static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, co
     return hipDeviceSynchronize() == hipSuccess ? GF_OK : GF_EDEVICE;
 }
 
-extern "C" {
-
-int gf_plan_encode(int field, const gf_gen *gens, int count, const gf_tuning *tune, gf_plan **out)
+static int plan_encode_impl(int field, const gf_gen *gens, int count, const gf_tuning *tune, gf_plan **out)
 {
     if (!out)
         return GF_EINVAL;
@@ -681,6 +686,123 @@ int gf_plan_encode(int field, const gf_gen *gens, int count, const gf_tuning *tu
         delete p;
         return rc;
     }
+    *out = p;
+    return GF_OK;
+}
+
+extern "C" {
+
+int gf_plan_encode(int field, const gf_gen *gens, int count, const gf_tuning *tune, gf_plan **out)
+{
+    return plan_encode_impl(field, gens, count, tune, out);
+}
+
+// One recoding as encode descriptors.  Coefficients are single field
+// elements, so the word-wise product of the encode kernels equals the element
+// product on them.  When each packet is one row [coefficients | payload] in
+// both input and output, header and payload are one product over N + len
+// bytes (returns 1, `pay` only); otherwise the header Cout = R * Cin and the
+// payload Yout = R * Bin are separate products (returns 2).
+static int recode_gens(const gf_recode_desc &r, gf_gen &head, gf_gen &pay)
+{
+    if (r.Bin == r.Cin + r.N && r.Yout == r.Cout + r.N && r.ld_b == r.ld_cin && r.ld_y == r.ld_cout) {
+        pay = gf_gen{r.R, r.Cin, r.Cout, r.Kout, r.M, r.N + r.len, r.ld_cin, r.ld_cout};
+        return 1;
+    }
+    head = gf_gen{r.R, r.Cin, r.Cout, r.Kout, r.M, (uint64_t)r.N, r.ld_cin, r.ld_cout};
+    pay = gf_gen{r.R, r.Bin, r.Yout, r.Kout, r.M, r.len, r.ld_b, r.ld_y};
+    return 2;
+}
+
+// Rows `a` (la bytes) and `b` (lb bytes) share the pitch ld: they are
+// disjoint when b sits in the gap after a's bytes within each row, or a in
+// the gap after b's.
+static bool rows_interleave(const uint8_t *a, size_t la, const uint8_t *b, size_t lb, size_t ld)
+{
+    const intptr_t d = (intptr_t)b - (intptr_t)a;
+    return (d >= (intptr_t)la && (size_t)d + lb <= ld) || (-d >= (intptr_t)lb && (size_t)(-d) + la <= ld);
+}
+
+static int check_recode_args(int field, const gf_recode_desc &r)
+{
+    if (r.reserved || r.N < 1 || r.M < 1)
+        return GF_EINVAL;
+    if (r.N > GF_MAX_N || r.M > GF_MAX_N)
+        return GF_ERANGE;
+    if ((r.M > 1 && r.ld_cin < r.N) || (r.Kout > 1 && r.ld_cout < r.N))
+        return GF_EINVAL;
+    gf_gen h, y;
+    if (recode_gens(r, h, y) == 1)
+        return check_encode_args(field, y.C, (int)y.K, (int)y.N, y.S, y.ld_s, y.Y, y.ld_y, y.len);
+    int rc = check_encode_args(field, h.C, (int)h.K, (int)h.N, h.S, h.ld_s, h.Y, h.ld_y, h.len);
+    if (!rc)
+        rc = check_encode_args(field, y.C, (int)y.K, (int)y.N, y.S, y.ld_s, y.Y, y.ld_y, y.len);
+    if (rc || r.Kout == 0)
+        return rc;
+    // each output against the other product's operands, and the two outputs
+    const size_t eh = envelope(r.Kout, r.ld_cout, r.N);
+    if (overlap(h.Y, eh, r.Bin, envelope(r.M, r.ld_b, r.len)))
+        return GF_EINVAL;
+    if (r.len) {
+        const size_t ey = envelope(r.Kout, r.ld_y, r.len);
+        if (overlap(y.Y, ey, r.Cin, envelope(r.M, r.ld_cin, r.N)))
+            return GF_EINVAL;
+        const bool apart = r.Kout == 1 ? !overlap(h.Y, r.N, y.Y, r.len)
+                           : r.ld_cout == r.ld_y && rows_interleave(h.Y, r.N, y.Y, r.len, r.ld_y);
+        if (!apart && overlap(y.Y, ey, h.Y, eh))
+            return GF_EINVAL;
+    }
+    return GF_OK;
+}
+
+int gf_recode(int field, const uint8_t *R, int Kout, int M, int N, const uint8_t *Cin, size_t ld_cin,
+              const uint8_t *Bin, size_t ld_b, uint8_t *Cout, size_t ld_cout, uint8_t *Yout, size_t ld_y,
+              size_t len, void *stream)
+{
+    if (Kout < 0 || M < 1 || N < 1)
+        return GF_EINVAL;
+    const gf_recode_desc r{R, Cin, Bin, Cout, Yout, (uint32_t)Kout, (uint32_t)M, (uint32_t)N, 0,
+                           len, ld_cin, ld_b, ld_cout, ld_y};
+    int rc = check_recode_args(field, r);
+    if (rc || Kout == 0)
+        return rc;
+    gf_gen h, y;
+    if (recode_gens(r, h, y) == 2 &&
+        (rc = encode_impl(field, h.C, (int)h.K, (int)h.N, h.S, h.ld_s, h.Y, h.ld_y, h.len, nullptr, nullptr, 0,
+                          stream)))
+        return rc;
+    if (y.len == 0)
+        return GF_OK;
+    return encode_impl(field, y.C, (int)y.K, (int)y.N, y.S, y.ld_s, y.Y, y.ld_y, y.len, nullptr, nullptr, 0,
+                       stream);
+}
+
+int gf_plan_recode(int field, const gf_recode_desc *descs, int count, const gf_tuning *tune, gf_plan **out)
+{
+    if (!out)
+        return GF_EINVAL;
+    *out = nullptr;
+    if (!valid_field(field) || count < 0 || (count > 0 && !descs))
+        return GF_EINVAL;
+    std::vector<gf_gen> heads, pays(count);
+    for (int i = 0; i < count; i++) {
+        int rc = check_recode_args(field, descs[i]);
+        if (rc)
+            return rc;
+        gf_gen h;
+        if (recode_gens(descs[i], h, pays[i]) == 2)
+            heads.push_back(h);
+    }
+    gf_plan *head = nullptr, *p = nullptr;
+    int rc = heads.empty() ? GF_OK : plan_encode_impl(field, heads.data(), (int)heads.size(), tune, &head);
+    if (rc)
+        return rc;
+    if ((rc = plan_encode_impl(field, pays.data(), count, tune, &p))) {
+        gf_plan_destroy(head);
+        return rc;
+    }
+    p->kind = 2;
+    p->head = head;
     *out = p;
     return GF_OK;
 }
@@ -760,6 +882,8 @@ static int run_plan(gf_plan *p, int *d_rank, hipStream_t s)
     if (rc)
         return rc;
     const int f = p->field;
+    if (p->head && (rc = run_plan(p->head, nullptr, s)))
+        return rc;
     if (p->kind == 1) {
         for (int c = 0; c < 4; c++) {
             if (p->class_count[c] == 0)
@@ -780,7 +904,7 @@ static int run_plan(gf_plan *p, int *d_rank, hipStream_t s)
 
 int gf_encode_batched(gf_plan *p, void *stream)
 {
-    if (!p || p->kind != 0)
+    if (!p || p->kind == 1)
         return GF_EINVAL;
     return run_plan(p, nullptr, (hipStream_t)stream);
 }

@@ -115,3 +115,42 @@ def test_plan_argument_checks():
     assert L.gf_decode_batched(None, None, None) == gf.GF_EINVAL
     assert L.gf_plan_launch_graph(None, None, None) == gf.GF_EINVAL
     L.gf_plan_destroy(None)
+
+
+def test_recode_argument_checks():
+    L = gf.lib()
+    # R: P1 (Kout x M = 4 x 3), Cin: P2 (3 rows of N = 5, pitch 5), Bin: P3 (3 x 100), Cout/Yout in P4
+    def rc(R=P1, K=4, M=3, N=5, Cin=P2, ldc=5, Bin=P3, ldb=100, Cout=P4, ldco=5, Yout=P4 + 4096, ldy=100,
+           length=100):
+        return L.gf_recode(8, R, K, M, N, Cin, ldc, Bin, ldb, Cout, ldco, Yout, ldy, length, None)
+    assert rc(K=0) == gf.GF_OK                       # nothing to send
+    assert rc(M=0) == gf.GF_EINVAL
+    assert rc(N=0) == gf.GF_EINVAL
+    assert rc(M=257) == gf.GF_ERANGE
+    assert rc(N=257) == gf.GF_ERANGE
+    assert rc(ldc=4) == gf.GF_EINVAL                 # coefficient rows narrower than N
+    assert rc(ldco=4) == gf.GF_EINVAL
+    assert rc(ldb=50) == gf.GF_EINVAL                # payload pitch below len
+    assert rc(Cout=P2 + 1) == gf.GF_EINVAL           # Cout over Cin
+    assert rc(Cout=P3 + 7) == gf.GF_EINVAL           # Cout over Bin
+    assert rc(Yout=P2) == gf.GF_EINVAL               # Yout over Cin
+    assert rc(Yout=P4 + 2) == gf.GF_EINVAL           # Yout over Cout
+    assert rc(Yout=P1 + 1) == gf.GF_EINVAL           # Yout over R
+    # packets as rows [coefficients | payload] (the accepted layout is run by the GPU tests): the
+    # payload may not run into the next row's coefficients
+    assert rc(Cin=P2, ldc=104, Bin=P2 + 5, ldb=104, Cout=P4, ldco=104, Yout=P4 + 5, ldy=104, length=100) == \
+        gf.GF_EINVAL
+
+
+def test_plan_recode_argument_checks():
+    L = gf.lib()
+    h = C.c_void_p()
+    d = gf.gf_recode_desc(P1, P2, P3, P4, P4 + 4096, 4, 3, 5, 1, 100, 5, 100, 5, 100)   # reserved != 0
+    assert L.gf_plan_recode(8, (gf.gf_recode_desc * 1)(d), 1, None, C.byref(h)) == gf.GF_EINVAL
+    d.reserved, d.M = 0, 300
+    assert L.gf_plan_recode(8, (gf.gf_recode_desc * 1)(d), 1, None, C.byref(h)) == gf.GF_ERANGE
+    d.M, d.Yout = 3, P2 + 1
+    assert L.gf_plan_recode(8, (gf.gf_recode_desc * 1)(d), 1, None, C.byref(h)) == gf.GF_EINVAL
+    assert L.gf_plan_recode(5, (gf.gf_recode_desc * 1)(d), 1, None, C.byref(h)) == gf.GF_EINVAL
+    assert L.gf_plan_recode(8, None, 1, None, C.byref(h)) == gf.GF_EINVAL
+    assert not h.value

@@ -374,3 +374,165 @@ def test_batched_decode(gf, n, layout):
                 assert (host(out) == 0x3C).all()
             else:
                 assert (host(out) == w).all()
+
+
+# ------------------------------------------------------------------ recoding
+
+def _relay(n, seed, Kout, M, N, L):
+    """Inputs of one recoding: R (Kout x M), received headers Cin (M x N) and
+    payloads Bin (M x L).  Recoding is linear in Bin, so random bytes serve."""
+    R = synth.uniform_field(synth.key(seed, 1), Kout * M, n).reshape(Kout, M)
+    Cin = synth.uniform_field(synth.key(seed, 2), M * N, n).reshape(M, N)
+    Bin = synth.random_bytes(synth.key(seed, 3), M * L).reshape(M, L)
+    return R, Cin, Bin
+
+
+@pytest.mark.parametrize("n", FIELDS)
+@pytest.mark.parametrize("Kout,M,N,L", [(1, 1, 1, 1), (5, 9, 7, 1000), (24, 64, 33, 1501), (40, 256, 256, 4099),
+                                       (3, 17, 200, 0), (0, 4, 4, 10)])
+def test_recode(gf, n, Kout, M, N, L):
+    torch = torch_cuda()
+    R, Cin, Bin = _relay(n, synth.key(70, n, Kout, M, N, L), Kout, M, N, L)
+    wantC, wantY = oracle.recode(n, R, Cin, Bin)
+    Cout = torch.full((Kout, N), 0x5A, dtype=torch.uint8, device="cuda")
+    Yout = torch.full((Kout, L), 0x5A, dtype=torch.uint8, device="cuda")
+    gf.gf_recode(n, dev(R), dev(Cin), dev(Bin), Cout, Yout)
+    torch.cuda.synchronize()
+    assert (host(Cout) == wantC).all()
+    assert (host(Yout) == wantY).all()
+
+
+@pytest.mark.parametrize("n", [1, 8])
+def test_recoded_packets_decode_on_gpu(gf, n):
+    """Encode, recode at a relay, decode at the receiver -- all on the GPU --
+    gives back the sources (Sec. I)."""
+    torch = torch_cuda()
+    N, M, L = 48, 60, 2000
+    S = synth.random_bytes(synth.key(71, n), N * L).reshape(N, L)
+    Cin = _invertible(n, N, synth.key(72, n))
+    Cin = np.concatenate([Cin, synth.uniform_field(synth.key(73, n), (M - N) * N, n).reshape(M - N, N)])
+    Bd = torch.empty((M, L), dtype=torch.uint8, device="cuda")
+    gf.gf_encode(n, dev(Cin), dev(S), Bd)
+    attempt = 0
+    while True:   # a relay matrix whose recoded headers have full rank
+        R = synth.uniform_field(synth.key(74, n, attempt), N * M, n).reshape(N, M)
+        if oracle.rank(n, oracle.matmul(n, R, Cin)) == N:
+            break
+        attempt += 1
+    Cout = torch.empty((N, N), dtype=torch.uint8, device="cuda")
+    Yout = torch.empty((N, L), dtype=torch.uint8, device="cuda")
+    gf.gf_recode(n, dev(R), dev(Cin), Bd, Cout, Yout)
+    out = torch.zeros((N, L), dtype=torch.uint8, device="cuda")
+    rank = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    gf.gf_decode(n, Cout, Yout, out, d_rank=rank)
+    torch.cuda.synchronize()
+    assert int(host(rank)[0]) == N
+    assert (host(out) == S).all()
+
+
+@pytest.mark.parametrize("n", FIELDS)
+@pytest.mark.parametrize("form", [0, 1, 2])
+def test_batched_recode_and_graph(gf, n, form):
+    torch = torch_cuda()
+    items, wants = [], []
+    for i in range(50):
+        M = int(synth.uniform_ints(synth.key(75, n, i), 1, 1, 130)[0])
+        N = int(synth.uniform_ints(synth.key(76, n, i), 1, 1, 130)[0])
+        Kout = int(synth.uniform_ints(synth.key(77, n, i), 1, 0, 70)[0])
+        L = int(synth.log_uniform_ints(synth.key(78, n, i), 1, 1, 3000)[0])
+        R, Cin, Bin = _relay(n, synth.key(79, n, i), Kout, M, N, L)
+        wants.append(oracle.recode(n, R, Cin, Bin))
+        _, Bd = padded_rows(Bin, synth.padded(L))
+        _, Yd = padded_rows(np.zeros((Kout, L), np.uint8), synth.padded(L))
+        Cd = torch.zeros((Kout, N), dtype=torch.uint8, device="cuda")
+        items.append((dev(R), dev(Cin), Bd, Cd, Yd))
+    plan = gf.gf_plan_recode(n, items, {"form": form})
+    if form:
+        assert plan.tuning()["form"] == form
+    for mode in ("eager", "graph", "graph"):
+        for it in items:
+            it[3].fill_(0xC3)
+            it[4].fill_(0xC3)
+        torch.cuda.synchronize()
+        if mode == "eager":
+            gf.gf_encode_batched(plan)
+        else:
+            gf.gf_plan_launch_graph(plan)
+        torch.cuda.synchronize()
+        for it, (wc, wy) in zip(items, wants):
+            assert (host(it[3]) == wc).all(), mode
+            assert (host(it[4]) == wy).all(), mode
+
+
+def _packet_rows(Cm, B, ld, fill=0x77):
+    """Device buffer of packets stored as rows [coefficients | payload], `ld` bytes apart.
+    Returns (coefficient view, payload view)."""
+    torch = torch_cuda()
+    rows, N = Cm.shape
+    L = B.shape[1]
+    buf = torch.full((max(rows, 1) * ld,), fill, dtype=torch.uint8, device="cuda")
+    v = buf[:rows * ld].view(rows, ld)
+    if rows:
+        v[:, :N].copy_(torch.from_numpy(np.ascontiguousarray(Cm)).to("cuda"))
+        v[:, N:N + L].copy_(torch.from_numpy(np.ascontiguousarray(B)).to("cuda"))
+    return v[:, :N], v[:, N:N + L]
+
+
+@pytest.mark.parametrize("n", FIELDS)
+@pytest.mark.parametrize("Kout,M,N,L,ld", [(5, 9, 7, 1000, 1008), (33, 64, 64, 1500, 1568), (16, 200, 131, 777, 910),
+                                          (40, 256, 256, 4099, 4368)])
+def test_recode_packet_rows(gf, n, Kout, M, N, L, ld):
+    """Packets stored as one row each, coefficients in front of the payload
+    (header and payload become one product over N + len bytes)."""
+    torch = torch_cuda()
+    R, Cin, Bin = _relay(n, synth.key(80, n, Kout, M, N), Kout, M, N, L)
+    wantC, wantY = oracle.recode(n, R, Cin, Bin)
+    Ci, Bi = _packet_rows(Cin, Bin, ld)
+    Co, Yo = _packet_rows(np.zeros((Kout, N), np.uint8), np.zeros((Kout, L), np.uint8), ld, fill=0x11)
+    gf.gf_recode(n, dev(R), Ci, Bi, Co, Yo)
+    torch.cuda.synchronize()
+    assert (host(Co) == wantC).all()
+    assert (host(Yo) == wantY).all()
+    # the pitch padding after each output packet is left alone
+    full = host(Co.as_strided((Kout, ld), (ld, 1)))
+    assert (full[:, N + L:] == 0x11).all()
+
+
+@pytest.mark.parametrize("n", [2, 8])
+@pytest.mark.parametrize("form", [0, 2])
+def test_batched_recode_mixed_layouts(gf, n, form):
+    """A plan over relays of both layouts: packet rows (one fused product) and
+    separate header and payload buffers (header launch, then payload launch)."""
+    torch = torch_cuda()
+    items, wants = [], []
+    for i in range(40):
+        M = int(synth.uniform_ints(synth.key(81, n, i), 1, 1, 256)[0])
+        N = int(synth.uniform_ints(synth.key(82, n, i), 1, 1, 256)[0])
+        Kout = int(synth.uniform_ints(synth.key(83, n, i), 1, 0, 80)[0])
+        L = int(synth.log_uniform_ints(synth.key(84, n, i), 1, 64, 9000)[0])
+        R, Cin, Bin = _relay(n, synth.key(85, n, i), Kout, M, N, L)
+        wants.append(oracle.recode(n, R, Cin, Bin))
+        if i % 2 == 0:
+            ld = synth.padded(N + L)
+            Ci, Bi = _packet_rows(Cin, Bin, ld)
+            Co, Yo = _packet_rows(np.zeros((Kout, N), np.uint8), np.zeros((Kout, L), np.uint8), ld)
+        else:
+            Ci = dev(Cin)
+            _, Bi = padded_rows(Bin, synth.padded(L))
+            Co = torch.zeros((Kout, N), dtype=torch.uint8, device="cuda")
+            _, Yo = padded_rows(np.zeros((Kout, L), np.uint8), synth.padded(L))
+        items.append((dev(R), Ci, Bi, Co, Yo))
+    plan = gf.gf_plan_recode(n, items, {"form": form})
+    for mode in ("eager", "graph", "graph"):
+        for it in items:
+            it[3].fill_(0xE7)
+            it[4].fill_(0xE7)
+        torch.cuda.synchronize()
+        if mode == "eager":
+            gf.gf_encode_batched(plan)
+        else:
+            gf.gf_plan_launch_graph(plan)
+        torch.cuda.synchronize()
+        for i, (it, (wc, wy)) in enumerate(zip(items, wants)):
+            assert (host(it[3]) == wc).all(), (mode, i)
+            assert (host(it[4]) == wy).all(), (mode, i)
