@@ -149,12 +149,17 @@ typedef struct {
  * form 1: byte-select table lookups on the vector ALUs.
  * form 2: the product as a GF(2) bit-matrix multiply on the matrix cores;
  *         packets longer than 2^34 bytes are rejected with GF_ERANGE.
- * form 0 on an encode plan: both forms are timed on the plan's own batch
- * while the plan is created (which writes the plan's outputs) and the faster
- * is kept (form 1 alone if a packet is too long for form 2); on a decode plan
- * form 0 means form 2 when every coded row starts 4-byte aligned, else 1. */
+ * form 3: bit planes on the vector ALUs, GF(2), GF(4) and GF(16) only (the
+ *         coefficient split into its bits, Sec. IV-B's decomposition; one
+ *         3-input bit operation per row, source, plane and dword);
+ *         GF_EINVAL for GF(256).
+ * form 0 on an encode plan: every form that applies is timed on the plan's
+ * own batch while the plan is created (which writes the plan's outputs) and
+ * the fastest is kept (form 2 is skipped if a packet is too long for it); on
+ * a decode plan form 0 means form 2 when every coded row starts 4-byte
+ * aligned, else 1. */
 typedef struct {
-    int form;           /* 0 auto, 1 table, 2 bit-matrix */
+    int form;           /* 0 auto, 1 table, 2 bit-matrix, 3 bit-plane */
     int bytes_per_lane; /* 0 = per tile; else 4, 8 or 16 payload bytes per lane everywhere */
     int grid_blocks;    /* persistent workgroups; 0 = as many as fit on the GPU at once */
     int reserved;       /* must be 0 */

@@ -143,9 +143,9 @@ struct gf_plan {
     int dev = 0;
     int count = 0;
     int fixed_D = 0;   // 0: lane width chosen per tile
-    int form = 1;      // 1 table (VALU byte-select), 2 bit-matrix on the matrix cores
+    int form = 1;      // 1 table (VALU byte-select), 2 bit-matrix on the matrix cores, 3 bit-plane (VALU)
     bool src_aligned4 = false;   // every generation's source rows start 4-byte aligned
-    double tune_ms[3] = {0, 0, 0};   // autotuning trial times per form (0: not timed)
+    double tune_ms[4] = {0, 0, 0, 0};   // autotuning trial times per form (0: not timed)
     int grid = 0;
     int ntiles = 0;
     DevGen *d_gens = nullptr;
@@ -539,6 +539,8 @@ static int launch_schedule(gf_plan *p, DevState *d, hipStream_t s)
     if (p->form == 2)
         e = launch_encode_mfma(p->d_gens, p->d_tiles, p->d_runs, p->d_bounds, p->ntiles, p->d_ctr, p->grid,
                                field_rows(d, f), p->src_aligned4, s);
+    else if (p->form == 3)
+        e = launch_encode_planes(f, p->d_gens, p->d_tiles, p->d_runs, p->d_bounds, p->ntiles, p->d_ctr, p->grid, s);
     else
         e = launch_encode_persistent(p->d_gens, p->d_tiles, p->d_runs, p->d_bounds, p->ntiles, p->d_ctr, p->grid,
                                      field_ptab(d, f), s);
@@ -567,7 +569,9 @@ static int make_schedule(gf_plan *p, DevState *d, const std::vector<DevGen> &g, 
     if (rc)
         return rc;
     p->d_bounds = p->d_runs + tq.runs.size();
-    int grid = d->cus * (form == 2 ? encode_mfma_blocks_per_cu(p->src_aligned4) : encode_blocks_per_cu());
+    int grid = d->cus * (form == 2   ? encode_mfma_blocks_per_cu(p->src_aligned4)
+                         : form == 3 ? encode_planes_blocks_per_cu(p->field)
+                                     : encode_blocks_per_cu());
     if (tune && tune->grid_blocks > 0)
         grid = tune->grid_blocks;
     const int per_block = form == 2 ? 1 : 4;
@@ -595,8 +599,9 @@ static double time_schedule(gf_plan *p, DevState *d)
     return ms;
 }
 
-// form: 1 table, 2 bit-matrix; 0 = time both on the plan's own data and keep
-// the faster (only when `may_run` allows launching before the caller asks).
+// form: 1 table, 2 bit-matrix, 3 bit-plane (n <= 4); 0 = time each on the
+// plan's own data and keep the fastest (only when `may_run` allows launching
+// before the caller asks).
 static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, const gf_tuning *tune, bool may_run)
 {
     DevState *d;
@@ -609,7 +614,7 @@ static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, co
         p->fixed_D = tune->bytes_per_lane / 4;
     }
     int form = tune ? tune->form : 0;
-    if (form < 0 || form > 2)
+    if (form < 0 || form > 3 || (form == 3 && p->field > 4))
         return GF_EINVAL;
     std::vector<DevGen> g = gens;
     p->src_aligned4 = true;
@@ -639,10 +644,12 @@ static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, co
         form = p->src_aligned4 ? 2 : 1;
     if (form != 0)
         return make_schedule(p, d, g, form, tune);
-    // autotune: both forms on the real batch
+    // autotune: every form that applies, on the real batch
     double best = -1;
     int best_form = 1;
-    for (int f : {1, 2}) {
+    for (int f : {1, 2, 3}) {
+        if (f == 3 && p->field > 4)
+            continue;
         if ((rc = make_schedule(p, d, g, f, tune)))
             return rc;
         const double ms = time_schedule(p, d);

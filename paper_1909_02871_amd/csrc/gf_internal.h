@@ -76,6 +76,9 @@ struct DevSys {
 #ifndef GF_ENC_WAVES_PER_SIMD
 #define GF_ENC_WAVES_PER_SIMD 2
 #endif
+#ifndef GF_PLANE_WAVES_PER_SIMD
+#define GF_PLANE_WAVES_PER_SIMD 3   // bit-plane form, n <= 2 (n = 4 needs the registers of 2)
+#endif
 // Device state of one generation being decoded progressively (serving).
 struct DevDecSlot {
     uint8_t *R;      // reduced echelon rows of the innovative coefficient vectors, row stride rs
@@ -152,6 +155,10 @@ hipError_t launch_encode_mfma(const DevGen *gens, const DevTile *tiles, const un
                               int ntiles, unsigned *counters, int grid, const uint8_t *rows_field, bool aligned4,
                               hipStream_t s);
 int encode_mfma_blocks_per_cu(bool aligned4);
+// Bit-plane form (fields with n <= 4) over the table form's wave tiles.
+hipError_t launch_encode_planes(int field, const DevGen *gens, const DevTile *tiles, const unsigned *runs,
+                                const unsigned *bounds, int ntiles, unsigned *counters, int grid, hipStream_t s);
+int encode_planes_blocks_per_cu(int field);
 hipError_t launch_invert(const DevSys *sys, int count, const uint8_t *C, int N, uint8_t *Cinv, int *rank,
                          const uint32_t *ptab_field, const uint8_t *inv_field, hipStream_t s);
 int encode_blocks_per_cu();

@@ -54,18 +54,36 @@ __device__ __forceinline__ uint32_t prod4(const uint4 &ta, uint32_t tb, uint32_t
     return prod(ta.x, ta.y, ta.z, ta.w, tb, split(x));
 }
 
+// Plain loads and stores through the global address space: a generic (flat)
+// access also counts against the LDS wait counter, so an LDS read issued
+// after it would wait for the global load as well and undo the prefetch.
+typedef uint32_t gf_u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t gf_u32x2 __attribute__((ext_vector_type(2)));
+
+template <class T>
+__device__ __forceinline__ T gld(const void *p)
+{
+    return *reinterpret_cast<const __attribute__((address_space(1))) T *>(reinterpret_cast<uintptr_t>(p));
+}
+
+template <class T>
+__device__ __forceinline__ void gst(void *p, T v)
+{
+    *reinterpret_cast<__attribute__((address_space(1))) T *>(reinterpret_cast<uintptr_t>(p)) = v;
+}
+
 template <int D>
 __device__ __forceinline__ void load_row(const uint8_t *p, uint64_t avail, bool vec, uint32_t (&x)[D])
 {
     if (vec && avail >= 4u * D) {
         if constexpr (D == 4) {
-            const uint4 t = *reinterpret_cast<const uint4 *>(p);
+            const gf_u32x4 t = gld<gf_u32x4>(p);
             x[0] = t.x; x[1] = t.y; x[2] = t.z; x[3] = t.w;
         } else if constexpr (D == 2) {
-            const uint2 t = *reinterpret_cast<const uint2 *>(p);
+            const gf_u32x2 t = gld<gf_u32x2>(p);
             x[0] = t.x; x[1] = t.y;
         } else {
-            x[0] = *reinterpret_cast<const uint32_t *>(p);
+            x[0] = gld<uint32_t>(p);
         }
     } else {
 #pragma unroll
@@ -74,7 +92,7 @@ __device__ __forceinline__ void load_row(const uint8_t *p, uint64_t avail, bool 
 #pragma unroll
         for (int b = 0; b < 4 * D; b++)
             if ((uint64_t)b < avail)
-                x[b >> 2] |= (uint32_t)p[b] << (8 * (b & 3));
+                x[b >> 2] |= (uint32_t)gld<uint8_t>(p + b) << (8 * (b & 3));
     }
 }
 
@@ -83,17 +101,17 @@ __device__ __forceinline__ void store_row(uint8_t *p, uint64_t avail, bool vec, 
 {
     if (vec && avail >= 4u * D) {
         if constexpr (D == 4) {
-            *reinterpret_cast<uint4 *>(p) = make_uint4(x[0], x[1], x[2], x[3]);
+            gst<gf_u32x4>(p, gf_u32x4{x[0], x[1], x[2], x[3]});
         } else if constexpr (D == 2) {
-            *reinterpret_cast<uint2 *>(p) = make_uint2(x[0], x[1]);
+            gst<gf_u32x2>(p, gf_u32x2{x[0], x[1]});
         } else {
-            *reinterpret_cast<uint32_t *>(p) = x[0];
+            gst<uint32_t>(p, x[0]);
         }
     } else {
 #pragma unroll
         for (int b = 0; b < 4 * D; b++)
             if ((uint64_t)b < avail)
-                p[b] = (uint8_t)(x[b >> 2] >> (8 * (b & 3)));
+                gst<uint8_t>(p + b, (uint8_t)(x[b >> 2] >> (8 * (b & 3))));
     }
 }
 
@@ -276,7 +294,7 @@ __device__ __forceinline__ void wave_tile(const uint8_t *__restrict__ C, int K, 
 #pragma unroll
             for (int e = lane; e < KW * NCW; e += 64) {
                 const int kk = e / NCW, j = e % NCW;
-                const uint32_t c = (kk < kv && j < nc) ? (uint32_t)C[(uint64_t)(k0 + kk) * N + g + j] : 0u;
+                const uint32_t c = (kk < kv && j < nc) ? (uint32_t)gld<uint8_t>(C + (uint64_t)(k0 + kk) * N + g + j) : 0u;
                 st.t[kk][j][0] = ptab4[c * 2];
                 st.t[kk][j][1] = ptab4[c * 2 + 1];
             }
@@ -516,6 +534,192 @@ __global__ __launch_bounds__(256, GF_ENC_WAVES_PER_SIMD) void k_encode_waves(con
             else
                 wave_tile<1>(g.C, (int)g.K, (int)g.N, g.S, g.ld_s, g.Y, g.ld_y, g.len, (int)tl.k0, p0,
                              g.align >= 4, ptab4, stage[wave], lane, 0, (int)g.N, false, staged);
+        }
+    }
+    if (lane == 0)
+        queue_retire(counters, gridDim.x * WAVES);
+}
+
+// ------------------------------------------------------- encode, bit-plane form
+//
+// For n <= 4 a product is cheapest as the XOR of bit planes: with c = sum of
+// c_b alpha^b, c * x = XOR over b of c_b (alpha^b x), and alpha^b x is a few
+// shifts and masks of the packed words (the GF(2)-linearity behind the
+// paper's Alg. 2, with the coefficient split into bits instead of the data).
+// The planes of a source dword are built once and shared by every coded row
+// of the tile; each (row, source, plane) then costs one 3-input bit operation
+// per dword, acc ^ (plane & mask), where mask is all ones when bit b of the
+// coefficient is set.  The masks are staged in LDS per wave, the two sources
+// of a step side by side, so one uniform LDS read serves 2 n of them.
+
+// a ^ (b & c) in one instruction (truth table over src0 = 0xF0, src1 = 0xCC,
+// src2 = 0xAA); written out so the compiler keeps one per (row, source, plane)
+// instead of regrouping the XORs.
+__device__ __forceinline__ uint32_t and_xor(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x78);
+}
+
+// x times alpha for every n-bit word of x.
+template <int NB>
+__device__ __forceinline__ uint32_t times_alpha(uint32_t x)
+{
+    if constexpr (NB == 2) {
+        // x^2 = x + 1: (h, l) -> (h ^ l, h)
+        return ((x >> 1) & 0x55555555u) | ((x ^ (x << 1)) & 0xAAAAAAAAu);
+    } else {
+        // x^4 = x + 1: shift up within the nibble, the top bit folds into bits 0 and 1
+        const uint32_t t = x & 0x88888888u;
+        return ((x << 1) & 0xEEEEEEEEu) ^ (t >> 3) ^ (t >> 2);
+    }
+}
+
+constexpr int planes_per_stage(int NB) { return 64 / NB; }   // sources whose masks fit one stage
+
+template <int NB, int D>
+__device__ __forceinline__ void wave_tile_planes(const uint8_t *__restrict__ C, int K, int N,
+                                                 const uint8_t *__restrict__ S, uint64_t ld_s,
+                                                 uint8_t *__restrict__ Y, uint64_t ld_y, uint64_t len, int k0,
+                                                 uint64_t p0, bool vec, uint32_t *__restrict__ mk, int lane,
+                                                 bool staged)
+{
+    constexpr int NCP = planes_per_stage(NB);
+    static_assert(KW * NCP * NB * 4 <= (int)sizeof(WaveStage), "mask stage exceeds the wave's LDS");
+    const uint64_t p = p0 + (uint64_t)lane * (4u * D);
+    const uint64_t avail = p < len ? len - p : 0;
+    const int kv = min(KW, K - k0);
+
+    uint32_t acc[KW][D];
+#pragma unroll
+    for (int kk = 0; kk < KW; kk++)
+#pragma unroll
+        for (int d = 0; d < D; d++)
+            acc[kk][d] = 0;
+
+    // the pair of sources in use; the next pair is loaded while it is used
+    const uint8_t *src = S + p;
+    uint32_t xa[D], xb[D];
+    load_lane<D>(src, avail, vec, xa);
+    if (N > 1)
+        load_lane<D>(src + ld_s, avail, vec, xb);
+    else
+#pragma unroll
+        for (int d = 0; d < D; d++)
+            xb[d] = 0;
+
+    for (int g = 0; g < N; g += 2) {
+        const int nn = g & (NCP - 1);
+        if (nn == 0 && !staged) {
+            // masks of rows k0.. and sources g..g+NCP-1: mk[(kk * NCP + j) * NB + b]
+            wave_sync();
+            const int nc = min(NCP, N - g);
+#pragma unroll 4
+            for (int it = 0; it < KW * NCP / 64; it++) {
+                const int e = lane + 64 * it, kk = e / NCP, j = e % NCP;
+                const uint32_t c = (kk < kv && j < nc) ? (uint32_t)gld<uint8_t>(C + (uint64_t)(k0 + kk) * N + g + j) : 0u;
+#pragma unroll
+                for (int b = 0; b < NB; b++)
+                    mk[e * NB + b] = 0u - ((c >> b) & 1u);
+            }
+            wave_sync();
+        }
+        uint32_t pa[NB][D], pb[NB][D];
+#pragma unroll
+        for (int d = 0; d < D; d++) {
+            pa[0][d] = xa[d];
+            pb[0][d] = xb[d];
+#pragma unroll
+            for (int b = 1; b < NB; b++) {
+                pa[b][d] = times_alpha<NB>(pa[b - 1][d]);
+                pb[b][d] = times_alpha<NB>(pb[b - 1][d]);
+            }
+        }
+        // a missing source reads as zero (its masks are zero as well)
+        if (g + 2 < N)
+            load_lane<D>(src + (uint64_t)(g + 2) * ld_s, avail, vec, xa);
+        if (g + 3 < N)
+            load_lane<D>(src + (uint64_t)(g + 3) * ld_s, avail, vec, xb);
+        else
+#pragma unroll
+            for (int d = 0; d < D; d++)
+                xb[d] = 0;
+#pragma unroll
+        for (int k8 = 0; k8 < KW; k8 += 8) {
+            if (k8 < kv) {
+#pragma unroll
+                for (int kk = k8; kk < k8 + 8; kk++) {
+                    // 2 NB masks: source nn (planes 0..NB-1), then source nn + 1
+                    uint32_t m[2 * NB];
+                    const uint32_t *mp = mk + (kk * NCP + nn) * NB;
+                    if constexpr (NB == 1) {
+                        const uint2 v = *reinterpret_cast<const uint2 *>(mp);
+                        m[0] = v.x; m[1] = v.y;
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 2 * NB; q += 4) {
+                            const uint4 v = *reinterpret_cast<const uint4 *>(mp + q);
+                            m[q] = v.x; m[q + 1] = v.y; m[q + 2] = v.z; m[q + 3] = v.w;
+                        }
+                    }
+#pragma unroll
+                    for (int d = 0; d < D; d++) {
+                        uint32_t a = acc[kk][d];
+#pragma unroll
+                        for (int b = 0; b < NB; b++) {
+                            a = and_xor(a, pa[b][d], m[b]);
+                            a = and_xor(a, pb[b][d], m[NB + b]);
+                        }
+                        acc[kk][d] = a;
+                    }
+                }
+            }
+        }
+    }
+    if (avail == 0)
+        return;
+#pragma unroll
+    for (int kk = 0; kk < KW; kk++)
+        if (kk < kv)
+            store_row<D>(Y + (uint64_t)(k0 + kk) * ld_y + p, avail, vec, acc[kk]);
+}
+
+// Persistent bit-plane encode over the same wave tiles and queues as the
+// table form.
+template <int NB>
+__global__ __launch_bounds__(256, NB <= 2 ? GF_PLANE_WAVES_PER_SIMD : 2) void k_encode_planes(const DevGen *__restrict__ gens,
+                                                                             const DevTile *__restrict__ tiles,
+                                                                             const unsigned *__restrict__ runs,
+                                                                             const unsigned *__restrict__ bounds,
+                                                                             unsigned *counters)
+{
+    __shared__ WaveStage stage[WAVES];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t *mk = reinterpret_cast<uint32_t *>(&stage[wave]);
+    QueueCursor cursor;
+    for (;;) {
+        int t = 0;
+        if (lane == 0)
+            t = queue_next_tile(counters, runs, bounds, cursor);
+        t = __builtin_amdgcn_readlane(t, 0);
+        if (t < 0)
+            break;
+        const DevTile tl = tiles[t];
+        const DevGen g = gens[tl.gen];
+        if (g.status && *g.status != g.need)
+            continue;
+        const int d = tl.D & 0xFF, strips = (tl.D >> 8) + 1;
+        for (int q = 0; q < strips; q++) {
+            const uint64_t p0 = tl.p0 + (uint64_t)q * 256u * (uint64_t)d;
+            const bool staged = q > 0 && (int)g.N <= planes_per_stage(NB);
+            if (d == 4)
+                wave_tile_planes<NB, 4>(g.C, (int)g.K, (int)g.N, g.S, g.ld_s, g.Y, g.ld_y, g.len, (int)tl.k0, p0,
+                                        g.align >= 16, mk, lane, staged);
+            else if (d == 2)
+                wave_tile_planes<NB, 2>(g.C, (int)g.K, (int)g.N, g.S, g.ld_s, g.Y, g.ld_y, g.len, (int)tl.k0, p0,
+                                        g.align >= 8, mk, lane, staged);
+            else
+                wave_tile_planes<NB, 1>(g.C, (int)g.K, (int)g.N, g.S, g.ld_s, g.Y, g.ld_y, g.len, (int)tl.k0, p0,
+                                        g.align >= 4, mk, lane, staged);
         }
     }
     if (lane == 0)
@@ -1605,6 +1809,33 @@ hipError_t launch_encode_persistent(const DevGen *gens, const DevTile *tiles, co
     hipLaunchKernelGGL(k_encode_waves, dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters,
                        reinterpret_cast<const uint4 *>(ptab_field));
     return hipGetLastError();
+}
+
+hipError_t launch_encode_planes(int field, const DevGen *gens, const DevTile *tiles, const unsigned *runs,
+                                const unsigned *bounds, int ntiles, unsigned *counters, int grid, hipStream_t s)
+{
+    if (ntiles <= 0)
+        return hipSuccess;
+    if (field == 1)
+        hipLaunchKernelGGL(k_encode_planes<1>, dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters);
+    else if (field == 2)
+        hipLaunchKernelGGL(k_encode_planes<2>, dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters);
+    else if (field == 4)
+        hipLaunchKernelGGL(k_encode_planes<4>, dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+int encode_planes_blocks_per_cu(int field)
+{
+    const void *k = field == 1   ? reinterpret_cast<const void *>(&k_encode_planes<1>)
+                    : field == 2 ? reinterpret_cast<const void *>(&k_encode_planes<2>)
+                                 : reinterpret_cast<const void *>(&k_encode_planes<4>);
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, 0) != hipSuccess || nb < 1)
+        return 1;
+    return nb;
 }
 
 int encode_blocks_per_cu()

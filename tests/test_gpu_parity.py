@@ -125,11 +125,17 @@ def test_encode(gf, n, K, N, L):
 
 
 @pytest.mark.parametrize("n", FIELDS)
-@pytest.mark.parametrize("form,bpl", [(1, 0), (1, 4), (1, 8), (1, 16), (2, 0)])
+@pytest.mark.parametrize("form,bpl", [(1, 0), (1, 4), (1, 8), (1, 16), (2, 0), (3, 0), (3, 4), (3, 8), (3, 16)])
 @pytest.mark.parametrize("grid", [0, 1, 7])
 def test_encode_every_variant(gf, n, form, bpl, grid):
-    """Every schedule of both kernel forms gives the same bytes (batched path, 30 generations)."""
+    """Every schedule of every kernel form gives the same bytes (batched path, 30
+    generations; N up to 80 spans several mask stages of the bit-plane form)."""
     torch = torch_cuda()
+    if form == 3 and n == 8:
+        C1, S1, Y1 = dev(np.ones((2, 2), np.uint8)), dev(np.ones((2, 8), np.uint8)), dev(np.zeros((2, 8), np.uint8))
+        with pytest.raises(gf.GFError):      # the bit-plane form covers n <= 4 only
+            gf.gf_plan_encode(n, [(C1, S1, Y1)], tune={"form": 3})
+        return
     gens, keep, wants = [], [], []
     for i in range(30):
         N = int(synth.uniform_ints(synth.key(11, i), 1, 1, 80)[0])
@@ -161,12 +167,14 @@ def test_encode_every_variant(gf, n, form, bpl, grid):
 
 
 @pytest.mark.parametrize("n", FIELDS)
-@pytest.mark.parametrize("form", [0, 2])
+@pytest.mark.parametrize("form", [0, 2, 3])
 @pytest.mark.parametrize("pitch,off", [(3, 1), (4, 4)])
 def test_batched_encode_odd_rows(gf, n, form, pitch, off):
-    """Row pitch and offset off the 16-byte grid: odd (byte paths of both forms)
+    """Row pitch and offset off the 16-byte grid: odd (byte paths of every form)
     and word-aligned (word copies of the bit-matrix form); the autotuned plan."""
     torch = torch_cuda()
+    if form == 3 and n == 8:
+        pytest.skip("the bit-plane form covers n <= 4")
     items, wants = [], []
     for i in range(12):
         N = [1, 7, 8, 9, 16, 17, 33, 100, 255, 256, 40, 3][i]
@@ -178,7 +186,7 @@ def test_batched_encode_odd_rows(gf, n, form, pitch, off):
         yb, Yd = padded_rows(np.zeros((K, L), np.uint8), L + 5, 3, fill=0x5A)
         items.append((dev(g.C), Sd, Yd, yb, K, L))
     plan = gf.gf_plan_encode(n, [(C, S, Y) for C, S, Y, _, _, _ in items], tune={"form": form})
-    assert plan.tuning()["form"] in (1, 2)
+    assert plan.tuning()["form"] == form if form else plan.tuning()["form"] in ((1, 2, 3) if n <= 4 else (1, 2))
     for _, _, Yd, _, _, _ in items:
         Yd.zero_()
     gf.gf_encode_batched(plan)
