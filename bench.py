@@ -63,6 +63,55 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+ALG1_SRC = os.path.join(ROOT, "bench_alg1.c")
+ALG1_LIB = os.path.join(ROOT, "libbench_alg1.so")
+
+
+def alg1_build() -> str:
+    """Compile the host AVX-512BW region madd (Sec. IV-A) used as CPU context."""
+    import subprocess
+    tmp = ALG1_LIB + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Werror", "-shared", "-fPIC", "-o", tmp, ALG1_SRC])
+    os.replace(tmp, ALG1_LIB)
+    return ALG1_LIB
+
+
+def alg1_lib():
+    import ctypes as C
+    if not os.path.exists(ALG1_LIB) or os.path.getmtime(ALG1_LIB) < os.path.getmtime(ALG1_SRC):
+        alg1_build()
+    L = C.CDLL(ALG1_LIB)
+    L.alg1_supported.restype = C.c_int
+    L.alg1_region_madd.restype = C.c_int
+    L.alg1_region_madd.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_size_t]
+    L.alg1_encode_seconds.restype = C.c_double
+    L.alg1_encode_seconds.argtypes = [C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p,
+                                      C.c_size_t, C.c_size_t, C.c_int]
+    return L
+
+
+def host_alg1_sweep() -> dict:
+    """One host core running the paper's split-nibble shuffle madd (AVX-512BW): encode of one
+    generation, N = K = 16, over packet lengths from 128 B to 64 KiB (the shape of the paper's
+    single-core measurements), per field.  Context for the GPU figures, not a target."""
+    L = alg1_lib()
+    if not L.alg1_supported():
+        return {"supported": False}
+    out = {"supported": True, "cores": 1, "N": 16, "K": 16, "points": []}
+    for n in (2, 4, 8):
+        for P in (128, 512, 1500, 8192, 65536):
+            g = synth.generation(synth.key(synth.BASE_SEED + 9, n, P), n, 16, 16, P)
+            S = np.ascontiguousarray(g.S)
+            Cm = np.ascontiguousarray(g.C)
+            Y = np.zeros((16, P), np.uint8)
+            reps = 21 if P <= 8192 else 7
+            t = L.alg1_encode_seconds(n, Cm.ctypes.data, 16, 16, S.ctypes.data, P, Y.ctypes.data, P, P, reps)
+            out["points"].append({"field": "GF(2^%d)" % n, "packet_bytes": P, "encode_us": round(t * 1e6, 3),
+                                  "gbs": round(16 * P / t / 1e9, 3),
+                                  "coded_gbit_s": round(16 * P * 8 / t / 1e9, 2)})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -503,6 +552,13 @@ def extra_workloads(gf, torch, args) -> dict:
         del plan, S, Cm, Y
         torch.cuda.empty_cache()
     out["k_sweep_gf256_9000B"] = ks
+
+    # ---- the paper's own CPU method on this host, one core (context)
+    out["host_alg1_avx512"] = host_alg1_sweep()
+    for pt in out["host_alg1_avx512"].get("points", []):
+        if pt["packet_bytes"] in (1500, 65536):
+            log("host Alg. 1 %s %d B: %.2f GB/s (%.1f us per 16 x 16 encode)"
+                % (pt["field"], pt["packet_bytes"], pt["gbs"], pt["encode_us"]))
     return out
 
 
