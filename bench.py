@@ -41,22 +41,28 @@ TABLE_OPS_PER_MADD = 4.5 / 4.0
 HBM_PEAK_GBS = 8000.0
 MFMA_FP4_TFLOPS = 10100.0
 
-# HBM bytes per launch of the batched encode kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE
-# (calibrated against a 1 GiB copy: fetch x 2.000, write x 1.000), valid only for the kernel
-# source they were taken with (sha256 of csrc/gf_kernels.hip); otherwise reported as null.
+# Sources each persistent encode kernel is built from: its counters below stay valid while they are unchanged.
+KERNEL_SOURCES = {2: ("gf_mfma.hip", "gf_queue.h", "gf_internal.h"),
+                  1: ("gf_kernels.hip", "gf_queue.h", "gf_internal.h"),
+                  3: ("gf_kernels.hip", "gf_queue.h", "gf_internal.h")}
+
+# HBM bytes per launch of the batched encode kernel of each form, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (KiB, averages over the profiled launches), scaled by what the same counters read for a
+# 1 GiB device copy (fetch x 2.000, write x 1.000); keyed by the sha256 of the kernel's sources, so a
+# changed kernel reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    # kernel source hash, form -> HBM bytes per launch: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB, averages over
-    # the profiled launches; the factors come from a 1 GiB device copy read by the same counters)
-    ("99243ca088ccbad8211e30533fbf3786632f8d464f001c54cec9a1f929e29baf", 2): 1462628 * 1024 * 2.0 + 2469149 * 1024,
-    ("99243ca088ccbad8211e30533fbf3786632f8d464f001c54cec9a1f929e29baf", 1): 3100195 * 1024 * 2.0 + 2449758 * 1024,
+    ("a4f50c451fc9e4c64d764b96396ba72771e6b27dd0c2ded5720c67f248c17480", 2): 1464011 * 1024 * 2.0 + 2467770 * 1024,
+    ("c73cedc53f821c5733bc2d1144174e01eca57d43450373e10442cd845f9e3d8a", 1): 3100758 * 1024 * 2.0 + 2449730 * 1024,
 }
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(form: int) -> str:
     import hashlib
-    path = os.path.join(ROOT, "paper_1909_02871_amd", "csrc", "gf_kernels.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES.get(form, ()):
+        with open(os.path.join(ROOT, "paper_1909_02871_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def log(*a):
@@ -253,7 +259,7 @@ def main():
     madds = b.byte_madds
     hbm_bytes = b.source_bytes + int((b.Ks * b.Ls).sum()) + int((b.Ks * b.Ns).sum())
     hbm_roof_src = HBM_PEAK_GBS * b.source_bytes / hbm_bytes
-    traffic = MEASURED_TRAFFIC.get((kernel_source_hash(), tuning["form"])) if n == 8 and args.count == 10000 \
+    traffic = MEASURED_TRAFFIC.get((kernel_source_hash(tuning["form"]), tuning["form"])) if n == 8 and args.count == 10000 \
         else None
     if tuning["form"] == 2:
         # the bit-matrix product: 8K x 8N x L bit multiply-adds = 64 per byte-madd, 2 flops each,
