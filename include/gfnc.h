@@ -64,6 +64,9 @@ const char *gf_strerror(int code);
 
 /* Largest generation size N accepted by encode and decode. */
 #define GF_MAX_N 256
+/* Most coded rows of one generation in a batched plan or a serving request
+ * (GF_ERANGE above it; a single gf_encode has no such limit). */
+#define GF_MAX_K 65535
 
 /* ----------------------------------------------------------- region ops
  * madd (Sec. II; the shuffle kernel of Sec. IV-A, Algorithm 1):

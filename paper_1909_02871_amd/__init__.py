@@ -30,6 +30,7 @@ GF_2, GF_4, GF_16, GF_256 = 1, 2, 4, 8
 FIELDS = (GF_2, GF_4, GF_16, GF_256)
 GF_OK, GF_EINVAL, GF_ENOTINIT, GF_EDEVICE, GF_ESINGULAR, GF_ENOMEM, GF_ERANGE = 0, -1, -2, -3, -4, -5, -6
 GF_MAX_N = 256
+GF_MAX_K = 65535
 
 _lib = None
 

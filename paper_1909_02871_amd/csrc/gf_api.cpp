@@ -674,6 +674,8 @@ static int plan_encode_impl(int field, const gf_gen *gens, int count, const gf_t
     std::vector<DevGen> g(count);
     for (int i = 0; i < count; i++) {
         const gf_gen &x = gens[i];
+        if (x.K > GF_MAX_K)
+            return GF_ERANGE;
         int rc = check_encode_args(field, x.C, (int)x.K, (int)x.N, x.S, x.ld_s, x.Y, x.ld_y, x.len);
         if (rc)
             return rc;
@@ -734,7 +736,7 @@ static int check_recode_args(int field, const gf_recode_desc &r)
 {
     if (r.reserved || r.N < 1 || r.M < 1)
         return GF_EINVAL;
-    if (r.N > GF_MAX_N || r.M > GF_MAX_N)
+    if (r.N > GF_MAX_N || r.M > GF_MAX_N || r.Kout > GF_MAX_K)
         return GF_ERANGE;
     if ((r.M > 1 && r.ld_cin < r.N) || (r.Kout > 1 && r.ld_cout < r.N))
         return GF_EINVAL;

@@ -399,7 +399,7 @@ int gf_serve_submit_encode(gf_server *sv, uint64_t id, const uint8_t *C, int K, 
 {
     if (!sv || K < 1 || N < 1 || len == 0 || !C || !S || (N > 1 && ld_s < len))
         return GF_EINVAL;
-    if (N > GF_MAX_N)
+    if (N > GF_MAX_N || K > GF_MAX_K)
         return GF_ERANGE;
     std::lock_guard<std::mutex> lk(sv->mu);
     if (sv->reqs.count(id))

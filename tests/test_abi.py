@@ -107,6 +107,8 @@ def test_plan_argument_checks():
     assert L.gf_plan_encode(8, bad, 1, None, C.byref(h)) == gf.GF_EINVAL and not h.value
     big = (gf.gf_gen * 1)(gf.gf_gen(P1, P2, P3, 2, 300, 10, 10, 10))     # N > 256
     assert L.gf_plan_encode(8, big, 1, None, C.byref(h)) == gf.GF_ERANGE
+    tall = (gf.gf_gen * 1)(gf.gf_gen(P1, P2, P3, 65536, 2, 10, 10, 10))  # K > 65535 (tile row index is 16-bit)
+    assert L.gf_plan_encode(8, tall, 1, None, C.byref(h)) == gf.GF_ERANGE
     assert L.gf_plan_encode(3, bad, 1, None, C.byref(h)) == gf.GF_EINVAL
     assert L.gf_plan_encode(8, bad, 1, None, None) == gf.GF_EINVAL
     sysbad = (gf.gf_sys * 1)(gf.gf_sys(P1, P2, P3, 4, 1, 10, 10, 10))    # reserved != 0
@@ -149,6 +151,9 @@ def test_plan_recode_argument_checks():
     assert L.gf_plan_recode(8, (gf.gf_recode_desc * 1)(d), 1, None, C.byref(h)) == gf.GF_EINVAL
     d.reserved, d.M = 0, 300
     assert L.gf_plan_recode(8, (gf.gf_recode_desc * 1)(d), 1, None, C.byref(h)) == gf.GF_ERANGE
+    d.M, d.Kout = 3, 65536
+    assert L.gf_plan_recode(8, (gf.gf_recode_desc * 1)(d), 1, None, C.byref(h)) == gf.GF_ERANGE
+    d.Kout = 4
     d.M, d.Yout = 3, P2 + 1
     assert L.gf_plan_recode(8, (gf.gf_recode_desc * 1)(d), 1, None, C.byref(h)) == gf.GF_EINVAL
     assert L.gf_plan_recode(5, (gf.gf_recode_desc * 1)(d), 1, None, C.byref(h)) == gf.GF_EINVAL
