@@ -287,6 +287,9 @@ static int encode_impl(int field, const uint8_t *C, int K, int N, const uint8_t 
     if (rc)
         return rc;
     const uint32_t al = row_align(S, N > 1 ? ld_s : 0, Y, K > 1 ? ld_y : 0);
+    if (!status && !(tune && tune->bytes_per_lane) && small_ok(K, N, len, al))
+        return dev_err(launch_small(C, K, N, S, ld_s, Y, ld_y, len, field_ptab(d, field), field_inv(d, field), nullptr,
+                                    false, (hipStream_t)stream));
     Single sc = pick_single(K, N, len, al, d->cus);
     if (tune && tune->bytes_per_lane) {
         if (tune->bytes_per_lane != 4 && tune->bytes_per_lane != 8 && tune->bytes_per_lane != 16)
@@ -373,6 +376,9 @@ int gf_decode(int field, const uint8_t *C, int N, const uint8_t *B, size_t ld_b,
         return rc;
     uint8_t *cinv = static_cast<uint8_t *>(ws);
     int *rank = d_rank ? d_rank : reinterpret_cast<int *>(cinv + ((((size_t)N * N + 255) / 256) * 256));
+    if (small_ok(N, N, len, row_align(B, N > 1 ? ld_b : 0, S, N > 1 ? ld_s : 0)))
+        return dev_err(launch_small(C, N, N, B, ld_b, S, ld_s, len, field_ptab(d, field), field_inv(d, field), rank,
+                                    true, (hipStream_t)stream));
     hipError_t e = launch_invert(nullptr, 0, C, N, cinv, rank, field_ptab(d, field), field_inv(d, field),
                                  (hipStream_t)stream);
     if (e != hipSuccess)

@@ -162,6 +162,14 @@ int encode_planes_blocks_per_cu(int field);
 hipError_t launch_invert(const DevSys *sys, int count, const uint8_t *C, int N, uint8_t *Cinv, int *rank,
                          const uint32_t *ptab_field, const uint8_t *inv_field, hipStream_t s);
 int encode_blocks_per_cu();
+// One small generation in one launch (N, K <= 32, len <= 8192, rows 4-byte
+// aligned: align from row_align): Y = C S, or for a decode (K = N) S = C^-1 B
+// with the inversion in the same kernel, the rank written to *rank (if not
+// null) and no output for a singular C.
+bool small_ok(int K, int N, uint64_t len, uint32_t align);
+hipError_t launch_small(const uint8_t *C, int K, int N, const uint8_t *S, uint64_t ld_s, uint8_t *Y, uint64_t ld_y,
+                        uint64_t len, const uint32_t *ptab_field, const uint8_t *inv_field, int *rank, bool decode,
+                        hipStream_t s);
 uint32_t row_align(const void *S, uint64_t ld_s, const void *Y, uint64_t ld_y);
 // Device tables of `field` on the current device (initialising it if needed).
 int gfnc_field_tables(int field, const uint32_t **ptab, const uint8_t **inv);

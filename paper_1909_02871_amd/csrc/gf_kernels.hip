@@ -688,7 +688,7 @@ __global__ __launch_bounds__(256, NB <= 2 ? GF_PLANE_WAVES_PER_SIMD : 2) void k_
 // A: the caller's LDS matrix, MAXN rows of MAXN / 4 + 1 dwords; row(r) gives the address
 // of the matrix's row r (N bytes, device memory written before this kernel or
 // read-only input).
-template <int MAXN, class RowOf>
+template <int MAXN, int NT = 256, class RowOf>
 __device__ void invert_rows(uint32_t *A, RowOf row, int N, uint8_t *__restrict__ Cinv, int *rank_out,
                             const uint4 *__restrict__ ptab4, const uint8_t *__restrict__ invg)
 {
@@ -701,25 +701,41 @@ __device__ void invert_rows(uint32_t *A, RowOf row, int N, uint8_t *__restrict__
     __shared__ int piv[MAXN];
     __shared__ int src[MAXN];
     uint8_t *Ab = reinterpret_cast<uint8_t *>(A);
+    // NT threads take part: the whole workgroup (256, barriers between the
+    // phases) or its first wave alone (64, which needs no workgroup barrier:
+    // a wave's LDS accesses complete in order).
+    static_assert(NT == 256 || (NT == 64 && MAXN <= 64), "invert_rows runs on 256 threads, or on 64 for N <= 64");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    auto sync = [&]() {
+        if constexpr (NT == 256)
+            __syncthreads();
+        else
+            wave_sync();
+    };
     const int NW = (N + 3) >> 2;
     // row updates: thread tid owns column dword cl of rows r0, r0 + RS, ...
-    constexpr int RS = 256 / RW;
+    constexpr int RS = NT / RW;
     const int cl = tid % RW, r0 = tid / RW;
 
-    for (int i = tid; i < 512; i += 256)
+    // all loads of a phase are issued before the first is used (one memory wait)
+#pragma unroll
+    for (int i = tid; i < 512; i += NT)
         T[i >> 1][i & 1] = ptab4[i];
-    IV[tid] = invg[tid];
+#pragma unroll
+    for (int i = tid; i < 256; i += NT)
+        IV[i] = invg[i];
 
     auto load_matrix = [&]() {
-        for (int i = tid; i < N * RW; i += 256) {
+#pragma unroll 4
+        for (int i = tid; i < N * RW; i += NT) {
             const int r = i / RW, w = i - r * RW;
             const uint8_t *src = row(r);
             uint32_t v = 0;
-            for (int b = 0; b < 4; b++) {
+#pragma unroll
+            for (int b = 0; b < 4; b++) {   // clamped, masked: no branch between the loads
                 const int c = 4 * w + b;
-                if (c < N)
-                    v |= (uint32_t)src[c] << (8 * b);
+                const uint32_t x = src[min(c, N - 1)];
+                v |= (c < N ? x : 0u) << (8 * b);
             }
             A[r * PRW + w] = v;
         }
@@ -728,9 +744,11 @@ __device__ void invert_rows(uint32_t *A, RowOf row, int N, uint8_t *__restrict__
     auto find_pivot = [&](int j, int from) -> int {
         const bool ok = tid < N && tid >= from && Ab[tid * (4 * PRW) + j] != 0;
         const uint64_t m = __ballot(ok);
+        if constexpr (NT == 64)
+            return m ? (int)__builtin_ctzll(m) : (1 << 30);
         if (lane == 0)
             cand[wave] = m ? wave * 64 + __builtin_ctzll(m) : (1 << 30);
-        __syncthreads();
+        sync();
         const int pr = min(min(cand[0], cand[1]), min(cand[2], cand[3]));
         return pr;
     };
@@ -743,7 +761,7 @@ __device__ void invert_rows(uint32_t *A, RowOf row, int N, uint8_t *__restrict__
     };
 
     load_matrix();
-    __syncthreads();
+    sync();
 
     bool singular = false;
     for (int j = 0; j < N; j++) {
@@ -755,7 +773,7 @@ __device__ void invert_rows(uint32_t *A, RowOf row, int N, uint8_t *__restrict__
         swap_rows(pr, j);
         if (tid == 0)
             piv[j] = pr;
-        __syncthreads();
+        sync();
         if (tid < NW) {   // wave 0 only: reads below happen before the write
             uint32_t a = A[j * PRW + tid];
             const uint32_t pinv = IV[Ab[j * (4 * PRW) + j]];
@@ -765,7 +783,7 @@ __device__ void invert_rows(uint32_t *A, RowOf row, int N, uint8_t *__restrict__
         }
         if (tid < N)
             fcol[tid] = tid == j ? 0 : Ab[tid * (4 * PRW) + j];
-        __syncthreads();
+        sync();
         if (cl < NW) {   // thread: column dword cl of rows r0, r0 + RS, ...
             // branch-free: where fcol is 0 the row's byte j is 0 already and the
             // product is 0 (row j itself, whose fcol is 0, keeps its leading 1)
@@ -778,7 +796,7 @@ __device__ void invert_rows(uint32_t *A, RowOf row, int N, uint8_t *__restrict__
                 A[i * PRW + cl] = (A[i * PRW + cl] & k) ^ prod4(T[f][0], T[f][1].x, pj);
             }
         }
-        __syncthreads();
+        sync();
     }
 
     if (!singular) {
@@ -791,8 +809,8 @@ __device__ void invert_rows(uint32_t *A, RowOf row, int N, uint8_t *__restrict__
                 src[piv[l]] = t;
             }
         }
-        __syncthreads();
-        for (int it = tid; it < N * N; it += 256) {
+        sync();
+        for (int it = tid; it < N * N; it += NT) {
             const int i = it / N, c = it - i * N;
             Cinv[it] = Ab[i * (4 * PRW) + src[c]];
         }
@@ -802,27 +820,27 @@ __device__ void invert_rows(uint32_t *A, RowOf row, int N, uint8_t *__restrict__
     }
 
     // Singular: recompute the exact rank by forward elimination of a fresh copy.
-    __syncthreads();
+    sync();
     load_matrix();
-    __syncthreads();
+    sync();
     int prow = 0;
     for (int j = 0; j < N && prow < N; j++) {
         const int pr = find_pivot(j, prow);
         if (pr >= N) {
-            __syncthreads();
+            sync();
             continue;
         }
         swap_rows(pr, prow);
-        __syncthreads();
+        sync();
         if (tid < NW) {
             const uint32_t pinv = IV[Ab[prow * (4 * PRW) + j]];
             const uint32_t a = A[prow * PRW + tid];
             A[prow * PRW + tid] = prod4(T[pinv][0], T[pinv][1].x, a);
         }
-        __syncthreads();
+        sync();
         if (tid < N)
             fcol[tid] = tid > prow ? Ab[tid * (4 * PRW) + j] : 0;
-        __syncthreads();
+        sync();
         if (cl < NW) {
             const uint32_t pj = A[prow * PRW + cl];
 #pragma unroll 4
@@ -831,7 +849,7 @@ __device__ void invert_rows(uint32_t *A, RowOf row, int N, uint8_t *__restrict__
                 A[i * PRW + cl] ^= prod4(T[f][0], T[f][1].x, pj);
             }
         }
-        __syncthreads();
+        sync();
         prow++;
     }
     if (tid == 0 && rank_out)
@@ -864,6 +882,87 @@ __global__ __launch_bounds__(256) void k_invert_batched(const DevSys *__restrict
     if ((int)s.N > MAXN || (MAXN > 32 && (int)s.N <= MAXN / 2))
         return;   // handled by the launch of another size class
     invert_body<MAXN>(s.C, (int)s.N, s.Cinv, s.rank, ptab4, invg);
+}
+
+// ------------------------------------------------- one small generation
+//
+// A single small generation (N, K <= 32, short rows) is latency-bound: the
+// general path streams the sources through a few waves one pair at a time
+// and needs a second launch to clear the output of source slices.  Here one
+// launch gives every (coded row, 4-byte column) its own thread, which issues
+// all N source loads before anything else, so the kernel waits for memory
+// about once; the K x N product tables are staged in LDS meanwhile.  For a
+// decode the first wave of every workgroup also inverts C in its LDS (the
+// Gauss-Jordan of k_invert_one, with wave barriers in place of workgroup
+// ones) while the source loads are in flight, and all apply C^-1;
+// workgroup 0 reports the rank, and a singular C writes no output.
+
+constexpr int SMALL_MAX = 32;   // largest N and K of the small path
+
+__global__ __launch_bounds__(256) void k_small(const uint8_t *__restrict__ C, int K, int N,
+                                               const uint8_t *__restrict__ S, uint64_t ld_s, uint8_t *__restrict__ Y,
+                                               uint64_t ld_y, uint64_t len, const uint4 *__restrict__ ptab4,
+                                               const uint8_t *__restrict__ invg, int *rank, int decode)
+{
+    __shared__ uint4 T[SMALL_MAX * SMALL_MAX][2];
+    __shared__ uint8_t Ci[SMALL_MAX * SMALL_MAX];
+    __shared__ int rk;
+    const uint64_t ncols = (len + 3) / 4;
+    const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    const uint64_t kq = t / ncols;
+    const bool active = kq < (uint64_t)K;   // threads past the last row still join the barriers
+    const int k = active ? (int)kq : 0;
+    const uint64_t col = 4 * (t - kq * ncols);
+    const uint64_t avail = active ? len - col : 0;
+    // every source load is issued before the first is used: rows past N read
+    // row N - 1 (in bounds) and are masked to zero, with no branch per row
+    uint32_t x[SMALL_MAX];
+    if (avail >= 4) {
+#pragma unroll
+        for (int i = 0; i < SMALL_MAX; i++) {
+            const uint32_t v = gld<uint32_t>(S + (uint64_t)min(i, N - 1) * ld_s + col);
+            x[i] = i < N ? v : 0u;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < SMALL_MAX; i++) {
+            x[i] = 0;
+            if (i < N)
+                for (uint64_t b = 0; b < avail; b++)
+                    x[i] |= (uint32_t)gld<uint8_t>(S + (uint64_t)i * ld_s + col + b) << (8 * b);
+        }
+    }
+    const uint8_t *coef = C;
+    if (decode) {
+        __shared__ uint32_t A[SMALL_MAX * (SMALL_MAX / 4 + 1)];
+        if (threadIdx.x < 64)   // one wave: no workgroup barrier per pivot
+            invert_rows<SMALL_MAX, 64>(A, [&](int r) { return C + (uint64_t)r * N; }, N, Ci, &rk, ptab4, invg);
+        __syncthreads();
+        if (blockIdx.x == 0 && threadIdx.x == 0 && rank)
+            *rank = rk;
+        if (rk < N)
+            return;   // the same value in every thread of the workgroup
+        coef = Ci;
+    }
+    for (int e = threadIdx.x; e < K * N; e += 256) {
+        const uint32_t c = coef[e];
+        T[e][0] = ptab4[c * 2];
+        T[e][1] = ptab4[c * 2 + 1];
+    }
+    __syncthreads();
+    if (avail == 0)
+        return;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < SMALL_MAX; i++)
+        if (i < N)
+            acc ^= prod4(T[k * N + i][0], T[k * N + i][1].x, x[i]);
+    uint8_t *q = Y + (uint64_t)k * ld_y + col;
+    if (avail >= 4)
+        gst<uint32_t>(q, acc);
+    else
+        for (uint64_t b = 0; b < avail; b++)
+            gst<uint8_t>(q + b, (uint8_t)(acc >> (8 * b)));
 }
 
 // ------------------------------------------------------------------ serving
@@ -1152,6 +1251,23 @@ hipError_t launch_encode(int D, int nsplit, const uint8_t *C, int K, int N, cons
     else
         return hipErrorInvalidValue;
 #undef GF_DIRECT
+    return hipGetLastError();
+}
+
+bool small_ok(int K, int N, uint64_t len, uint32_t align)
+{
+    return K >= 1 && K <= SMALL_MAX && N >= 1 && N <= SMALL_MAX && len >= 1 && len <= 8192 && align >= 4;
+}
+
+hipError_t launch_small(const uint8_t *C, int K, int N, const uint8_t *S, uint64_t ld_s, uint8_t *Y, uint64_t ld_y,
+                        uint64_t len, const uint32_t *ptab_field, const uint8_t *inv_field, int *rank, bool decode,
+                        hipStream_t s)
+{
+    if (!small_ok(K, N, len, 4))
+        return hipErrorInvalidValue;
+    const uint64_t threads = (len + 3) / 4 * (uint64_t)K;
+    hipLaunchKernelGGL(k_small, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, C, K, N, S, ld_s, Y, ld_y,
+                       len, reinterpret_cast<const uint4 *>(ptab_field), inv_field, rank, decode ? 1 : 0);
     return hipGetLastError();
 }
 
