@@ -169,6 +169,10 @@ struct gf_plan {
     std::vector<gf_gen> gens;
     // recode: the encode plan of the coefficient headers, launched first
     gf_plan *head = nullptr;
+    // decode: streams and events that let the size classes' eliminations overlap
+    hipStream_t aux[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_done[3] = {nullptr, nullptr, nullptr};
 };
 
 int gfnc::gfnc_field_tables(int field, const uint32_t **ptab, const uint8_t **inv)
@@ -410,6 +414,14 @@ static void plan_free_device(gf_plan *p)
         delete p->head;
         p->head = nullptr;
     }
+    for (int i = 0; i < 3; i++) {
+        if (p->aux[i])
+            (void)hipStreamDestroy(p->aux[i]);
+        if (p->ev_done[i])
+            (void)hipEventDestroy(p->ev_done[i]);
+    }
+    if (p->ev_fork)
+        (void)hipEventDestroy(p->ev_fork);
 }
 
 }  // extern "C"
@@ -874,6 +886,12 @@ int gf_plan_decode(int field, const gf_sys *sys, int count, const gf_tuning *tun
     p->sys_order = order;
     if (!rc)
         rc = upload(&p->d_sys, ds);
+    for (int i = 0; i < 3 && !rc; i++)
+        if (hipStreamCreateWithFlags(&p->aux[i], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&p->ev_done[i], hipEventDisableTiming) != hipSuccess)
+            rc = GF_EDEVICE;
+    if (!rc && hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess)
+        rc = GF_EDEVICE;
     std::vector<DevGen> g(count);
     for (int i = 0; i < count; i++) {
         const gf_sys &s = sys[i];
@@ -900,13 +918,29 @@ static int run_plan(gf_plan *p, int *d_rank, hipStream_t s)
     if (p->head && (rc = run_plan(p->head, nullptr, s)))
         return rc;
     if (p->kind == 1) {
-        for (int c = 0; c < 4; c++) {
+        // the size classes' eliminations run side by side: the largest on `s`,
+        // the others on the plan's own streams, forked from and joined back to `s`
+        static const int kClassN[4] = {32, 64, 128, 256};
+        int classes = 0;
+        for (int c = 0; c < 4; c++)
+            classes += p->class_count[c] > 0;
+        if (classes > 1 && hipEventRecord(p->ev_fork, s) != hipSuccess)
+            return GF_EDEVICE;
+        int used = 0;
+        for (int c = 3; c >= 0; c--) {
             if (p->class_count[c] == 0)
                 continue;
-            hipError_t e = launch_invert(p->d_sys + p->class_begin[c], p->class_count[c], nullptr, 0, nullptr,
-                                         nullptr, field_ptab(d, f), field_inv(d, f), s);
+            hipStream_t on = used == 0 ? s : p->aux[used - 1];
+            if (used > 0 && hipStreamWaitEvent(on, p->ev_fork, 0) != hipSuccess)
+                return GF_EDEVICE;
+            hipError_t e = launch_invert(p->d_sys + p->class_begin[c], p->class_count[c], nullptr, kClassN[c], nullptr,
+                                         nullptr, field_ptab(d, f), field_inv(d, f), on);
             if (e != hipSuccess)
                 return GF_EDEVICE;
+            if (used > 0 && (hipEventRecord(p->ev_done[used - 1], on) != hipSuccess ||
+                             hipStreamWaitEvent(s, p->ev_done[used - 1], 0) != hipSuccess))
+                return GF_EDEVICE;
+            used++;
         }
     }
     if ((rc = launch_schedule(p, d, s)))

@@ -159,6 +159,8 @@ int encode_mfma_blocks_per_cu(bool aligned4);
 hipError_t launch_encode_planes(int field, const DevGen *gens, const DevTile *tiles, const unsigned *runs,
                                 const unsigned *bounds, int ntiles, unsigned *counters, int grid, hipStream_t s);
 int encode_planes_blocks_per_cu(int field);
+// One matrix (sys == nullptr: C, N, Cinv, rank) or `count` systems of one size
+// class (N <= 32, 64, 128 or 256; N names the class), one workgroup each.
 hipError_t launch_invert(const DevSys *sys, int count, const uint8_t *C, int N, uint8_t *Cinv, int *rank,
                          const uint32_t *ptab_field, const uint8_t *inv_field, hipStream_t s);
 int encode_blocks_per_cu();

@@ -1336,11 +1336,15 @@ hipError_t launch_invert(const DevSys *sys, int count, const uint8_t *C, int N, 
     }
     if (count <= 0)
         return hipSuccess;
-    // One launch per size class; each block skips systems of other classes.
-    hipLaunchKernelGGL(k_invert_batched<32>, dim3(count), dim3(256), 0, s, sys, pt, inv_field);
-    hipLaunchKernelGGL(k_invert_batched<64>, dim3(count), dim3(256), 0, s, sys, pt, inv_field);
-    hipLaunchKernelGGL(k_invert_batched<128>, dim3(count), dim3(256), 0, s, sys, pt, inv_field);
-    hipLaunchKernelGGL(k_invert_batched<256>, dim3(count), dim3(256), 0, s, sys, pt, inv_field);
+    // `sys` holds systems of one size class (the class of N); a block skips any other.
+    if (N <= 32)
+        hipLaunchKernelGGL(k_invert_batched<32>, dim3(count), dim3(256), 0, s, sys, pt, inv_field);
+    else if (N <= 64)
+        hipLaunchKernelGGL(k_invert_batched<64>, dim3(count), dim3(256), 0, s, sys, pt, inv_field);
+    else if (N <= 128)
+        hipLaunchKernelGGL(k_invert_batched<128>, dim3(count), dim3(256), 0, s, sys, pt, inv_field);
+    else
+        hipLaunchKernelGGL(k_invert_batched<256>, dim3(count), dim3(256), 0, s, sys, pt, inv_field);
     return hipGetLastError();
 }
 
