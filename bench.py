@@ -42,17 +42,17 @@ HBM_PEAK_GBS = 8000.0
 MFMA_FP4_TFLOPS = 10100.0
 
 # Sources each persistent encode kernel is built from: its counters below stay valid while they are unchanged.
-KERNEL_SOURCES = {2: ("gf_mfma.hip", "gf_queue.h", "gf_internal.h"),
-                  1: ("gf_kernels.hip", "gf_queue.h", "gf_internal.h"),
-                  3: ("gf_kernels.hip", "gf_queue.h", "gf_internal.h")}
+KERNEL_SOURCES = {2: ("gf_mfma.hip", "gf_queue.h", "gf_types.h"),
+                  1: ("gf_kernels.hip", "gf_queue.h", "gf_types.h", "gf_internal.h"),
+                  3: ("gf_kernels.hip", "gf_queue.h", "gf_types.h", "gf_internal.h")}
 
 # HBM bytes per launch of the batched encode kernel of each form, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (KiB, averages over the profiled launches), scaled by what the same counters read for a
 # 1 GiB device copy (fetch x 2.000, write x 1.000); keyed by the sha256 of the kernel's sources, so a
 # changed kernel reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("a4f50c451fc9e4c64d764b96396ba72771e6b27dd0c2ded5720c67f248c17480", 2): 1464011 * 1024 * 2.0 + 2467770 * 1024,
-    ("c73cedc53f821c5733bc2d1144174e01eca57d43450373e10442cd845f9e3d8a", 1): 3100758 * 1024 * 2.0 + 2449730 * 1024,
+    ("2703b4c06ce85a46f64d0792d04baeb9ece3016067a3dee21fc74f943cd0dde3", 2): 1462874 * 1024 * 2.0 + 2468920 * 1024,
+    ("b6d09bac99eb379cd710863dbfd295bfaf2f783145240a977e583581daccc1d0", 1): 3101279 * 1024 * 2.0 + 2449820 * 1024,
 }
 
 

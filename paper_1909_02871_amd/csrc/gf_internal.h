@@ -7,6 +7,8 @@
 
 #include <vector>
 
+#include "gf_types.h"
+
 namespace gfnc {
 
 // Field index 0..3 for n = 1, 2, 4, 8.
@@ -37,30 +39,6 @@ struct HostTables {
     uint8_t rows[4][256][8];    // bit-matrix rows, as in DevTables
 };
 const HostTables &host_tables();
-
-// Per-generation descriptor as the persistent kernels read it.
-struct DevGen {
-    const uint8_t *C;
-    const uint8_t *S;
-    uint8_t *Y;
-    uint64_t len, ld_s, ld_y;
-    uint32_t K, N;
-    const int *status;   // if non-null, the generation is skipped unless *status == need
-    int need;
-    uint32_t align;      // largest of 16, 8, 4, 1 dividing S, Y, ld_s and ld_y
-};
-
-// One wave tile of the persistent (table-form) encode: up to ENC_ROWS coded
-// rows from k0, over `strips` consecutive strips of 256*d payload bytes from
-// p0 (d dwords per lane), where D = d | (strips - 1) << 8; short generations
-// take several strips per tile so that claims and descriptor loads amortise.
-// The bit-matrix form uses gen and k0 only.
-struct DevTile {
-    uint32_t gen;
-    uint16_t k0;
-    uint16_t D;
-    uint64_t p0;
-};
 
 struct DevSys {
     const uint8_t *C;
@@ -103,12 +81,6 @@ struct DevPacket {
     const uint8_t *payload;   // len bytes
 };
 
-#ifndef GF_MF_PREFETCH
-#define GF_MF_PREFETCH 3
-#endif
-#ifndef GF_MF_WAVES_PER_SIMD
-#define GF_MF_WAVES_PER_SIMD 2
-#endif
 constexpr int ENC_ROWS = GF_ENC_ROWS;   // coded rows per wave tile
 inline uint64_t wave_strip(int D) { return 256ull * (uint64_t)D; }
 
@@ -119,20 +91,6 @@ hipError_t launch_region_batched(const void *d_regions, int count, uint64_t max_
 hipError_t launch_encode(int D, int nsplit, const uint8_t *C, int K, int N, const uint8_t *S, uint64_t ld_s,
                          uint8_t *Y, uint64_t ld_y, uint64_t len, const uint32_t *ptab_field, const int *status,
                          int need, bool aligned, hipStream_t s);
-// Work queues of the persistent encode kernels.  Tiles sit in MF_QUEUES
-// queues, one per XCD (workgroups are dealt to the 8 XCDs round robin, so
-// workgroup b starts on queue b % 8 and moves on to the others when it is
-// empty); all tiles of a generation share a queue, so its source stays in one
-// L2.  A claim takes a run of consecutive tiles (short tiles are grouped, so
-// claims stay rare).  runs[r] .. runs[r + 1] are the tiles of run r and
-// bounds[i] .. bounds[i + 1] the runs of queue i.  Counter words, each on its
-// own 256-byte line: MF_CTR_STRIDE * i, the next run of queue i;
-// MF_CTR_RETIRED, the retired workgroups or waves.  The last to retire sets
-// them all back to zero, so a launch needs no clearing beforehand.
-constexpr int MF_QUEUES = 8;
-constexpr int MF_CTR_STRIDE = 64;
-constexpr int MF_CTR_RETIRED = MF_CTR_STRIDE * MF_QUEUES;
-constexpr int GF_QUEUE_CTR_WORDS = MF_CTR_RETIRED + 1;
 
 struct TileQueues {
     std::vector<DevTile> tiles;
@@ -143,8 +101,6 @@ struct TileQueues {
 void build_tiles(const DevGen *g, size_t n, int fixed_D, TileQueues &q);
 // Bit-matrix form on the matrix cores: workgroup tiles of MF_ROWS coded rows
 // over the whole packet length in strips of MF_STRIP bytes (DevTile.D unused).
-constexpr int MF_ROWS = 16;
-constexpr int MF_STRIP = 256;
 void build_tiles_mfma(const DevGen *g, size_t n, TileQueues &q);
 
 hipError_t launch_encode_persistent(const DevGen *gens, const DevTile *tiles, const unsigned *runs,

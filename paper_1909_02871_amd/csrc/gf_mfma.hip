@@ -4,8 +4,8 @@
 
 #include <stdint.h>
 
-#include "gf_internal.h"
 #include "gf_queue.h"
+#include "gf_types.h"
 
 namespace gfnc {
 

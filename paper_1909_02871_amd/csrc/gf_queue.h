@@ -1,11 +1,11 @@
 // Device side of the persistent kernels' work queues (the layout of tiles,
-// runs, bounds and counters is described with TileQueues in gf_internal.h).
+// runs, bounds and counters is described with MF_QUEUES in gf_types.h).
 // Included by every kernel file whose kernels claim tiles from the queues.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
-#include "gf_internal.h"
+#include "gf_types.h"
 
 namespace gfnc {
 namespace {
