@@ -40,8 +40,11 @@ def build(force: bool = True) -> str:
 def lib():
     global _lib
     if _lib is None:
-        build(force=False)
-        L = C.CDLL(_LIB)
+        path = os.environ.get("GFO_LIB")   # a separately built copy (e.g. with host sanitizers)
+        if not path:
+            build(force=False)
+            path = _LIB
+        L = C.CDLL(path)
         sig = {
             "gfo_valid_field": (C.c_int, [C.c_int]),
             "gfo_poly": (C.c_int, [C.c_int]),
