@@ -378,6 +378,33 @@ def uniform_plan(gf, torch, n: int, K: int, N: int, L: int, count: int, seed: in
     return plan, S, Cm, Y, ld
 
 
+def relay_batch(gf, torch, count: int, keep_host: bool = False) -> dict:
+    """The relay workload: the uneven GF(256) shapes, each relay holding M = N received packets and
+    sending Kout = N recoded ones, packets stored as rows [N coefficients | payload] at a 16-byte
+    pitch; returns the recode plan (autotuned), the device buffers and the layout."""
+    b = synth.uneven_batch(8, count, seed_off=7)
+    Ns, Ls = b.Ns.astype(np.int64), b.Ls.astype(np.int64)
+    lds = np.array([synth.padded(int(N + L)) for N, L in zip(Ns, Ls)], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(Ns * lds)])
+    In_host = synth.random_bytes(synth.key(b.seed, 14), int(offs[-1]))
+    R_host = b.coef_blob()
+    In_dev = torch.from_numpy(In_host).to("cuda")
+    Out_dev = torch.empty(int(offs[-1]), dtype=torch.uint8, device="cuda")
+    R_dev = torch.from_numpy(R_host).to("cuda")
+    descs = (gf.gf_recode_desc * count)()
+    i0, o0, r0 = In_dev.data_ptr(), Out_dev.data_ptr(), R_dev.data_ptr()
+    for i in range(count):
+        N, L, ld, off = int(Ns[i]), int(Ls[i]), int(lds[i]), int(offs[i])
+        descs[i] = gf.gf_recode_desc(r0 + int(b.c_off[i]), i0 + off, i0 + off + N, o0 + off, o0 + off + N,
+                                     N, N, N, 0, L, ld, ld, ld, ld)
+    plan = gf.gf_plan_recode_desc(8, descs, count, keep=(In_dev, Out_dev, R_dev))
+    out = {"batch": b, "Ns": Ns, "Ls": Ls, "lds": lds, "offs": offs, "plan": plan, "In": In_dev, "Out": Out_dev,
+           "R": R_dev}
+    if keep_host:
+        out.update(In_host=In_host, R_host=R_host)
+    return out
+
+
 def extra_workloads(gf, torch, args) -> dict:
     """The other measured workloads: one generation (latency), the plain field/length sweep,
     the uneven batch over GF(16), recoding at a relay, the batched decode and a K sweep at fixed
@@ -482,20 +509,8 @@ def extra_workloads(gf, torch, args) -> dict:
 
     # ---- recoding at a relay: the uneven GF(256) shapes; each relay holds M = N received packets
     # and sends Kout = N recoded ones.  Packets are rows [N coefficients | payload], 16-byte pitch.
-    b = synth.uneven_batch(8, args.count, seed_off=7)
-    Ns, Ls = b.Ns.astype(np.int64), b.Ls.astype(np.int64)
-    lds = np.array([synth.padded(int(N + L)) for N, L in zip(Ns, Ls)], dtype=np.int64)
-    offs = np.concatenate([[0], np.cumsum(Ns * lds)])
-    In_dev = torch.from_numpy(synth.random_bytes(synth.key(b.seed, 14), int(offs[-1]))).to("cuda")
-    Out_dev = torch.empty(int(offs[-1]), dtype=torch.uint8, device="cuda")
-    R_dev = torch.from_numpy(b.coef_blob()).to("cuda")
-    descs = (gf.gf_recode_desc * args.count)()
-    i0, o0, r0 = In_dev.data_ptr(), Out_dev.data_ptr(), R_dev.data_ptr()
-    for i in range(args.count):
-        N, L, ld, off = int(Ns[i]), int(Ls[i]), int(lds[i]), int(offs[i])
-        descs[i] = gf.gf_recode_desc(r0 + int(b.c_off[i]), i0 + off, i0 + off + N, o0 + off, o0 + off + N,
-                                     N, N, N, 0, L, ld, ld, ld, ld)
-    plan = gf.gf_plan_recode_desc(8, descs, args.count, keep=(In_dev, Out_dev, R_dev))
+    rb = relay_batch(gf, torch, args.count)
+    b, Ns, plan = rb["batch"], rb["Ns"], rb["plan"]
     ms = time_ms(torch, lambda: gf.gf_plan_launch_graph(plan), reps=5, warm=2)
     out["recode_uneven_gf256"] = {"relays": args.count, "received_payload_bytes": b.source_bytes,
                                   "header_bytes": int((Ns * Ns).sum()), "layout": "packet rows [coefficients | payload]",
@@ -504,7 +519,7 @@ def extra_workloads(gf, torch, args) -> dict:
                                   "launch": "hip graph, 1 persistent kernel (header and payload in one product)"}
     log("recode, uneven GF(256): %.1f GB/s of received payload, %.3f ms" % (b.source_bytes / ms / 1e6, ms))
     plan.destroy()
-    del plan, In_dev, Out_dev, R_dev
+    del plan, rb
     torch.cuda.empty_cache()
 
     # ---- batched decode: 2048 systems, N in {32, 64, 128}, 1500 B, GF(256)
@@ -612,40 +627,36 @@ def single_generation_oracle(gf, torch, oracle) -> dict:
             "decode_equals_source": bool(r == 16 and R is not None and (R == g.S).all())}
 
 
-def serve_bench(gf, torch, args) -> dict:
-    """Serving: Poisson arrivals of 70% encode / 30% decode requests over GF(256).
+def serving_trace(gf, torch, count: int, n: int = 8) -> dict:
+    """The serving workload's requests: 70% encode / 30% decode over GF(2^n), N uniform in
+    {8..256}, packet length log-uniform in [64, 9000] B; a decode request receives the coded
+    packets of a rateless sender (fresh uniform coefficient vectors, 1.5 N emitted, 10% lost
+    i.i.d., random order), released one every microsecond from the request's arrival.  Arrival
+    times are left at 0 (the caller scales `unit_gaps`).  Also returns, per request, where its
+    coefficients and sources sit in the host and device blobs."""
+    from paper_1909_02871_amd.serving import TraceRequest
 
-    N uniform in {8..256}, packet length log-uniform in [64, 9000] B; a decode
-    request receives the coded packets of a rateless sender (fresh uniform
-    coefficient vectors, 1.5 N emitted, 10% lost i.i.d., random order),
-    released one every microsecond from the request's arrival.  The server
-    admits requests by an HBM budget.  First a run with every request
-    arriving at once gives the saturation throughput; then runs at 50% and
-    80% of it give the latency percentiles.
-    """
-    from paper_1909_02871_amd.serving import TraceRequest, percentile, replay
-
-    n = 8
-    count = args.serve_requests
-    reqs = synth.serving_stream(count, 1.0)          # shapes and kinds; arrival times are rescaled below
+    reqs = synth.serving_stream(count, 1.0)          # shapes and kinds; arrival times are rescaled later
     unit_gaps = np.array([r.arrival_s for r in reqs])
-    # payload and coefficients: one blob each, sliced per request
     enc = [r for r in reqs if r.kind == "encode"]
     dec = [r for r in reqs if r.kind == "decode"]
     pkt_per = {r.rid: int(np.ceil(1.5 * r.N)) for r in dec}
     s_need = sum(r.N * synth.padded(r.length) for r in reqs)
     c_need = sum(r.N * r.N for r in enc) + sum(pkt_per[r.rid] * r.N for r in dec)
     base = synth.key(synth.BASE_SEED + 4, 99)
-    S_dev = torch.from_numpy(synth.random_bytes(synth.key(base, 1), s_need)).to("cuda")
-    C_dev = torch.from_numpy(synth.uniform_field(synth.key(base, 2), c_need, n)).to("cuda")
+    S_host = synth.random_bytes(synth.key(base, 1), s_need)
+    C_host = synth.uniform_field(synth.key(base, 2), c_need, n)
+    S_dev = torch.from_numpy(S_host).to("cuda")
+    C_dev = torch.from_numpy(C_host).to("cuda")
     b_need = sum(pkt_per[r.rid] * synth.padded(r.length) for r in dec)
     B_dev = torch.empty(max(b_need, 16), dtype=torch.uint8, device="cuda")
     s_off = c_off = b_off = 0
-    trace = []
+    trace, where = [], {}
     src_bytes = 0
     for r in reqs:
         ld = synth.padded(r.length)
         S = S_dev[s_off:s_off + r.N * ld].view(r.N, ld)
+        where[r.rid] = {"kind": r.kind, "N": r.N, "length": r.length, "ld": ld, "s_off": s_off, "c_off": c_off}
         s_off += r.N * ld
         src_bytes += r.N * r.length
         if r.kind == "encode":
@@ -665,6 +676,27 @@ def serve_bench(gf, torch, args) -> dict:
             pk = [(Cp[j].data_ptr(), Bp[j].data_ptr(), 1e-6 * t) for t, j in enumerate(order) if not lost[j]]
             trace.append(TraceRequest(r.rid, 0.0, "decode", r.N, r.length, packets=pk))
     torch.cuda.synchronize()
+    return {"trace": trace, "unit_gaps": unit_gaps, "src_bytes": src_bytes, "enc": enc, "where": where,
+            "S_host": S_host, "C_host": C_host, "S_dev": S_dev, "C_dev": C_dev, "B_dev": B_dev}
+
+
+def serve_bench(gf, torch, args) -> dict:
+    """Serving: Poisson arrivals of 70% encode / 30% decode requests over GF(256).
+
+    N uniform in {8..256}, packet length log-uniform in [64, 9000] B; a decode
+    request receives the coded packets of a rateless sender (fresh uniform
+    coefficient vectors, 1.5 N emitted, 10% lost i.i.d., random order),
+    released one every microsecond from the request's arrival.  The server
+    admits requests by an HBM budget.  First a run with every request
+    arriving at once gives the saturation throughput; then runs at 50% and
+    80% of it give the latency percentiles.
+    """
+    from paper_1909_02871_amd.serving import percentile, replay
+
+    n = 8
+    count = args.serve_requests
+    st_ = serving_trace(gf, torch, count)
+    trace, unit_gaps, src_bytes, enc = st_["trace"], st_["unit_gaps"], st_["src_bytes"], st_["enc"]
     budget = int(args.serve_budget_gib * (1 << 30))
 
     def run(rate):

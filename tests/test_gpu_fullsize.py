@@ -7,7 +7,8 @@ sources everywhere.
 Workloads: the uneven batch (10,000 generations, N ~ U{8..256}, packets
 log-uniform in [64, 9000] B, K = N) over GF(16) and GF(256); the plain sweep
 (4096 generations, N = K = 64, 1500 / 9000 / 65536 B) over all four fields;
-the batched decode (2,048 systems, N in {32, 64, 128}, 1500 B) over GF(256).
+the batched decode (2,048 systems, N in {32, 64, 128}, 1500 B) over GF(256);
+recoding at 10,000 relays; the 4000-request serving stream.
 """
 import numpy as np
 import pytest
@@ -158,3 +159,67 @@ def test_decode_batch_full_size(gf):
     assert torch.equal(R_dev[valid], S_dev[valid])
     eplan.destroy()
     dplan.destroy()
+
+
+def test_recode_relay_full_size(gf):
+    """10,000 relays (the uneven GF(256) shapes, M = N received packets stored as rows
+    [coefficients | payload], Kout = N): sampled header and payload bytes of the
+    recoded packets against the oracle's recode; the row padding stays untouched."""
+    torch = torch_cuda()
+    rb = bench.relay_batch(gf, torch, 10000, keep_host=True)
+    b, Ns, Ls, lds, offs = rb["batch"], rb["Ns"], rb["Ls"], rb["lds"], rb["offs"]
+    rb["Out"].fill_(0xA5)
+    torch.cuda.synchronize()
+    gf.gf_plan_launch_graph(rb["plan"])
+    torch.cuda.synchronize()
+    Out = rb["Out"].cpu().numpy()
+    In, Rh = rb["In_host"], rb["R_host"]
+    rng = np.random.default_rng(synth.key(63))
+    for g in sorted({0, 9999, *(int(x) for x in rng.integers(0, 10000, 30))}):
+        N, L, ld, off = int(Ns[g]), int(Ls[g]), int(lds[g]), int(offs[g])
+        rows_in = In[off:off + N * ld].reshape(N, ld)
+        R = Rh[b.c_off[g]:b.c_off[g] + N * N].reshape(N, N)
+        rows, hcols, pcols = _sample_rows(rng, N), _sample_cols(rng, N), _sample_cols(rng, L)
+        wantC, wantY = oracle.recode(8, R[rows], np.ascontiguousarray(rows_in[:, hcols]),
+                                     np.ascontiguousarray(rows_in[:, [N + c for c in pcols]]))
+        got = Out[off:off + N * ld].reshape(N, ld)[rows]
+        assert (got[:, hcols] == wantC).all(), g
+        assert (got[:, [N + c for c in pcols]] == wantY).all(), g
+        assert (got[:, N + L:] == 0xA5).all(), g
+    rb["plan"].destroy()
+
+
+def test_serving_full_size(gf):
+    """The serving workload (4000 requests, 70% encode / 30% decode, GF(256), 10%
+    loss, random order) all arriving at once through a 4 GiB arena: every encode's
+    sampled bytes are the oracle's and every decode returns its sources exactly."""
+    from paper_1909_02871_amd.serving import replay
+    torch = torch_cuda()
+    st = bench.serving_trace(gf, torch, 4000)
+    where, S_host, C_host, S_dev = st["where"], st["S_host"], st["C_host"], st["S_dev"]
+    rng = np.random.default_rng(synth.key(64))
+    srv = gf.Server(field=8, budget_bytes=4 << 30)
+    bad = []
+
+    def check(d):
+        w = where[d["id"]]
+        N, L, ld, so = w["N"], w["length"], w["ld"], w["s_off"]
+        out = torch.empty((N, L), dtype=torch.uint8, device="cuda")
+        srv.copy_out(d["id"], out)
+        torch.cuda.synchronize()
+        if w["kind"] == "decode":
+            if d["rank"] != N or not torch.equal(out, S_dev[so:so + N * ld].view(N, ld)[:, :L]):
+                bad.append(d["id"])
+            return
+        rows, cols = _sample_rows(rng, N), _sample_cols(rng, L)
+        Cm = C_host[w["c_off"]:w["c_off"] + N * N].reshape(N, N)
+        S = S_host[so:so + N * ld].reshape(N, ld)
+        want = oracle.encode(8, Cm[rows], np.ascontiguousarray(S[:, cols]))
+        got = out.cpu().numpy()[np.ix_(rows, cols)]
+        if not (got == want).all():
+            bad.append(d["id"])
+
+    done = replay(srv, st["trace"], on_done=check, timeout_s=300)
+    srv.close()
+    assert len(done) == 4000
+    assert not bad, bad[:10]
