@@ -223,3 +223,35 @@ def test_serving_full_size(gf):
     srv.close()
     assert len(done) == 4000
     assert not bad, bad[:10]
+
+
+@pytest.mark.parametrize("n,form", [(8, 1), (8, 2), (4, 3), (8, "single")])
+def test_generation_past_2_gib(gf, n, form):
+    """One generation whose sources span more than 2^31 bytes (16 rows of 128 MiB +
+    12,345 B): the kernels' 64-bit offset paths, checked on sampled columns near the
+    start, across the 2^31 boundary of the row offsets and at the ragged end."""
+    torch = torch_cuda()
+    N, K, L = 16, 4, (1 << 27) + 12345
+    ld = L + 3          # odd pitch: rows are not word aligned past the first
+    if form in (2,):
+        ld = (L + 15) // 16 * 16   # the bit-matrix form's DMA path needs word-aligned rows
+    S = bench.device_bytes(torch, N * ld, synth.key(65, n))
+    Cm = bench.device_bytes(torch, K * N, synth.key(66, n), 1 << n).view(K, N)
+    Y = torch.full((K * ld,), 0xA5, dtype=torch.uint8, device="cuda")
+    S2, Y2 = S.view(N, ld)[:, :L], Y.view(K, ld)[:, :L]
+    if form == "single":
+        gf.gf_encode(n, Cm, S2, Y2)
+    else:
+        plan = gf.gf_plan_encode(n, [(Cm, S2, Y2)], tune={"form": form})
+        assert plan.tuning()["form"] == form
+        gf.gf_plan_launch_graph(plan)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(synth.key(67, n))
+    cols = sorted({0, 1, 255, 256, L - 1, L - 2, L - 300, (1 << 27) - 1, 1 << 27,
+                   *(int(x) for x in rng.integers(0, L, 8))})
+    cidx = torch.tensor(cols, device="cuda")
+    want = oracle.encode(n, Cm.cpu().numpy(), S2.index_select(1, cidx).cpu().numpy())
+    got = Y2.index_select(1, cidx).cpu().numpy()
+    assert (got == want).all(), cols
+    if form != "single":
+        plan.destroy()
