@@ -701,13 +701,14 @@ __device__ void invert_rows(uint32_t *A, RowOf row, int N, uint8_t *__restrict__
     __shared__ int piv[MAXN];
     __shared__ int src[MAXN];
     uint8_t *Ab = reinterpret_cast<uint8_t *>(A);
-    // NT threads take part: the whole workgroup (256, barriers between the
-    // phases) or its first wave alone (64, which needs no workgroup barrier:
+    // NT threads take part: the whole workgroup (256 or 1024, barriers between
+    // the phases) or its first wave alone (64, which needs no workgroup barrier:
     // a wave's LDS accesses complete in order).
-    static_assert(NT == 256 || (NT == 64 && MAXN <= 64), "invert_rows runs on 256 threads, or on 64 for N <= 64");
+    static_assert(NT == 256 || NT == 1024 || (NT == 64 && MAXN <= 64),
+                  "invert_rows runs on 256 or 1024 threads, or on 64 for N <= 64");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     auto sync = [&]() {
-        if constexpr (NT == 256)
+        if constexpr (NT >= 256)
             __syncthreads();
         else
             wave_sync();
@@ -746,7 +747,7 @@ __device__ void invert_rows(uint32_t *A, RowOf row, int N, uint8_t *__restrict__
         const uint64_t m = __ballot(ok);
         if constexpr (NT == 64)
             return m ? (int)__builtin_ctzll(m) : (1 << 30);
-        if (lane == 0)
+        if (lane == 0 && wave < 4)   // rows < 256 sit in the first four waves
             cand[wave] = m ? wave * 64 + __builtin_ctzll(m) : (1 << 30);
         sync();
         const int pr = min(min(cand[0], cand[1]), min(cand[2], cand[3]));
@@ -865,6 +866,18 @@ __device__ void invert_body(const uint8_t *__restrict__ Cg, int N, uint8_t *__re
     invert_rows<MAXN>(A, [&](int r) { return Cg + (uint64_t)r * N; }, N, Cinv, rank_out, ptab4, invg);
 }
 
+// One matrix of more than 64 columns on 1024 threads: the pivot steps are
+// latency-bound, and four times the waves hide more of it.
+template <int MAXN>
+__global__ __launch_bounds__(1024) void k_invert_one_wide(const uint8_t *__restrict__ C, int N,
+                                                          uint8_t *__restrict__ Cinv, int *rank,
+                                                          const uint4 *__restrict__ ptab4,
+                                                          const uint8_t *__restrict__ invg)
+{
+    __shared__ uint32_t A[MAXN * (MAXN / 4 + 1)];
+    invert_rows<MAXN, 1024>(A, [&](int r) { return C + (uint64_t)r * N; }, N, Cinv, rank, ptab4, invg);
+}
+
 template <int MAXN>
 __global__ __launch_bounds__(256) void k_invert_one(const uint8_t *__restrict__ C, int N, uint8_t *__restrict__ Cinv,
                                                     int *rank, const uint4 *__restrict__ ptab4,
@@ -974,12 +987,12 @@ __global__ __launch_bounds__(256) void k_small(const uint8_t *__restrict__ C, in
 // c[pivot(r)] * R[r] for all r at once clears every pivot column.  If nothing
 // is left the packet carried no new information.  Otherwise c is scaled to a
 // leading 1, its pivot column is cleared from the rows of R, and it is stored
-// with its raw coefficients and payload.  At rank N the raw coefficient
-// matrix is inverted (Gauss-Jordan, as in gf_invert) and the completion step
-// is recorded, which releases the payload product S = Csel^-1 * Bsel.
+// with its raw coefficients and payload.  At rank N the completion step is
+// recorded; k_absorb_invert, launched next, inverts the raw coefficient
+// matrix (Gauss-Jordan, as in gf_invert), which releases the payload product
+// S = Csel^-1 * Bsel of the step.
 //
-// During a step R lives in LDS (the inversion's matrix buffer, free until
-// then); packet descriptors are cached 64 at a time and the next packet's
+// During a step R lives in LDS; packet descriptors are cached 64 at a time and the next packet's
 // coefficients are fetched while the current one is reduced, so the loop over
 // packets touches device memory only for those prefetches.  The innovative
 // packets' raw coefficients and payloads are copied out after the loop.
@@ -1000,7 +1013,6 @@ __global__ __launch_bounds__(256) void k_absorb(const DevAbsorb *__restrict__ it
     __shared__ const uint8_t *row_pay[256];
     __shared__ DevPacket pkc[ABSORB_PKC];
     __shared__ int cand[4];
-    __shared__ int inv_rank;
     const DevAbsorb it = items[blockIdx.x];
     const DevDecSlot &s = it.s;
     const int N = (int)s.N, NW = (N + 3) >> 2;
@@ -1133,19 +1145,27 @@ __global__ __launch_bounds__(256) void k_absorb(const DevAbsorb *__restrict__ it
         s.meta[2] += seen;
         s.meta[3] += dropped;
     }
-    if (rank == N) {
-        __syncthreads();   // Rl is free: the inversion reads the raw rows from their sources
-        invert_rows<256>(Rl,
-                         [&](int r) {
-                             return r < rank0 ? s.Csel + (uint64_t)r * N : row_coef[r];
-                         },
-                         N, s.Cinv, &inv_rank, ptab4, invg);
-        __syncthreads();
-        if (tid == 0) {
-            __threadfence();
-            s.meta[1] = it.step;
-        }
-    }
+    // complete: k_absorb_invert (launched next) inverts Csel before the step's product
+    if (rank == N && tid == 0)
+        s.meta[1] = it.step;
+}
+
+// The generations that reached full rank in this step: Cinv = Csel^-1 on 1024
+// threads (the pivot steps are latency-bound; four times the waves of the
+// absorb workgroup hide more of it).  Csel holds the innovative coefficient
+// vectors, so it is invertible.
+__global__ __launch_bounds__(1024) void k_absorb_invert(const DevAbsorb *__restrict__ items,
+                                                        const uint4 *__restrict__ ptab4,
+                                                        const uint8_t *__restrict__ invg)
+{
+    __shared__ uint32_t A[256 * 65];
+    __shared__ int inv_rank;
+    const DevAbsorb it = items[blockIdx.x];
+    const DevDecSlot &s = it.s;
+    const int N = (int)s.N;
+    if (N > 256 || s.meta[0] != N || s.meta[1] != it.step)
+        return;
+    invert_rows<256, 1024>(A, [&](int r) { return s.Csel + (uint64_t)r * N; }, N, s.Cinv, &inv_rank, ptab4, invg);
 }
 
 __global__ void k_meta_init(int *const *__restrict__ metas, int n)
@@ -1329,9 +1349,9 @@ hipError_t launch_invert(const DevSys *sys, int count, const uint8_t *C, int N, 
         else if (N <= 64)
             hipLaunchKernelGGL(k_invert_one<64>, dim3(1), dim3(256), 0, s, C, N, Cinv, rank, pt, inv_field);
         else if (N <= 128)
-            hipLaunchKernelGGL(k_invert_one<128>, dim3(1), dim3(256), 0, s, C, N, Cinv, rank, pt, inv_field);
+            hipLaunchKernelGGL(k_invert_one_wide<128>, dim3(1), dim3(1024), 0, s, C, N, Cinv, rank, pt, inv_field);
         else
-            hipLaunchKernelGGL(k_invert_one<256>, dim3(1), dim3(256), 0, s, C, N, Cinv, rank, pt, inv_field);
+            hipLaunchKernelGGL(k_invert_one_wide<256>, dim3(1), dim3(1024), 0, s, C, N, Cinv, rank, pt, inv_field);
         return hipGetLastError();
     }
     if (count <= 0)
@@ -1354,6 +1374,8 @@ hipError_t launch_absorb(const DevAbsorb *items, int n, const DevPacket *pkts, c
     if (n <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(k_absorb, dim3(n), dim3(256), 0, s, items, pkts, reinterpret_cast<const uint4 *>(ptab_field),
+                       inv_field);
+    hipLaunchKernelGGL(k_absorb_invert, dim3(n), dim3(1024), 0, s, items, reinterpret_cast<const uint4 *>(ptab_field),
                        inv_field);
     return hipGetLastError();
 }
