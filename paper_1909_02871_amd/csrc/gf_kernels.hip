@@ -997,14 +997,18 @@ __global__ __launch_bounds__(256) void k_small(const uint8_t *__restrict__ C, in
 // packets touches device memory only for those prefetches.  The innovative
 // packets' raw coefficients and payloads are copied out after the loop.
 constexpr int ABSORB_PKC = 64;
+// One workgroup per generation of 16 waves: the passes over R of each packet
+// split its rows 16 ways (a step has at most a few dozen such workgroups, so
+// each has a CU to itself).
+constexpr int ABSORB_THREADS = 1024, ABSORB_WAVES = ABSORB_THREADS / 64;
 
-__global__ __launch_bounds__(256) void k_absorb(const DevAbsorb *__restrict__ items,
+__global__ __launch_bounds__(ABSORB_THREADS) void k_absorb(const DevAbsorb *__restrict__ items,
                                                 const DevPacket *__restrict__ pkts, const uint4 *__restrict__ ptab4,
                                                 const uint8_t *__restrict__ invg)
 {
-    __shared__ uint32_t Rl[256 * 65];   // row r at Rl + 65 r (odd stride); later the inversion's matrix
+    __shared__ uint32_t Rl[256 * 65];   // row r at Rl + 65 r (odd stride)
     __shared__ uint32_t cw[64];
-    __shared__ uint32_t part[4][64];
+    __shared__ uint32_t part[ABSORB_WAVES][64];
     __shared__ uint4 T[256][2];
     __shared__ uint8_t IV[256];
     __shared__ uint8_t fcol[256];
@@ -1023,12 +1027,13 @@ __global__ __launch_bounds__(256) void k_absorb(const DevAbsorb *__restrict__ it
     if (rank >= N || N > 256)
         return;
     const int rank0 = rank;
-    for (int i = tid; i < 512; i += 256)
+    for (int i = tid; i < 512; i += ABSORB_THREADS)
         T[i >> 1][i & 1] = ptab4[i];
-    IV[tid] = invg[tid];
-    for (int i = tid; i < rank; i += 256)
+    if (tid < 256)
+        IV[tid] = invg[tid];
+    for (int i = tid; i < rank; i += ABSORB_THREADS)
         pivc[i] = s.meta[4 + i];
-    for (int i = tid; i < rank * NW; i += 256) {
+    for (int i = tid; i < rank * NW; i += ABSORB_THREADS) {
         const int r = i / NW, w = i - r * NW;
         Rl[r * 65 + w] = reinterpret_cast<const uint32_t *>(s.R + (uint64_t)r * s.rs)[w];
     }
@@ -1060,27 +1065,32 @@ __global__ __launch_bounds__(256) void k_absorb(const DevAbsorb *__restrict__ it
         if (have_next && tid < NW)
             nextv = coef_dword(pkc[slot + 1].coef);
         __syncthreads();
-        for (int r = tid; r < rank; r += 256) {   // the vector's entry in each row's pivot column
+        for (int r = tid; r < rank; r += ABSORB_THREADS) {   // the vector's entry in each row's pivot column
             const int pc = pivc[r];
             fcol[r] = (uint8_t)(cw[pc >> 2] >> (8 * (pc & 3)));
         }
         __syncthreads();
-        if (lane < NW) {   // wave w sums rows w, w + 4, ... of column dword `lane`
+        if (lane < NW) {   // wave w sums rows w, w + W, ... of column dword `lane`
             uint32_t acc = 0;
 #pragma unroll 4
-            for (int r = wave; r < rank; r += 4) {   // a zero factor adds a zero product
+            for (int r = wave; r < rank; r += ABSORB_WAVES) {   // a zero factor adds a zero product
                 const uint32_t f = fcol[r];
                 acc ^= prod4(T[f][0], T[f][1].x, Rl[r * 65 + lane]);
             }
             part[wave][lane] = acc;
         }
         __syncthreads();
-        if (tid < NW)
-            cw[tid] ^= part[0][tid] ^ part[1][tid] ^ part[2][tid] ^ part[3][tid];
+        if (tid < NW) {
+            uint32_t x = cw[tid];
+#pragma unroll
+            for (int w = 0; w < ABSORB_WAVES; w++)
+                x ^= part[w][tid];
+            cw[tid] = x;
+        }
         __syncthreads();
         const bool nz = tid < N && ((cw[tid >> 2] >> (8 * (tid & 3))) & 0xFFu) != 0;
         const uint64_t m = __ballot(nz);
-        if (lane == 0)
+        if (lane == 0 && wave < 4)   // entries < 256 sit in the first four waves
             cand[wave] = m ? wave * 64 + __builtin_ctzll(m) : (1 << 30);
         __syncthreads();
         const int lead = min(min(cand[0], cand[1]), min(cand[2], cand[3]));
@@ -1095,13 +1105,13 @@ __global__ __launch_bounds__(256) void k_absorb(const DevAbsorb *__restrict__ it
             const uint32_t iv = IV[lv];
             cw[tid] = prod4(T[iv][0], T[iv][1].x, cw[tid]);
         }
-        for (int r = tid; r < rank; r += 256)
+        for (int r = tid; r < rank; r += ABSORB_THREADS)
             fcol[r] = Rb[r * 260 + lead];
         __syncthreads();
-        if (lane < NW) {   // wave w clears the new pivot column from rows w, w + 4, ...
+        if (lane < NW) {   // wave w clears the new pivot column from rows w, w + W, ...
             const uint32_t c = cw[lane];
 #pragma unroll 4
-            for (int r = wave; r < rank; r += 4) {
+            for (int r = wave; r < rank; r += ABSORB_WAVES) {
                 const uint32_t f = fcol[r];
                 Rl[r * 65 + lane] ^= prod4(T[f][0], T[f][1].x, c);
             }
@@ -1117,28 +1127,28 @@ __global__ __launch_bounds__(256) void k_absorb(const DevAbsorb *__restrict__ it
         __syncthreads();
     }
     // R back to device memory; the new rows' raw coefficients and payloads
-    for (int i = tid; i < rank * NW; i += 256) {
+    for (int i = tid; i < rank * NW; i += ABSORB_THREADS) {
         const int r = i / NW, w = i - r * NW;
         reinterpret_cast<uint32_t *>(s.R + (uint64_t)r * s.rs)[w] = Rl[r * 65 + w];
     }
     for (int rr = rank0; rr < rank; rr++) {
         const uint8_t *pc = row_coef[rr];
-        for (int b = tid; b < N; b += 256)
+        for (int b = tid; b < N; b += ABSORB_THREADS)
             s.Csel[(uint64_t)rr * N + b] = pc[b];
         const uint8_t *src = row_pay[rr];
         uint8_t *dst = s.Bsel + (uint64_t)rr * s.ld;
         if (((((uintptr_t)dst) | ((uintptr_t)src)) & 3u) == 0) {
             const uint64_t words = s.len >> 2;
-            for (uint64_t w = tid; w < words; w += 256)
+            for (uint64_t w = tid; w < words; w += ABSORB_THREADS)
                 reinterpret_cast<uint32_t *>(dst)[w] = reinterpret_cast<const uint32_t *>(src)[w];
-            for (uint64_t b = (words << 2) + tid; b < s.len; b += 256)
+            for (uint64_t b = (words << 2) + tid; b < s.len; b += ABSORB_THREADS)
                 dst[b] = src[b];
         } else {
-            for (uint64_t b = tid; b < s.len; b += 256)
+            for (uint64_t b = tid; b < s.len; b += ABSORB_THREADS)
                 dst[b] = src[b];
         }
     }
-    for (int i = tid; i < rank; i += 256)
+    for (int i = tid; i < rank; i += ABSORB_THREADS)
         s.meta[4 + i] = pivc[i];
     if (tid == 0) {
         s.meta[0] = rank;
@@ -1373,8 +1383,8 @@ hipError_t launch_absorb(const DevAbsorb *items, int n, const DevPacket *pkts, c
 {
     if (n <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_absorb, dim3(n), dim3(256), 0, s, items, pkts, reinterpret_cast<const uint4 *>(ptab_field),
-                       inv_field);
+    hipLaunchKernelGGL(k_absorb, dim3(n), dim3(ABSORB_THREADS), 0, s, items, pkts,
+                       reinterpret_cast<const uint4 *>(ptab_field), inv_field);
     hipLaunchKernelGGL(k_absorb_invert, dim3(n), dim3(1024), 0, s, items, reinterpret_cast<const uint4 *>(ptab_field),
                        inv_field);
     return hipGetLastError();
