@@ -51,8 +51,8 @@ KERNEL_SOURCES = {2: ("gf_mfma.hip", "gf_queue.h", "gf_types.h"),
 # 1 GiB device copy (fetch x 2.000, write x 1.000); keyed by the sha256 of the kernel's sources, so a
 # changed kernel reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("2703b4c06ce85a46f64d0792d04baeb9ece3016067a3dee21fc74f943cd0dde3", 2): 1462874 * 1024 * 2.0 + 2468920 * 1024,
-    ("b6d09bac99eb379cd710863dbfd295bfaf2f783145240a977e583581daccc1d0", 1): 3101279 * 1024 * 2.0 + 2449820 * 1024,
+    ("7ad78d1933b585a4c6d0e24c967c05ae4650722f57dbacd37f7a163f88507ed4", 2): 1460653 * 1024 * 2.0 + 2468953 * 1024,
+    ("1a952e22777da81a98b85761a4df95aabe2fa1d14b7f451ff6e1b06c467140bd", 1): 3099752 * 1024 * 2.0 + 2449757 * 1024,
 }
 
 

@@ -26,8 +26,6 @@ namespace gfnc {
 
 namespace {
 
-constexpr int NC = 32;   // source rows per LDS table stage
-
 struct Sel {
     uint32_t a, b, c;
 };

@@ -251,7 +251,7 @@ __device__ __forceinline__ void mf_tile(const DevGen &g, int k0, int nks, const 
                                         gf_v16f (&acc)[4][2], int wave, int lane)
 {
     const int r = lane & 31, h = lane >> 5;
-    const int K = (int)g.K, N = (int)g.N;
+    const int N = (int)g.N;
     const uint64_t nstrips = (g.len + MF_STRIP - 1) / MF_STRIP;
     const uint64_t lane_col = (uint64_t)wave * 64u + 2u * (uint64_t)r;
     auto load_src = [&](uint64_t strip, int ks, uint32_t (&u)[4]) {
