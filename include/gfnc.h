@@ -131,7 +131,11 @@ int gf_invert(int field, const uint8_t *C, int N, uint8_t *Cinv, int *d_rank, vo
  * A plan describes many uneven generations once; launching it is a single
  * persistent kernel (encode) or an elimination kernel plus a persistent
  * apply kernel (decode).  Plans own their device schedule and workspace;
- * creating one allocates and synchronises, launching one does neither. */
+ * creating one allocates and synchronises, launching one does neither.
+ * A plan runs on the device that was current when it was created (launching
+ * it with another device current is GF_EINVAL).  Launches of one plan share
+ * its work-queue counters, so they must not overlap: launch a plan again only
+ * on the same stream, or after the previous launch has completed. */
 typedef struct {
     const uint8_t *C;   /* device, K x N */
     const uint8_t *S;   /* device, N rows, ld_s apart */
@@ -255,9 +259,16 @@ int gf_plan_recode(int field, const gf_recode_desc *descs, int count, const gf_t
  * used once a step runs at or after its release time.  Completion time is
  * the `now` of the call that observed it.
  *
- * Not thread-safe across calls on one server except where noted: calls are
- * serialised by an internal mutex.  A completed request's output (device,
- * `out` with row pitch `ld_out`) stays valid until gf_serve_release. */
+ * Calls on one server may come from several threads; an internal mutex
+ * serialises them.  A completed request's output (device, `out` with row
+ * pitch `ld_out`) stays valid until gf_serve_release.
+ *
+ * Errors: argument errors are returned and change nothing.  A device or
+ * memory failure inside gf_serve_step or gf_serve_drain (GF_EDEVICE,
+ * GF_ENOMEM) can leave requests taken off their queues but never launched,
+ * so the server keeps that code: every later submit, push, step and drain
+ * returns it, while poll, copy_out, release and stats still serve what had
+ * completed; destroy the server to recover. */
 typedef struct gf_server gf_server;
 
 typedef struct {

@@ -908,11 +908,21 @@ int gf_plan_decode(int field, const gf_sys *sys, int count, const gf_tuning *tun
     return GF_OK;
 }
 
+// A plan's device buffers belong to the device that was current when it was
+// made; it runs only while that device is current.
+static int plan_device_ok(const gf_plan *p)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return GF_EDEVICE;
+    return dev == p->dev ? GF_OK : GF_EINVAL;
+}
+
 static int run_plan(gf_plan *p, int *d_rank, hipStream_t s)
 {
     DevState *d;
-    int rc = current_state(&d);
-    if (rc)
+    int rc = plan_device_ok(p);
+    if (rc || (rc = current_state(&d)))
         return rc;
     const int f = p->field;
     if (p->head && (rc = run_plan(p->head, nullptr, s)))
@@ -969,6 +979,8 @@ int gf_plan_launch_graph(gf_plan *p, int *d_rank, void *stream)
 {
     if (!p)
         return GF_EINVAL;
+    if (int rc = plan_device_ok(p))
+        return rc;
     if (p->exec && p->graph_rank != d_rank) {
         (void)hipGraphExecDestroy(p->exec);
         (void)hipGraphDestroy(p->graph);
@@ -981,8 +993,11 @@ int gf_plan_launch_graph(gf_plan *p, int *d_rank, void *stream)
         int rc = run_plan(p, p->kind == 1 ? d_rank : nullptr, p->cap);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(p->cap, &g);
-        if (rc)
+        if (rc) {
+            if (g)
+                (void)hipGraphDestroy(g);
             return rc;
+        }
         if (e != hipSuccess || !g)
             return GF_EDEVICE;
         hipGraphExec_t x = nullptr;
@@ -1012,8 +1027,12 @@ void gf_plan_destroy(gf_plan *p)
 {
     if (!p)
         return;
+    int cur = -1;
+    const bool other = hipGetDevice(&cur) == hipSuccess && cur != p->dev && hipSetDevice(p->dev) == hipSuccess;
     (void)hipDeviceSynchronize();
     plan_free_device(p);
+    if (other)
+        (void)hipSetDevice(cur);
     delete p;
 }
 

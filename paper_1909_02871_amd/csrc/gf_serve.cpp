@@ -145,6 +145,7 @@ struct gf_server {
     StepBuf bufs[kInflight + 1];
     int next_buf = 0;
     gf_serve_counters st{};
+    int err = GF_OK;   // first device or memory failure of a step; sticky
 };
 
 namespace {
@@ -302,6 +303,15 @@ int ensure_buf(StepBuf &b, size_t bytes, size_t nstatus)
 
 size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
+// A step or drain that fails part-way leaves requests taken off their queues
+// but never launched or collected, so the server refuses further work.
+int fail(gf_server *sv, int rc)
+{
+    if (rc && !sv->err)
+        sv->err = rc;
+    return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -402,6 +412,8 @@ int gf_serve_submit_encode(gf_server *sv, uint64_t id, const uint8_t *C, int K, 
     if (N > GF_MAX_N || K > GF_MAX_K)
         return GF_ERANGE;
     std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->err)
+        return sv->err;
     if (sv->reqs.count(id))
         return GF_EINVAL;
     Req *r = new Req;
@@ -433,6 +445,8 @@ int gf_serve_submit_decode(gf_server *sv, uint64_t id, int N, size_t len, double
     if (N > GF_MAX_N)
         return GF_ERANGE;
     std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->err)
+        return sv->err;
     if (sv->reqs.count(id))
         return GF_EINVAL;
     Req *r = new Req;
@@ -459,6 +473,8 @@ int gf_serve_push_packet(gf_server *sv, uint64_t id, const uint8_t *coef, const 
     if (!sv || !coef || !payload)
         return GF_EINVAL;
     std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->err)
+        return sv->err;
     auto it = sv->reqs.find(id);
     if (it == sv->reqs.end() || it->second->kind != 1 || it->second->state == DONE)
         return GF_EINVAL;
@@ -493,9 +509,11 @@ int gf_serve_step(gf_server *sv, double now)
     if (!sv)
         return GF_EINVAL;
     std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->err)
+        return sv->err;
     int rc = collect(sv, now, true);
     if (rc)
-        return rc;
+        return fail(sv, rc);
 
     // admission: FIFO, stop at the first request that does not fit
     std::vector<Req *> admitted;
@@ -595,7 +613,7 @@ int gf_serve_step(gf_server *sv, double now)
         const size_t total = align16(o_stat + status_meta.size() * sizeof(int *));
         // the buffer of this ring slot was last used kInflight + 1 steps ago; that step has retired
         if ((rc = ensure_buf(b, total, status_meta.size())))
-            return rc;
+            return fail(sv, rc);
         memcpy(b.host + o_abs, absorb.data(), absorb.size() * sizeof(DevAbsorb));
         memcpy(b.host + o_pk, pk.data(), pk.size() * sizeof(DevPacket));
         memcpy(b.host + o_gen, gens.data(), gens.size() * sizeof(DevGen));
@@ -634,7 +652,7 @@ int gf_serve_step(gf_server *sv, double now)
         if (e == hipSuccess)
             e = hipEventRecord(b.ev, s);
         if (e != hipSuccess)
-            return GF_EDEVICE;
+            return fail(sv, GF_EDEVICE);
     }
     sv->inflight.push_back(std::move(f));
     return (int)sv->inflight.size();
@@ -707,9 +725,11 @@ int gf_serve_drain(gf_server *sv, double now)
     if (!sv)
         return GF_EINVAL;
     std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->err)
+        return sv->err;
     while (!sv->inflight.empty()) {
         if (!sv->cfg.dry_run && hipEventSynchronize(sv->bufs[sv->inflight.front().buf].ev) != hipSuccess)
-            return GF_EDEVICE;
+            return fail(sv, GF_EDEVICE);
         retire(sv, now);
     }
     return GF_OK;
