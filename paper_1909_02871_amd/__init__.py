@@ -148,6 +148,18 @@ def _dev_u8(t, name: str):
     return t
 
 
+def _rank_ptr(d_rank, count: int, name: str = "d_rank"):
+    """Device pointer of an int32 CUDA tensor with at least `count` entries, or None."""
+    if d_rank is None:
+        return None
+    torch = _torch()
+    if not isinstance(d_rank, torch.Tensor) or d_rank.device.type != "cuda" or d_rank.dtype != torch.int32:
+        raise TypeError("%s must be a CUDA int32 tensor" % name)
+    if not d_rank.is_contiguous() or d_rank.numel() < count:
+        raise ValueError("%s must be contiguous with at least %d entries" % (name, count))
+    return d_rank.data_ptr()
+
+
 def _rows(t, name: str) -> Tuple[int, int, int]:
     """(rows, row length, leading dimension in bytes) of a 2-D uint8 tensor with unit inner stride."""
     _dev_u8(t, name)
@@ -230,21 +242,21 @@ def gf_decode(field: int, Cm, B, S, ws=None, d_rank=None, length: Optional[int] 
         raise ValueError("shape mismatch")
     if ws is None:
         ws = torch.empty(gf_decode_workspace(N), dtype=torch.uint8, device=Cm.device)
-    rp = 0
-    if d_rank is not None:
-        if d_rank.dtype != torch.int32 or d_rank.device.type != "cuda":
-            raise TypeError("d_rank must be a CUDA int32 tensor")
-        rp = d_rank.data_ptr()
+    _dev_u8(ws, "ws")
+    if not ws.is_contiguous():
+        raise ValueError("ws must be contiguous")
+    rp = _rank_ptr(d_rank, 1)
     _check(lib().gf_decode(field, Cm.data_ptr(), N, B.data_ptr(), ld_b, S.data_ptr(), ld_s, L, ws.data_ptr(),
-                           ws.numel(), rp or None, _stream(stream)), "gf_decode")
+                           ws.numel(), rp, _stream(stream)), "gf_decode")
     return ws
 
 
 def gf_invert(field: int, Cm, Cinv, d_rank=None, stream=None):
     N, N2, _ = _rows(Cm, "C")
+    _dev_u8(Cinv, "Cinv")
     if N != N2 or not Cm.is_contiguous() or not Cinv.is_contiguous() or tuple(Cinv.shape) != (N, N):
         raise ValueError("C and Cinv must be contiguous N x N matrices")
-    rp = d_rank.data_ptr() if d_rank is not None else None
+    rp = _rank_ptr(d_rank, 1)
     _check(lib().gf_invert(field, Cm.data_ptr(), N, Cinv.data_ptr(), rp, _stream(stream)), "gf_invert")
 
 
@@ -332,12 +344,12 @@ def gf_encode_batched(plan: Plan, stream=None):
 
 
 def gf_decode_batched(plan: Plan, d_rank=None, stream=None):
-    rp = d_rank.data_ptr() if d_rank is not None else None
+    rp = _rank_ptr(d_rank, plan.count)
     _check(lib().gf_decode_batched(plan._h, rp, _stream(stream)), "gf_decode_batched")
 
 
 def gf_plan_launch_graph(plan: Plan, d_rank=None, stream=None):
-    rp = d_rank.data_ptr() if d_rank is not None else None
+    rp = _rank_ptr(d_rank, plan.count) if plan.kind == "decode" else None
     _check(lib().gf_plan_launch_graph(plan._h, rp, _stream(stream)), "gf_plan_launch_graph")
 
 
@@ -444,17 +456,24 @@ class Server:
         self._h = h
         self.field = field
         self._buf = (gf_serve_done * 1024)()
+        self._shape = {}   # request id -> (output rows, bytes per row)
 
     @staticmethod
     def _ptr(x):
-        return x.data_ptr() if hasattr(x, "data_ptr") else int(x)
+        if hasattr(x, "data_ptr"):
+            if getattr(x, "device", None) is None or x.device.type != "cuda":
+                raise TypeError("server inputs must be CUDA tensors or device pointers")
+            return x.data_ptr()
+        return int(x)
 
     def submit_encode(self, rid: int, Cm, S, K: int, N: int, ld_s: int, length: int, now: float):
         _check(lib().gf_serve_submit_encode(self._h, rid, self._ptr(Cm), K, N, self._ptr(S), ld_s, length, now),
                "gf_serve_submit_encode")
+        self._shape[rid] = (K, length)
 
     def submit_decode(self, rid: int, N: int, length: int, now: float):
         _check(lib().gf_serve_submit_decode(self._h, rid, N, length, now), "gf_serve_submit_decode")
+        self._shape[rid] = (N, length)
 
     def push_packet(self, rid: int, coef, payload, release: float):
         _check(lib().gf_serve_push_packet(self._h, rid, self._ptr(coef), self._ptr(payload), release),
@@ -494,11 +513,15 @@ class Server:
 
     def release(self, rid: int):
         _check(lib().gf_serve_release(self._h, rid), "gf_serve_release")
+        self._shape.pop(rid, None)
 
     def copy_out(self, rid: int, dst, stream=None):
         """Copy a completed request's output rows into the 2-D CUDA uint8 tensor `dst`
         (enqueued on `stream`, default torch's current stream)."""
         _dev_u8(dst, "dst")
+        rows, length = self._shape.get(rid, (0, 0))
+        if dst.dim() != 2 or (dst.stride(1) != 1 and dst.shape[1] > 1) or dst.shape[0] < rows or dst.shape[1] < length:
+            raise ValueError("dst must be 2-D with contiguous rows, at least %d x %d" % (rows, length))
         _check(lib().gf_serve_copy_out(self._h, rid, dst.data_ptr(), max(dst.stride(0), dst.shape[1]),
                                        _stream(stream)), "gf_serve_copy_out")
 

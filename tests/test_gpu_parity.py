@@ -544,3 +544,49 @@ def test_batched_recode_mixed_layouts(gf, n, form):
         for i, (it, (wc, wy)) in enumerate(zip(items, wants)):
             assert (host(it[3]) == wc).all(), (mode, i)
             assert (host(it[4]) == wy).all(), (mode, i)
+
+
+# ------------------------------------------------------------------ binding checks
+
+def test_binding_rejects_host_and_short_buffers(gf):
+    """Arguments that would hand a kernel a host pointer, or a rank or output
+    buffer shorter than the call writes, raise in the binding before any launch."""
+    torch = torch_cuda()
+    print("binding checks", flush=True)
+    N = 8
+    Cm = dev(_invertible(8, N, synth.key(2024)))
+    Cinv_host = torch.empty((N, N), dtype=torch.uint8)
+    with pytest.raises(TypeError):
+        gf.gf_invert(8, Cm, Cinv_host)
+    with pytest.raises(TypeError):   # rank must be int32 on the device
+        gf.gf_invert(8, Cm, torch.empty((N, N), dtype=torch.uint8, device="cuda"),
+                     d_rank=torch.zeros(1, dtype=torch.int64, device="cuda"))
+    B = dev(synth.random_bytes(synth.key(2025), N * 64).reshape(N, 64))
+    S = torch.empty((N, 64), dtype=torch.uint8, device="cuda")
+    with pytest.raises(TypeError):   # workspace on the host
+        gf.gf_decode(8, Cm, B, S, ws=torch.empty(gf.gf_decode_workspace(N), dtype=torch.uint8))
+    plan = gf.gf_plan_decode(8, [(Cm, B, S), (Cm, B, torch.empty_like(S))])
+    with pytest.raises(ValueError):  # one rank slot for two systems
+        gf.gf_decode_batched(plan, d_rank=torch.zeros(1, dtype=torch.int32, device="cuda"))
+    rank = torch.zeros(2, dtype=torch.int32, device="cuda")
+    gf.gf_decode_batched(plan, d_rank=rank)
+    torch.cuda.synchronize()
+    assert host(rank).tolist() == [N, N]
+    plan.destroy()
+
+    srv = gf.Server(field=8, budget_bytes=1 << 24)
+    with pytest.raises(TypeError):   # encode inputs on the host
+        srv.submit_encode(1, torch.zeros((4, N), dtype=torch.uint8), S, 4, N, 64, 64, 0.0)
+    Ce = synth.uniform_field(synth.key(2026), 4 * N, 8).reshape(4, N)
+    srv.submit_encode(1, dev(Ce), S, 4, N, 64, 64, 0.0)
+    srv.step(0.0)
+    srv.drain(0.0)
+    (d,) = srv.poll()
+    with pytest.raises(ValueError):  # three rows for a four-row output
+        srv.copy_out(1, torch.empty((3, 64), dtype=torch.uint8, device="cuda"))
+    out = torch.empty((4, 64), dtype=torch.uint8, device="cuda")
+    srv.copy_out(1, out)
+    torch.cuda.synchronize()
+    assert (host(out) == oracle.encode(8, Ce, host(S))).all()
+    srv.release(1)
+    srv.close()
