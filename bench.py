@@ -138,6 +138,10 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the other workloads (single generation, field/length sweep, GF(16) batch, "
                          "batched decode, K sweep)")
+    ap.add_argument("--only", default=None,
+                    choices=[name for name, _ in EXTRA_PARTS] + ["serve"],
+                    help="run just this one of the other workloads (or the serving runs), print its JSON "
+                         "and exit (for profiling one workload's kernels)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (to calibrate HBM counters) and exit")
     args = ap.parse_args()
@@ -164,6 +168,10 @@ def main():
         print(json.dumps({"copy_bytes": nb}))
         return
     gf.gf_init()
+    if args.only:
+        res = serve_bench(gf, torch, args) if args.only == "serve" else extra_workloads(gf, torch, args, args.only)
+        print(json.dumps({"only": args.only, "result": res}), flush=True)
+        return
     n = args.field
 
     # ------------------------------------------------------------ inputs
@@ -405,10 +413,18 @@ def relay_batch(gf, torch, count: int, keep_host: bool = False) -> dict:
     return out
 
 
-def extra_workloads(gf, torch, args) -> dict:
+def extra_workloads(gf, torch, args, only=None) -> dict:
     """The other measured workloads: one generation (latency), the plain field/length sweep,
-    the uneven batch over GF(16), recoding at a relay, the batched decode and a K sweep at fixed
-    packet length."""
+    the uneven batch over GF(16), recoding at a relay, the batched decode, a K sweep at fixed
+    packet length and the paper's CPU method on the host.  `only`: run just that one."""
+    out = {}
+    for name, fn in EXTRA_PARTS:
+        if only is None or only == name:
+            out.update(fn(gf, torch, args))
+    return out
+
+
+def part_single_generation(gf, torch, args) -> dict:
     out = {}
     # ---- one generation: GF(256), 16 x 16 x 1500 B, encode and decode back (latency, one launch each)
     g = synth.single_generation()
@@ -452,7 +468,11 @@ def extra_workloads(gf, torch, args) -> dict:
     log("single generation: encode %.1f us, decode %.1f us per call (one isolated call: %.1f / %.1f us)"
         % (enc_ms * 1e3, dec_ms * 1e3, enc_one, dec_one))
     del Cd, Sd, Yd, Rd, ws
+    return out
 
+
+def part_sweep(gf, torch, args) -> dict:
+    out = {}
     # ---- plain sweep: 4096 generations, N = K = 64, every field and packet length
     sweep = []
     count = 4096
@@ -486,7 +506,11 @@ def extra_workloads(gf, torch, args) -> dict:
             del plan, S, Cm, Y, R, d_regs
             torch.cuda.empty_cache()
     out["sweep"] = sweep
+    return out
 
+
+def part_uneven_gf16(gf, torch, args) -> dict:
+    out = {}
     # ---- the uneven batch over GF(16)
     b = synth.uneven_batch(4, args.count)
     S_dev = torch.from_numpy(b.source_blob()).to("cuda")
@@ -506,7 +530,11 @@ def extra_workloads(gf, torch, args) -> dict:
     plan.destroy()
     del plan, S_dev, C_dev, Y_dev
     torch.cuda.empty_cache()
+    return out
 
+
+def part_recode(gf, torch, args) -> dict:
+    out = {}
     # ---- recoding at a relay: the uneven GF(256) shapes; each relay holds M = N received packets
     # and sends Kout = N recoded ones.  Packets are rows [N coefficients | payload], 16-byte pitch.
     rb = relay_batch(gf, torch, args.count)
@@ -521,7 +549,11 @@ def extra_workloads(gf, torch, args) -> dict:
     plan.destroy()
     del plan, rb
     torch.cuda.empty_cache()
+    return out
 
+
+def part_decode(gf, torch, args) -> dict:
+    out = {}
     # ---- batched decode: 2048 systems, N in {32, 64, 128}, 1500 B, GF(256)
     db = synth.decode_batch(2048, 1500)
     count = len(db.Ns)
@@ -580,7 +612,11 @@ def extra_workloads(gf, torch, args) -> dict:
     dplan.destroy()
     del S_dev, B_dev, R_dev, C_dev
     torch.cuda.empty_cache()
+    return out
 
+
+def part_k_sweep(gf, torch, args) -> dict:
+    out = {}
     # ---- K sweep at 9000 B: where encode meets the HBM roofline
     ks = []
     for K in (1, 2, 4, 8, 16, 32, 64, 128, 256):
@@ -598,7 +634,11 @@ def extra_workloads(gf, torch, args) -> dict:
         del plan, S, Cm, Y
         torch.cuda.empty_cache()
     out["k_sweep_gf256_9000B"] = ks
+    return out
 
+
+def part_host_alg1(gf, torch, args) -> dict:
+    out = {}
     # ---- the paper's own CPU method on this host, one core (context)
     out["host_alg1_avx512"] = host_alg1_sweep()
     for pt in out["host_alg1_avx512"].get("points", []):
@@ -606,6 +646,11 @@ def extra_workloads(gf, torch, args) -> dict:
             log("host Alg. 1 %s %d B: %.2f GB/s (%.1f us per 16 x 16 encode)"
                 % (pt["field"], pt["packet_bytes"], pt["gbs"], pt["encode_us"]))
     return out
+
+
+EXTRA_PARTS = (("single_generation", part_single_generation), ("sweep", part_sweep),
+               ("uneven_gf16", part_uneven_gf16), ("recode", part_recode), ("decode", part_decode),
+               ("k_sweep", part_k_sweep), ("host_alg1", part_host_alg1))
 
 
 def single_generation_oracle(gf, torch, oracle) -> dict:
