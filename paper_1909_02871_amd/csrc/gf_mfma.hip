@@ -376,8 +376,6 @@ constexpr int vm_wait(int newer_loads)
 constexpr int kWaitAll = vm_wait(0);
 static_assert(4 * MF_PAIRS_AHEAD < 64, "vmcnt field is 6 bits");
 
-typedef unsigned short gf_u16x2 __attribute__((ext_vector_type(2)));
-
 // The operands of one step: the coefficient bits of the 4 row tiles and the
 // source bits of the wave's 2 column tiles.
 struct MfOperands {
@@ -385,10 +383,11 @@ struct MfOperands {
     gf_v8i b[2];
 };
 
+template <int RT0 = 0, int RT1 = 4>
 __device__ __forceinline__ void mf_mma(const MfOperands &o, gf_v16f (&acc)[4][2])
 {
 #pragma unroll
-    for (int rt = 0; rt < 4; rt++) {
+    for (int rt = RT0; rt < RT1; rt++) {
         acc[rt][0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(o.a[rt], o.b[0], acc[rt][0], 4, 4, 0, 0, 0, 0);
         acc[rt][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(o.a[rt], o.b[1], acc[rt][1], 4, 4, 0, 0, 0, 0);
     }
@@ -396,15 +395,13 @@ __device__ __forceinline__ void mf_mma(const MfOperands &o, gf_v16f (&acc)[4][2]
 
 constexpr int kMfRestart = 2048;
 
-// Instruction order for a step's products and the unpacking of the next
-// step's operands (whose LDS reads are already issued): two MFMAs while the
-// reads are in flight, then the unpacking spread between the remaining six.
+// Instruction order for the last six products of a step and the unpacking of
+// the next step's operands, one MFMA after every six vector instructions.
 __device__ __forceinline__ void mf_step_schedule()
 {
-    __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);   // MFMA
 #pragma unroll
     for (int i = 0; i < 6; i++) {
-        __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);   // VALU
+        __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);   // VALU
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
     }
 }
@@ -530,7 +527,7 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
         // MFMA operands.  Bytes of rows past N and past the packet end need no
         // masking (see copy_pair).
         struct Raw {
-            gf_u16x2 p01, p23;
+            uint32_t s[4];   // columns 2r, 2r + 1 of source rows 0..3 (one 16-bit read each)
             uint32_t y[4];
         };
         auto fetch_issue = [&](int zf, int ksf, auto wait_imm) {
@@ -538,31 +535,35 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
             asm volatile("" ::: "memory");
             const uint16_t *rows = reinterpret_cast<const uint16_t *>(&Sw[wave][zf & (MF_STAGES - 1)][4 * h][0]);
             Raw w;
-            w.p01.x = rows[0 * 32 + r];
-            w.p01.y = rows[1 * 32 + r];
-            w.p23.x = rows[2 * 32 + r];
-            w.p23.y = rows[3 * 32 + r];
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                w.s[q] = rows[q * 32 + r];
 #pragma unroll
             for (int rt = 0; rt < 4; rt++)
                 w.y[rt] = Ybuf[ksf][rt][lane];
             return w;
         };
         auto fetch_unpack = [&](const Raw &w, MfOperands &o) {
-            const uint32_t t01 = __builtin_bit_cast(uint32_t, w.p01);   // r0c0 r0c1 r1c0 r1c1
-            const uint32_t t23 = __builtin_bit_cast(uint32_t, w.p23);   // r2c0 r2c1 r3c0 r3c1
-            o.b[0] = fp4_source(__builtin_amdgcn_perm(t23, t01, 0x06040200u));   // column 2r of rows 0..3
-            o.b[1] = fp4_source(__builtin_amdgcn_perm(t23, t01, 0x07050301u));   // column 2r + 1
+            const uint32_t t01 = __builtin_amdgcn_perm(w.s[1], w.s[0], 0x05010400u);   // r0c0 r1c0 r0c1 r1c1
+            const uint32_t t23 = __builtin_amdgcn_perm(w.s[3], w.s[2], 0x05010400u);   // r2c0 r3c0 r2c1 r3c1
+            o.b[0] = fp4_source(__builtin_amdgcn_perm(t23, t01, 0x05040100u));   // column 2r of rows 0..3
+            o.b[1] = fp4_source(__builtin_amdgcn_perm(t23, t01, 0x07060302u));   // column 2r + 1
 #pragma unroll
             for (int rt = 0; rt < 4; rt++)
                 o.a[rt] = fp4_coef(w.y[rt]);
         };
         // One step: the next operands are read and unpacked while this step's
-        // products run (the scheduling fence keeps the reads ahead of them).
+        // products run.  The fences keep the LDS reads first and the first two
+        // products next, so the wait for the reads (the reads are kept as four
+        // separate words, since packing them would need their values at once)
+        // sits behind two MFMAs instead of in front of them.
         auto step = [&](int zn, int ksn, const MfOperands &cur, MfOperands &nxt, auto wait_imm) {
             const Raw w = fetch_issue(zn, ksn, wait_imm);
             __builtin_amdgcn_sched_barrier(0);
+            mf_mma<0, 1>(cur, acc);
+            __builtin_amdgcn_sched_barrier(0);
             fetch_unpack(w, nxt);
-            mf_mma(cur, acc);
+            mf_mma<1, 4>(cur, acc);
             mf_step_schedule();
         };
 
