@@ -51,8 +51,8 @@ KERNEL_SOURCES = {2: ("gf_mfma.hip", "gf_queue.h", "gf_types.h"),
 # 1 GiB device copy (fetch x 2.000, write x 1.000); keyed by the sha256 of the kernel's sources, so a
 # changed kernel reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("7ad78d1933b585a4c6d0e24c967c05ae4650722f57dbacd37f7a163f88507ed4", 2): 1460653 * 1024 * 2.0 + 2468953 * 1024,
-    ("1a952e22777da81a98b85761a4df95aabe2fa1d14b7f451ff6e1b06c467140bd", 1): 3099752 * 1024 * 2.0 + 2449757 * 1024,
+    ("2af0db5c06d9262f822681b4618cfebe16e5f0528c2624d7aa021e1ae926eb49", 2): 1502115 * 1024 * 2.0 + 2476407 * 1024,
+    ("1a952e22777da81a98b85761a4df95aabe2fa1d14b7f451ff6e1b06c467140bd", 1): 3099702 * 1024 * 2.0 + 2449784 * 1024,
 }
 
 
