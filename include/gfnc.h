@@ -46,7 +46,8 @@ typedef enum { GF_2 = 1, GF_4 = 2, GF_16 = 4, GF_256 = 8 } gf_field;
 
 enum {
     GF_OK = 0,
-    GF_EINVAL = -1,      /* bad argument: field, coefficient >= q, size, null, overlap */
+    GF_EINVAL = -1,      /* bad argument: field, coefficient >= q, size, null, overlap, or a
+                            buffer span ((rows - 1) * pitch + len) past the address space */
     GF_ENOTINIT = -2,    /* library could not initialise its tables */
     GF_EDEVICE = -3,     /* a HIP runtime call failed */
     GF_ESINGULAR = -4,   /* coefficient matrix not invertible (from gf_decode_sync) */

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <mutex>
 #include <numeric>
 #include <vector>
@@ -99,6 +100,23 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb)
 }
 
 size_t envelope(size_t rows, size_t ld, size_t len) { return rows == 0 || len == 0 ? 0 : (rows - 1) * ld + len; }
+
+// Byte span of `rows` rows `ld` apart, `len` bytes each, starting at p (0 when
+// empty); false when the span or its end address does not fit in 64 bits, so
+// the overlap checks never see a wrapped size.
+bool span_of(const void *p, size_t rows, size_t ld, size_t len, size_t *out)
+{
+    size_t n = 0;
+    if (rows > 0 && len > 0) {
+        if (rows > 1 && ld > (SIZE_MAX - len) / (rows - 1))
+            return false;
+        n = (rows - 1) * ld + len;
+    }
+    if (n > UINTPTR_MAX - (uintptr_t)p)
+        return false;
+    *out = n;
+    return true;
+}
 
 struct Single {
     int D;
@@ -224,9 +242,10 @@ static int region_common(int mode, int field, uint8_t *y, const uint8_t *x, int 
         return GF_EINVAL;
     if (len == 0)
         return GF_OK;
-    if (!y || !x)
+    size_t ny, nx;
+    if (!y || !x || !span_of(y, 1, 0, len, &ny) || !span_of(x, 1, 0, len, &nx))
         return GF_EINVAL;
-    if (y != x && overlap(y, len, x, len))
+    if (y != x && overlap(y, ny, x, nx))
         return GF_EINVAL;
     DevState *d;
     int rc = current_state(&d);
@@ -277,8 +296,10 @@ static int check_encode_args(int field, const uint8_t *C, int K, int N, const ui
         return GF_EINVAL;
     if ((N > 1 && ld_s < len) || (K > 1 && ld_y < len))
         return GF_EINVAL;
-    const size_t ey = envelope(K, ld_y, len);
-    if (overlap(Y, ey, S, envelope(N, ld_s, len)) || overlap(Y, ey, C, (size_t)K * N))
+    size_t ey, es, ec;
+    if (!span_of(Y, K, ld_y, len, &ey) || !span_of(S, N, ld_s, len, &es) || !span_of(C, K, N, N, &ec))
+        return GF_EINVAL;
+    if (overlap(Y, ey, S, es) || overlap(Y, ey, C, ec))
         return GF_EINVAL;
     return GF_OK;
 }
@@ -348,7 +369,8 @@ int gf_invert(int field, const uint8_t *C, int N, uint8_t *Cinv, int *d_rank, vo
         return GF_EINVAL;
     if (N > GF_MAX_N)
         return GF_ERANGE;
-    if (overlap(C, (size_t)N * N, Cinv, (size_t)N * N))
+    size_t nc, ni;
+    if (!span_of(C, N, N, N, &nc) || !span_of(Cinv, N, N, N, &ni) || overlap(C, nc, Cinv, ni))
         return GF_EINVAL;
     DevState *d;
     int rc = current_state(&d);
@@ -369,10 +391,12 @@ int gf_decode(int field, const uint8_t *C, int N, const uint8_t *B, size_t ld_b,
         return GF_EINVAL;
     if (len > 0 && (!B || !S || (N > 1 && (ld_b < len || ld_s < len))))
         return GF_EINVAL;
-    const size_t es = envelope(N, ld_s, len);
-    if (overlap(S, es, B, envelope(N, ld_b, len)) || overlap(S, es, C, (size_t)N * N) ||
-        overlap(S, es, ws, ws_bytes) || overlap(ws, ws_bytes, C, (size_t)N * N) ||
-        overlap(ws, ws_bytes, B, envelope(N, ld_b, len)))
+    size_t es, eb, ec, ew;
+    if (!span_of(S, N, ld_s, len, &es) || !span_of(B, N, ld_b, len, &eb) || !span_of(C, N, N, N, &ec) ||
+        !span_of(ws, 1, 0, ws_bytes, &ew))
+        return GF_EINVAL;
+    if (overlap(S, es, B, eb) || overlap(S, es, C, ec) || overlap(S, es, ws, ew) || overlap(ws, ew, C, ec) ||
+        overlap(ws, ew, B, eb))
         return GF_EINVAL;
     DevState *d;
     int rc = current_state(&d);
@@ -849,8 +873,11 @@ int gf_plan_decode(int field, const gf_sys *sys, int count, const gf_tuning *tun
             return GF_ERANGE;
         if (!s.C || (s.len > 0 && (!s.B || !s.S || (s.N > 1 && (s.ld_b < s.len || s.ld_s < s.len)))))
             return GF_EINVAL;
-        const size_t es = envelope(s.N, s.ld_s, s.len);
-        if (overlap(s.S, es, s.B, envelope(s.N, s.ld_b, s.len)) || overlap(s.S, es, s.C, (size_t)s.N * s.N))
+        size_t es, eb, ec;
+        if (!span_of(s.S, s.N, s.ld_s, s.len, &es) || !span_of(s.B, s.N, s.ld_b, s.len, &eb) ||
+            !span_of(s.C, s.N, s.N, s.N, &ec))
+            return GF_EINVAL;
+        if (overlap(s.S, es, s.B, eb) || overlap(s.S, es, s.C, ec))
             return GF_EINVAL;
     }
     gf_plan *p = new (std::nothrow) gf_plan;

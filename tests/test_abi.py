@@ -159,3 +159,41 @@ def test_plan_recode_argument_checks():
     assert L.gf_plan_recode(5, (gf.gf_recode_desc * 1)(d), 1, None, C.byref(h)) == gf.GF_EINVAL
     assert L.gf_plan_recode(8, None, 1, None, C.byref(h)) == gf.GF_EINVAL
     assert not h.value
+
+
+def test_spans_that_do_not_fit_the_address_space_are_rejected():
+    """A buffer's byte span, (rows - 1) * pitch + len, and its end address must
+    fit in 64 bits; otherwise the overlap checks would see a wrapped size."""
+    L = gf.lib()
+    top = (1 << 64) - 8
+    huge = 1 << 63
+    assert L.gf_region_madd(8, top, P2, 3, 100, None) == gf.GF_EINVAL           # y runs past 2^64
+    assert L.gf_region_mul(8, P1, top, 3, 100, None) == gf.GF_EINVAL            # x runs past 2^64
+    assert L.gf_encode(8, P1, 3, 2, P2, 10, P3, huge, 10, None) == gf.GF_EINVAL  # 2 * 2^63 + 10 wraps
+    assert L.gf_encode(8, P1, 2, 3, P2, huge, P3, 10, 10, None) == gf.GF_EINVAL
+    assert L.gf_encode(8, (1 << 64) - 2, 2, 2, P2, 10, P3, 10, 10, None) == gf.GF_EINVAL   # C's 4 bytes run past 2^64
+    ws = L.gf_decode_workspace(4)
+    assert L.gf_decode(8, P1, 4, P2, huge, P3, 10, 10, P4, ws, None, None) == gf.GF_EINVAL
+    assert L.gf_decode(8, P1, 4, P2, 10, P3, huge, 10, P4, ws, None, None) == gf.GF_EINVAL
+    assert L.gf_decode(8, P1, 4, P2, 10, P3, 10, 10, top, ws, None, None) == gf.GF_EINVAL
+    assert L.gf_invert(8, top, 4, P2, None, None) == gf.GF_EINVAL
+    assert L.gf_recode(8, P1, 3, 3, 5, P2, 5, P3, 100, P4, 5, P4 + 4096, huge, 100, None) == gf.GF_EINVAL
+    h = C.c_void_p()
+    sysd = (gf.gf_sys * 1)(gf.gf_sys(P1, P2, P3, 4, 0, 10, huge, 10))
+    assert L.gf_plan_decode(8, sysd, 1, None, C.byref(h)) == gf.GF_EINVAL and not h.value
+    gens = (gf.gf_gen * 1)(gf.gf_gen(P1, P2, P3, 3, 2, 10, 10, huge))
+    assert L.gf_plan_encode(8, gens, 1, None, C.byref(h)) == gf.GF_EINVAL and not h.value
+
+
+def test_spans_that_fit_still_pass_validation():
+    """The same calls with pitches that fit get past every argument check (and
+    then report the missing device: GF_EDEVICE without a GPU)."""
+    if gf.lib().gf_init() != gf.GF_EDEVICE:
+        pytest.skip("a device is present: valid calls would launch")
+    L = gf.lib()
+    assert L.gf_region_madd(8, P1, P2, 3, 100, None) == gf.GF_EDEVICE
+    assert L.gf_encode(8, P1, 3, 2, P2, 10, P3, 1 << 20, 10, None) == gf.GF_EDEVICE
+    assert L.gf_encode(8, P1, 1, 2, P2, 10, P3, 1 << 63, 10, None) == gf.GF_EDEVICE   # one row: pitch unused
+    ws = L.gf_decode_workspace(4)
+    assert L.gf_decode(8, P1, 4, P2, 10, P3, 10, 10, P4, ws, None, None) == gf.GF_EDEVICE
+    assert L.gf_invert(8, P1, 4, P2, None, None) == gf.GF_EDEVICE
