@@ -50,7 +50,9 @@ enum {
                             buffer span ((rows - 1) * pitch + len) past the address space */
     GF_ENOTINIT = -2,    /* library could not initialise its tables */
     GF_EDEVICE = -3,     /* a HIP runtime call failed */
-    GF_ESINGULAR = -4,   /* coefficient matrix not invertible (from gf_decode_sync) */
+    GF_ESINGULAR = -4,   /* coefficient matrix not invertible: not returned by the asynchronous
+                            calls (they write the rank to d_rank); for callers that synchronise
+                            and find rank < N */
     GF_ENOMEM = -5,      /* device or host allocation failed (plan creation only) */
     GF_ERANGE = -6       /* size above a documented limit */
 };
