@@ -53,7 +53,7 @@ enum {
     GF_ESINGULAR = -4,   /* coefficient matrix not invertible: not returned by the asynchronous
                             calls (they write the rank to d_rank); for callers that synchronise
                             and find rank < N */
-    GF_ENOMEM = -5,      /* device or host allocation failed (plan creation only) */
+    GF_ENOMEM = -5,      /* device or host allocation failed (plan and server creation, serving steps) */
     GF_ERANGE = -6       /* size above a documented limit */
 };
 
@@ -103,9 +103,9 @@ int gf_region_madd_batched(int field, const gf_region *d_regions, int count, siz
  * Eq. (1) for K coding vectors at once:
  *     Y[k][j] = sum_{i<N} C[k][i] * S[i][j],   k < K, j < len,
  * a product of the K x N coefficient matrix with the generation.
- * C: device, K x N row-major, one element per byte (entries >= q are an error
- *    only if checked: the kernel reads them modulo nothing -- callers keep
- *    them < q).
+ * C: device, K x N row-major, one element per byte.  Entries must be < q:
+ *    device matrices are not checked, and what an entry >= q contributes
+ *    depends on the kernel form.
  * S: device, N rows of len bytes, row i at S + i*ld_s (ld_s >= len).
  * Y: device, K rows, row k at Y + k*ld_y (ld_y >= len); overwritten.
  * Y must not overlap S or C.  1 <= N <= GF_MAX_N, K >= 0. */
