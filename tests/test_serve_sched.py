@@ -134,3 +134,55 @@ def test_percentiles():
     assert percentile(v, 100) == 100
     assert percentile([3.0], 99) == 3.0
     assert percentile([5, 1, 4, 2, 3], 50) == 3
+
+
+def test_release_needs_a_polled_request_and_finished_decodes_take_no_packets():
+    s = gf.Server(budget_bytes=1 << 20, dry_run=True)
+    s.submit_decode(5, 2, 100, 0.0)
+    with pytest.raises(gf.GFError):
+        s.release(5)                                  # not completed yet
+    for j in range(2):
+        s.push_packet(5, FAKE + j, FAKE + j, 0.0)
+    s.step(0.0)
+    s.step(0.1)
+    with pytest.raises(gf.GFError):
+        s.release(5)                                  # completed but not polled
+    (d,) = s.poll()
+    assert d["id"] == 5 and d["rank"] == 2
+    with pytest.raises(gf.GFError):
+        s.push_packet(5, FAKE, FAKE, 0.2)             # the generation is decoded
+    s.release(5)
+    assert s.stats()["arena_used"] == 0
+
+
+def test_calls_from_several_threads_are_serialised():
+    import threading
+
+    s = gf.Server(budget_bytes=1 << 30, dry_run=True)
+    per_thread, threads = 200, 8
+
+    def work(t):
+        for i in range(per_thread):
+            rid = t * per_thread + i
+            s.submit_decode(rid, 4, 64, 0.0)
+            for j in range(4):
+                s.push_packet(rid, FAKE + j, FAKE + j, 0.0)
+
+    ws = [threading.Thread(target=work, args=(t,)) for t in range(threads)]
+    for w in ws:
+        w.start()
+    for w in ws:
+        w.join()
+    st = s.stats()
+    assert st["submitted"] == per_thread * threads
+    assert st["packets_pushed"] == 4 * per_thread * threads
+    done, t = 0, 0.0
+    while done < per_thread * threads:
+        t += 1.0
+        s.step(t)
+        for d in s.poll():
+            assert d["rank"] == 4
+            s.release(d["id"])
+            done += 1
+        assert t < 1000
+    assert s.stats()["arena_used"] == 0
