@@ -140,3 +140,50 @@ def test_decode_accepts_exactly_the_contract():
         got = L.gf_decode(field, C or None, N, B or None, ld_b, S or None, ld_s, length, ws or None, ws_bytes, None,
                           None)
         assert got == want, (field, hex(C), N, hex(B), ld_b, hex(S), ld_s, length, hex(ws), ws_bytes)
+
+
+def _rows_bytes(p, rows, ld, width):
+    return [(p + r * ld, width) for r in range(rows)] if width > 0 else []
+
+
+def _any_overlap(xs, ys):
+    return any(overlap(a, b) for a in xs for b in ys)
+
+
+def test_accepted_recodings_never_overlap_their_outputs():
+    """Recoding's checks are stricter than the per-byte rule (they compare row
+    spans), so every accepted call must have outputs disjoint from each other
+    and from every input, all below 2^64; and the two usual layouts (separate
+    buffers; packets as rows [coefficients | payload]) must be accepted."""
+    L = gf.lib()
+    rng = np.random.default_rng(4)
+    base = 0x4000_0000
+    accepted = 0
+    for _ in range(20000):
+        Kout, M, N = int(rng.integers(0, 5)), int(rng.integers(1, 5)), int(rng.integers(1, 9))
+        length = int(rng.integers(0, 40))
+        R, Cin, Bin, Cout, Yout = (base + int(rng.integers(0, 600)) for _ in range(5))
+        if rng.integers(0, 20) == 0:
+            Yout = TOP - int(rng.integers(1, 300))
+        ld_cin, ld_b, ld_cout, ld_y = (int(rng.integers(0, 60)) for _ in range(4))
+        if rng.integers(0, 3) == 0:          # the packet-row layout, sometimes with a broken pitch
+            ld = N + length + int(rng.integers(0, 8))
+            Bin, Yout, ld_cin, ld_b, ld_cout, ld_y = Cin + N, Cout + N, ld, ld, ld, ld + int(rng.integers(0, 2))
+        got = L.gf_recode(8, R, Kout, M, N, Cin, ld_cin, Bin, ld_b, Cout, ld_cout, Yout, ld_y, length, None)
+        if got != gf.GF_EDEVICE or Kout == 0:
+            continue
+        accepted += 1
+        outs = [_rows_bytes(Cout, Kout, ld_cout, N), _rows_bytes(Yout, Kout, ld_y, length)]
+        ins = [_rows_bytes(R, Kout, M, M), _rows_bytes(Cin, M, ld_cin, N), _rows_bytes(Bin, M, ld_b, length)]
+        for o in outs:
+            assert all(a + n <= M64 for a, n in o)
+            for i in ins:
+                assert not _any_overlap(o, i), (Kout, M, N, length, R, Cin, Bin, Cout, Yout)
+        assert not _any_overlap(outs[0], outs[1])
+    assert accepted > 500
+    # the usual layouts are accepted
+    assert L.gf_recode(8, base, 3, 4, 6, base + 0x1000, 6, base + 0x2000, 100, base + 0x3000, 6,
+                       base + 0x4000, 100, 100, None) == gf.GF_EDEVICE
+    ld = 6 + 100 + 10
+    assert L.gf_recode(8, base, 3, 4, 6, base + 0x1000, ld, base + 0x1006, ld, base + 0x3000, ld,
+                       base + 0x3006, ld, 100, None) == gf.GF_EDEVICE
