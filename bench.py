@@ -118,7 +118,7 @@ def host_alg1_sweep() -> dict:
     return out
 
 
-def main():
+def make_parser() -> argparse.ArgumentParser:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -144,7 +144,11 @@ def main():
                          "and exit (for profiling one workload's kernels)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (to calibrate HBM counters) and exit")
-    args = ap.parse_args()
+    return ap
+
+
+def main():
+    args = make_parser().parse_args()
 
     if args.gpus != 1:
         print("bench.py measures one GPU only: the generations are independent, so several GPUs would each "

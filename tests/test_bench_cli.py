@@ -48,3 +48,36 @@ def test_source_hash_tracks_the_kernel_files(tmp_path, monkeypatch):
     (csrc / "gf_types.h").write_bytes(b"changed")
     assert bench.kernel_source_hash(2) != h2 and bench.kernel_source_hash(1) != h1
     assert all(len(k[0]) == 64 and k[1] in bench.KERNEL_SOURCES for k in bench.MEASURED_TRAFFIC)
+
+
+def _profile_bench_commands():
+    """The bench.py command lines in the code blocks of the committed profile summaries."""
+    import glob
+    import re
+    import shlex
+    cmds = []
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        text = open(path).read().replace("\\\n", " ")
+        blocks = re.findall(r"```\n(.*?)```", text, flags=re.S)
+        for line in "\n".join(blocks).splitlines():
+            line = line.strip()
+            m = re.match(r'B="python3 <repo>/bench\.py([^"]*)"', line)
+            if m:
+                cmds.append((os.path.basename(path), shlex.split(m.group(1))))
+            elif "bench.py" in line:
+                tail = line.split("bench.py", 1)[1]
+                cmds.append((os.path.basename(path), [t for t in shlex.split(tail) if t != "$B"]))
+    return cmds
+
+
+def test_profile_commands_run_committed_options():
+    """Every bench.py command that a profile summary gives parses with the
+    committed bench.py (its flags and workload names exist)."""
+    cmds = _profile_bench_commands()
+    assert len(cmds) >= 6
+    parser = bench.make_parser()
+    for where, args in cmds:
+        try:
+            parser.parse_args(args)
+        except SystemExit:
+            pytest.fail("%s: bench.py %s does not parse" % (where, " ".join(args)))
