@@ -436,7 +436,7 @@ def part_single_generation(gf, torch, args) -> dict:
     Sd = torch.from_numpy(g.S).to("cuda")
     Yd = torch.empty_like(Sd)
     Rd = torch.empty_like(Sd)
-    ws = torch.empty(gf.gf_decode_workspace(16), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(gf.gf_decode_workspace(8, 16), dtype=torch.uint8, device="cuda")
     rank = torch.zeros(1, dtype=torch.int32, device="cuda")
     # the C-ABI calls with their arguments marshalled once (the Python binding's own checks cost
     # several microseconds per call and are not the library's latency)
@@ -445,7 +445,7 @@ def part_single_generation(gf, torch, args) -> dict:
     cp, sp, yp, rp, wp, kp = Cd.data_ptr(), Sd.data_ptr(), Yd.data_ptr(), Rd.data_ptr(), ws.data_ptr(), rank.data_ptr()
     nws = ws.numel()
     enc = lambda: L.gf_encode(8, cp, 16, 16, sp, 1500, yp, 1500, 1500, st)   # noqa: E731
-    dec = lambda: L.gf_decode(8, cp, 16, yp, 1500, rp, 1500, 1500, wp, nws, kp, st)   # noqa: E731
+    dec = lambda: L.gf_decode(8, cp, yp, 1500, 16, rp, 1500, 1500, wp, nws, kp, st)   # noqa: E731
     enc_ms = time_ms(torch, enc, reps=500, warm=20)
     dec_ms = time_ms(torch, dec, reps=500, warm=20)
 

@@ -114,17 +114,24 @@ int gf_encode(int field, const uint8_t *C, int K, int N, const uint8_t *S, size_
 
 /* --------------------------------------------------------------- decode
  * Gauss-Jordan decoding of one generation: S = C^-1 B.
+ * The argument order follows the madd signature of Sec. IV-A (operands, then
+ * the destination with its pitch, then the byte length).
  * C: device, N x N coefficient rows of the N received coded packets.
  * B: device, N coded packets, row i at B + i*ld_b.
  * S: device output, row i at S + i*ld_s; written only if C is invertible.
- * ws: device workspace of at least gf_decode_workspace(N) bytes.
+ * ws: device workspace of at least gf_decode_workspace(field, N, 1) bytes
+ *     (it receives C^-1, and the rank when d_rank is NULL).
  * d_rank: device int (may be NULL); receives rank(C).  The call returns
  * GF_OK once enqueued; rank < N means singular and S untouched.
- * 1 <= N <= GF_MAX_N. */
-size_t gf_decode_workspace(int N);
-int gf_decode(int field, const uint8_t *C, int N, const uint8_t *B, size_t ld_b,
-              uint8_t *S, size_t ld_s, size_t len, void *ws, size_t ws_bytes,
-              int *d_rank, void *stream);
+ * 1 <= N <= GF_MAX_N (GF_ERANGE above). */
+int gf_decode(int field, const uint8_t *C, const uint8_t *B, size_t ld_b, int N, uint8_t *S, size_t ld_s,
+              size_t len, void *ws, size_t ws_bytes, int *d_rank, void *stream);
+
+/* Device workspace in bytes for decoding `count` systems of at most max_N
+ * source packets each: count * (max_N^2 rounded up to 256) plus 256-byte
+ * rounded room for count ranks.  0 for a bad field, max_N outside
+ * [1, GF_MAX_N] or count < 1. */
+size_t gf_decode_workspace(int field, int max_N, int count);
 
 /* Invert one N x N matrix: Cinv (device, N x N) := C^-1; *d_rank := rank(C).
  * Cinv is written only if C is invertible.  Uses no workspace. */

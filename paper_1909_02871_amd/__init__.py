@@ -76,8 +76,8 @@ _SIGS = {
     "gf_region_madd_batched": (C.c_int, [C.c_int, C.c_void_p, C.c_int, C.c_size_t, C.c_void_p]),
     "gf_encode": (C.c_int, [C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p,
                             C.c_size_t, C.c_size_t, C.c_void_p]),
-    "gf_decode_workspace": (C.c_size_t, [C.c_int]),
-    "gf_decode": (C.c_int, [C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t,
+    "gf_decode_workspace": (C.c_size_t, [C.c_int, C.c_int, C.c_int]),
+    "gf_decode": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p, C.c_size_t,
                             C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
     "gf_invert": (C.c_int, [C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "gf_plan_encode": (C.c_int, [C.c_int, C.POINTER(gf_gen), C.c_int, C.POINTER(gf_tuning),
@@ -225,8 +225,8 @@ def gf_encode(field: int, Cm, S, Y, length: Optional[int] = None, stream=None):
                            _stream(stream)), "gf_encode")
 
 
-def gf_decode_workspace(N: int) -> int:
-    return int(lib().gf_decode_workspace(N))
+def gf_decode_workspace(field: int, max_N: int, count: int = 1) -> int:
+    return int(lib().gf_decode_workspace(field, max_N, count))
 
 
 def gf_decode(field: int, Cm, B, S, ws=None, d_rank=None, length: Optional[int] = None, stream=None):
@@ -241,12 +241,12 @@ def gf_decode(field: int, Cm, B, S, ws=None, d_rank=None, length: Optional[int] 
     if nB < N or nS < N or L > lB or L > lS:
         raise ValueError("shape mismatch")
     if ws is None:
-        ws = torch.empty(gf_decode_workspace(N), dtype=torch.uint8, device=Cm.device)
+        ws = torch.empty(gf_decode_workspace(field, N), dtype=torch.uint8, device=Cm.device)
     _dev_u8(ws, "ws")
     if not ws.is_contiguous():
         raise ValueError("ws must be contiguous")
     rp = _rank_ptr(d_rank, 1)
-    _check(lib().gf_decode(field, Cm.data_ptr(), N, B.data_ptr(), ld_b, S.data_ptr(), ld_s, L, ws.data_ptr(),
+    _check(lib().gf_decode(field, Cm.data_ptr(), B.data_ptr(), ld_b, N, S.data_ptr(), ld_s, L, ws.data_ptr(),
                            ws.numel(), rp, _stream(stream)), "gf_decode")
     return ws
 

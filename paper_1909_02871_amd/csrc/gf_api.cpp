@@ -356,11 +356,14 @@ int gf_encode_each(int field, const gf_gen *gens, int count, const gf_tuning *tu
     return GF_OK;
 }
 
-size_t gf_decode_workspace(int N)
+// Bytes of one inverse of up to max_N x max_N, rounded to 256.
+static size_t inverse_bytes(int max_N) { return (((size_t)max_N * max_N + 255) / 256) * 256; }
+
+size_t gf_decode_workspace(int field, int max_N, int count)
 {
-    if (N < 1 || N > GF_MAX_N)
+    if (!valid_field(field) || max_N < 1 || max_N > GF_MAX_N || count < 1)
         return 0;
-    return (((size_t)N * N + 255) / 256) * 256 + 256;
+    return (size_t)count * inverse_bytes(max_N) + (((size_t)count * sizeof(int) + 255) / 256) * 256;
 }
 
 int gf_invert(int field, const uint8_t *C, int N, uint8_t *Cinv, int *d_rank, void *stream)
@@ -380,30 +383,30 @@ int gf_invert(int field, const uint8_t *C, int N, uint8_t *Cinv, int *d_rank, vo
                                  (hipStream_t)stream));
 }
 
-int gf_decode(int field, const uint8_t *C, int N, const uint8_t *B, size_t ld_b, uint8_t *S, size_t ld_s,
-              size_t len, void *ws, size_t ws_bytes, int *d_rank, void *stream)
+// Checks of a decode's matrix and rows (the workspace aside).
+static int check_decode_args(int field, const uint8_t *C, const uint8_t *B, size_t ld_b, int N, const uint8_t *S,
+                             size_t ld_s, size_t len, size_t *es, size_t *eb, size_t *ec)
 {
     if (!valid_field(field) || N < 1)
         return GF_EINVAL;
     if (N > GF_MAX_N)
         return GF_ERANGE;
-    if (!C || !ws || ws_bytes < gf_decode_workspace(N))
+    if (!C)
         return GF_EINVAL;
     if (len > 0 && (!B || !S || (N > 1 && (ld_b < len || ld_s < len))))
         return GF_EINVAL;
-    size_t es, eb, ec, ew;
-    if (!span_of(S, N, ld_s, len, &es) || !span_of(B, N, ld_b, len, &eb) || !span_of(C, N, N, N, &ec) ||
-        !span_of(ws, 1, 0, ws_bytes, &ew))
+    if (!span_of(S, N, ld_s, len, es) || !span_of(B, N, ld_b, len, eb) || !span_of(C, N, N, N, ec))
         return GF_EINVAL;
-    if (overlap(S, es, B, eb) || overlap(S, es, C, ec) || overlap(S, es, ws, ew) || overlap(ws, ew, C, ec) ||
-        overlap(ws, ew, B, eb))
+    if (overlap(S, *es, B, *eb) || overlap(S, *es, C, *ec))
         return GF_EINVAL;
-    DevState *d;
-    int rc = current_state(&d);
-    if (rc)
-        return rc;
-    uint8_t *cinv = static_cast<uint8_t *>(ws);
-    int *rank = d_rank ? d_rank : reinterpret_cast<int *>(cinv + ((((size_t)N * N + 255) / 256) * 256));
+    return GF_OK;
+}
+
+// S = C^-1 B with the inverse written to `cinv` (N^2 bytes) and the rank to
+// `rank` (both device memory the caller of this function provides).
+static int decode_impl(DevState *d, int field, const uint8_t *C, const uint8_t *B, size_t ld_b, int N, uint8_t *S,
+                       size_t ld_s, size_t len, uint8_t *cinv, int *rank, void *stream)
+{
     if (small_ok(N, N, len, row_align(B, N > 1 ? ld_b : 0, S, N > 1 ? ld_s : 0)))
         return dev_err(launch_small(C, N, N, B, ld_b, S, ld_s, len, field_ptab(d, field), field_inv(d, field), rank,
                                     true, (hipStream_t)stream));
@@ -414,6 +417,25 @@ int gf_decode(int field, const uint8_t *C, int N, const uint8_t *B, size_t ld_b,
     if (len == 0)
         return GF_OK;
     return encode_impl(field, cinv, N, N, B, ld_b, S, ld_s, len, nullptr, rank, N, stream);
+}
+
+int gf_decode(int field, const uint8_t *C, const uint8_t *B, size_t ld_b, int N, uint8_t *S, size_t ld_s,
+              size_t len, void *ws, size_t ws_bytes, int *d_rank, void *stream)
+{
+    size_t es, eb, ec, ew;
+    int rc = check_decode_args(field, C, B, ld_b, N, S, ld_s, len, &es, &eb, &ec);
+    if (rc)
+        return rc;
+    if (!ws || ws_bytes < gf_decode_workspace(field, N, 1) || !span_of(ws, 1, 0, ws_bytes, &ew))
+        return GF_EINVAL;
+    if (overlap(S, es, ws, ew) || overlap(ws, ew, C, ec) || overlap(ws, ew, B, eb))
+        return GF_EINVAL;
+    DevState *d;
+    if ((rc = current_state(&d)))
+        return rc;
+    uint8_t *cinv = static_cast<uint8_t *>(ws);
+    int *rank = d_rank ? d_rank : reinterpret_cast<int *>(cinv + inverse_bytes(N));
+    return decode_impl(d, field, C, B, ld_b, N, S, ld_s, len, cinv, rank, stream);
 }
 
 // ------------------------------------------------------------------ plans

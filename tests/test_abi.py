@@ -44,11 +44,16 @@ def test_strerror():
 
 def test_decode_workspace_sizes():
     L = gf.lib()
-    assert L.gf_decode_workspace(0) == 0
-    assert L.gf_decode_workspace(257) == 0
+    assert L.gf_decode_workspace(8, 0, 1) == 0
+    assert L.gf_decode_workspace(8, 257, 1) == 0
+    assert L.gf_decode_workspace(3, 16, 1) == 0      # bad field
+    assert L.gf_decode_workspace(8, 16, 0) == 0      # no systems
     for N in (1, 16, 100, 256):
-        ws = L.gf_decode_workspace(N)
+        ws = L.gf_decode_workspace(8, N, 1)
         assert ws >= N * N + 4 and ws % 256 == 0
+        for count in (2, 7, 2048):
+            many = L.gf_decode_workspace(4, N, count)
+            assert many >= count * (N * N + 4) and many % 256 == 0
 
 
 @pytest.mark.parametrize("field", [0, 3, 5, 16, -1])
@@ -57,7 +62,7 @@ def test_bad_field(field):
     assert L.gf_region_madd(field, P1, P2, 1, 10, None) == gf.GF_EINVAL
     assert L.gf_region_mul(field, P1, P2, 1, 10, None) == gf.GF_EINVAL
     assert L.gf_encode(field, P1, 2, 2, P2, 10, P3, 10, 10, None) == gf.GF_EINVAL
-    assert L.gf_decode(field, P1, 2, P2, 10, P3, 10, 10, P4, 1 << 16, None, None) == gf.GF_EINVAL
+    assert L.gf_decode(field, P1, P2, 10, 2, P3, 10, 10, P4, 1 << 16, None, None) == gf.GF_EINVAL
 
 
 @pytest.mark.parametrize("field,c", [(1, 2), (2, 4), (4, 16), (8, 256), (8, -1)])
@@ -90,12 +95,12 @@ def test_encode_argument_checks():
 
 def test_decode_argument_checks():
     L = gf.lib()
-    ws = L.gf_decode_workspace(4)
-    assert L.gf_decode(8, P1, 0, P2, 10, P3, 10, 10, P4, ws, None, None) == gf.GF_EINVAL
-    assert L.gf_decode(8, P1, 300, P2, 10, P3, 10, 10, P4, 1 << 20, None, None) == gf.GF_ERANGE
-    assert L.gf_decode(8, P1, 4, P2, 10, P3, 10, 10, P4, ws - 1, None, None) == gf.GF_EINVAL  # small ws
-    assert L.gf_decode(8, P1, 4, P2, 10, P2 + 3, 10, 10, P4, ws, None, None) == gf.GF_EINVAL  # S overlaps B
-    assert L.gf_decode(8, P1, 4, P2, 10, P3, 10, 10, P3 + 8, ws, None, None) == gf.GF_EINVAL  # ws overlaps S
+    ws = L.gf_decode_workspace(8, 4, 1)
+    assert L.gf_decode(8, P1, P2, 10, 0, P3, 10, 10, P4, ws, None, None) == gf.GF_EINVAL
+    assert L.gf_decode(8, P1, P2, 10, 300, P3, 10, 10, P4, 1 << 20, None, None) == gf.GF_ERANGE
+    assert L.gf_decode(8, P1, P2, 10, 4, P3, 10, 10, P4, ws - 1, None, None) == gf.GF_EINVAL  # small ws
+    assert L.gf_decode(8, P1, P2, 10, 4, P2 + 3, 10, 10, P4, ws, None, None) == gf.GF_EINVAL  # S overlaps B
+    assert L.gf_decode(8, P1, P2, 10, 4, P3, 10, 10, P3 + 8, ws, None, None) == gf.GF_EINVAL  # ws overlaps S
     assert L.gf_invert(8, P1, 4, P1 + 2, None, None) == gf.GF_EINVAL                          # Cinv overlaps C
     assert L.gf_invert(8, P1, 0, P2, None, None) == gf.GF_EINVAL
 
@@ -172,10 +177,10 @@ def test_spans_that_do_not_fit_the_address_space_are_rejected():
     assert L.gf_encode(8, P1, 3, 2, P2, 10, P3, huge, 10, None) == gf.GF_EINVAL  # 2 * 2^63 + 10 wraps
     assert L.gf_encode(8, P1, 2, 3, P2, huge, P3, 10, 10, None) == gf.GF_EINVAL
     assert L.gf_encode(8, (1 << 64) - 2, 2, 2, P2, 10, P3, 10, 10, None) == gf.GF_EINVAL   # C's 4 bytes run past 2^64
-    ws = L.gf_decode_workspace(4)
-    assert L.gf_decode(8, P1, 4, P2, huge, P3, 10, 10, P4, ws, None, None) == gf.GF_EINVAL
-    assert L.gf_decode(8, P1, 4, P2, 10, P3, huge, 10, P4, ws, None, None) == gf.GF_EINVAL
-    assert L.gf_decode(8, P1, 4, P2, 10, P3, 10, 10, top, ws, None, None) == gf.GF_EINVAL
+    ws = L.gf_decode_workspace(8, 4, 1)
+    assert L.gf_decode(8, P1, P2, huge, 4, P3, 10, 10, P4, ws, None, None) == gf.GF_EINVAL
+    assert L.gf_decode(8, P1, P2, 10, 4, P3, huge, 10, P4, ws, None, None) == gf.GF_EINVAL
+    assert L.gf_decode(8, P1, P2, 10, 4, P3, 10, 10, top, ws, None, None) == gf.GF_EINVAL
     assert L.gf_invert(8, top, 4, P2, None, None) == gf.GF_EINVAL
     assert L.gf_recode(8, P1, 3, 3, 5, P2, 5, P3, 100, P4, 5, P4 + 4096, huge, 100, None) == gf.GF_EINVAL
     h = C.c_void_p()
@@ -194,6 +199,6 @@ def test_spans_that_fit_still_pass_validation():
     assert L.gf_region_madd(8, P1, P2, 3, 100, None) == gf.GF_EDEVICE
     assert L.gf_encode(8, P1, 3, 2, P2, 10, P3, 1 << 20, 10, None) == gf.GF_EDEVICE
     assert L.gf_encode(8, P1, 1, 2, P2, 10, P3, 1 << 63, 10, None) == gf.GF_EDEVICE   # one row: pitch unused
-    ws = L.gf_decode_workspace(4)
-    assert L.gf_decode(8, P1, 4, P2, 10, P3, 10, 10, P4, ws, None, None) == gf.GF_EDEVICE
+    ws = L.gf_decode_workspace(8, 4, 1)
+    assert L.gf_decode(8, P1, P2, 10, 4, P3, 10, 10, P4, ws, None, None) == gf.GF_EDEVICE
     assert L.gf_invert(8, P1, 4, P2, None, None) == gf.GF_EDEVICE

@@ -112,7 +112,7 @@ def decode_contract(L, field, C, N, B, ld_b, S, ld_s, length, ws, ws_bytes):
         return gf.GF_EINVAL
     if N > 256:
         return gf.GF_ERANGE
-    if not C or not ws or ws_bytes < L.gf_decode_workspace(N):
+    if not C or not ws or ws_bytes < L.gf_decode_workspace(8, N, 1):
         return gf.GF_EINVAL
     if length > 0 and (not B or not S or (N > 1 and (ld_b < length or ld_s < length))):
         return gf.GF_EINVAL
@@ -133,12 +133,11 @@ def test_decode_accepts_exactly_the_contract():
         N = int(rng.integers(0, 6)) if rng.integers(0, 5) else int(rng.integers(250, 300))
         C, B, S, ws = (_ptr(rng, base) for _ in range(4))
         length, ld_b, ld_s = _size(rng), _size(rng), _size(rng)
-        need = int(L.gf_decode_workspace(max(1, min(N, 256))))
+        need = int(L.gf_decode_workspace(8, max(1, min(N, 256)), 1))
         ws_bytes = int(rng.choice([0, need - 1, need, need + 100])) if need else 0
         ws_bytes = max(ws_bytes, 0)
         want = decode_contract(L, field, C, N, B, ld_b, S, ld_s, length, ws, ws_bytes)
-        got = L.gf_decode(field, C or None, N, B or None, ld_b, S or None, ld_s, length, ws or None, ws_bytes, None,
-                          None)
+        got = L.gf_decode(field, C or None, B or None, ld_b, N, S or None, ld_s, length, ws or None, ws_bytes, None, None)
         assert got == want, (field, hex(C), N, hex(B), ld_b, hex(S), ld_s, length, hex(ws), ws_bytes)
 
 

@@ -564,7 +564,7 @@ def test_binding_rejects_host_and_short_buffers(gf):
     B = dev(synth.random_bytes(synth.key(2025), N * 64).reshape(N, 64))
     S = torch.empty((N, 64), dtype=torch.uint8, device="cuda")
     with pytest.raises(TypeError):   # workspace on the host
-        gf.gf_decode(8, Cm, B, S, ws=torch.empty(gf.gf_decode_workspace(N), dtype=torch.uint8))
+        gf.gf_decode(8, Cm, B, S, ws=torch.empty(gf.gf_decode_workspace(8, N), dtype=torch.uint8))
     plan = gf.gf_plan_decode(8, [(Cm, B, S), (Cm, B, torch.empty_like(S))])
     with pytest.raises(ValueError):  # one rank slot for two systems
         gf.gf_decode_batched(plan, d_rank=torch.zeros(1, dtype=torch.int32, device="cuda"))
