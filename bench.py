@@ -273,55 +273,42 @@ def main():
     hbm_roof_src = HBM_PEAK_GBS * b.source_bytes / hbm_bytes
     traffic = MEASURED_TRAFFIC.get((kernel_source_hash(tuning["form"]), tuning["form"])) if n == 8 and args.count == 10000 \
         else None
+    kernel = {1: "k_encode_waves", 2: "k_encode_mfma_dma", 3: "k_encode_planes"}[tuning["form"]]
+    # the HBM roofline: algorithmic bytes of one launch (sources, coefficients and coded rows, each
+    # moved once) over the kernel's measured time, against the 8 TB/s peak
+    achieved = hbm_bytes / (kern_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None if traffic is None else int(traffic),
+                "kernel": kernel, "kernel_ms": round(kern_ms, 4), "algorithmic_bytes": hbm_bytes,
+                "byte_madds_per_s": round(madds / (kern_ms * 1e-3), 1)}
+    # what actually bounds it: the kernel's own compute roofline
     if tuning["form"] == 2:
         # the bit-matrix product: 8K x 8N x L bit multiply-adds = 64 per byte-madd, 2 flops each,
-        # against the dense FP4 matrix-core peak
-        achieved = 128.0 * madds / (kern_ms * 1e-3) / 1e12
-        roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": MFMA_FP4_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / MFMA_FP4_TFLOPS, 4), "kernel": "k_encode_mfma_dma"}
+        # against the dense FP4 matrix-core peak; at 100% of it this batch would run at
+        # 78.9 T byte-madd/s / (byte-weighted mean K) of source
+        tflops = 128.0 * madds / (kern_ms * 1e-3) / 1e12
+        cap_src = MFMA_FP4_TFLOPS * 1e12 / 128.0 * b.source_bytes / madds / 1e9
+        roofline["compute"] = {"bound": "mfma", "achieved": round(tflops, 2), "peak": MFMA_FP4_TFLOPS,
+                               "unit": "TFLOP/s", "frac": round(tflops / MFMA_FP4_TFLOPS, 4),
+                               "source_gbs_at_peak": round(cap_src, 1),
+                               "hbm_frac_at_peak": round(cap_src / hbm_roof_src, 4)}
     else:
-        achieved = madds / (kern_ms * 1e-3) / 1e12
         peak = VALU_LANE_OPS / TABLE_OPS_PER_MADD / 1e12
-        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
-                    "unit": "T byte-madd/s", "frac": round(achieved / peak, 4), "kernel": "k_encode_waves"}
-    roofline.update({"traffic": None if traffic is None else int(traffic), "kernel_ms": round(kern_ms, 4),
-                     "algorithmic_bytes": hbm_bytes, "byte_madds_per_s": round(madds / (kern_ms * 1e-3), 1)})
+        got = madds / (kern_ms * 1e-3) / 1e12
+        roofline["compute"] = {"bound": "alu", "achieved": round(got, 3), "peak": round(peak, 3),
+                               "unit": "T byte-madd/s", "frac": round(got / peak, 4)}
+    copy_gbs = stream_copy_gbs(torch)
+    roofline["measured_copy_gbs"] = round(copy_gbs, 1)
+    roofline["frac_of_measured_copy"] = round(achieved / copy_gbs, 4)
+    log("roofline: %.1f GB/s of algorithmic HBM bytes = %.3f of 8 TB/s (device copy measures %.0f GB/s)"
+        % (achieved, achieved / HBM_PEAK_GBS, copy_gbs))
 
     # ------------------------------------------------------------ CPU oracle
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        Y_host = Y_dev.cpu().numpy()
-        order = np.argsort(synth.words(synth.key(synth.BASE_SEED + 2, 99), args.count))
-        budget = args.cpu_seconds * 1.2e8          # byte-madds the plain oracle does in about that time
-        picked, acc = [], 0
-        for i in order:
-            w = int(b.Ks[i] * b.Ns[i] * b.Ls[i])
-            if acc + w > budget and picked:
-                continue
-            picked.append(int(i))
-            acc += w
-            if acc >= budget:
-                break
-        ok = True
-        src = 0
-        t0 = time.perf_counter()
-        outs = []
-        for i in picked:
-            Cm, S = b.generation(i, S_host, C_host)
-            outs.append(oracle.encode(n, Cm, S))
-            src += int(b.Ns[i] * b.Ls[i])
-        dt = time.perf_counter() - t0
-        for i, want in zip(picked, outs):
-            K, L, ld = int(b.Ks[i]), int(b.Ls[i]), int(b.lds[i])
-            got = Y_host[b.y_off[i]:b.y_off[i] + K * ld].reshape(K, ld)[:, :L]
-            ok = ok and bool((got == want).all())
-        cpu = {"value": round(src / dt / 1e9, 6), "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": "%d of %d generations (%.3g byte-madds, %.1f MB of source), plain C oracle, one thread"
-                         % (len(picked), args.count, acc, src / 1e6),
-               "seconds": round(dt, 2), "gpu_output_bit_exact_on_sample": ok}
+        cpu = cpu_oracle_baseline(oracle, b, S_host, C_host, Y_dev.cpu().numpy(), args)
         cpu["single_generation"] = single_generation_oracle(gf, torch, oracle)
-        log("cpu oracle: %.4f GB/s over %d generations; GPU bit-exact on sample: %s" % (cpu["value"], len(picked), ok))
 
     del S_dev, C_dev, Y_dev, plan
     torch.cuda.empty_cache()
@@ -369,23 +356,27 @@ def time_ms(torch, fn, reps=5, warm=2) -> float:
 
 
 def device_bytes(torch, nbytes: int, seed: int, hi: int = 256):
-    """Seeded uniform bytes in [0, hi), generated on the device (large sweep inputs)."""
-    g = torch.Generator(device="cuda")
-    g.manual_seed(seed)
-    return torch.randint(0, hi, (nbytes,), dtype=torch.uint8, device="cuda", generator=g)
+    """Seeded uniform bytes in [0, hi) (hi a power of two), drawn on the device from the
+    seeded stream ``synth.random_bytes(seed, nbytes)`` (large inputs stay off the host)."""
+    t = synth.device_random_bytes(torch, seed, nbytes)
+    if hi < 256:
+        t &= hi - 1
+    return t
 
 
-def uniform_plan(gf, torch, n: int, K: int, N: int, L: int, count: int, seed: int, tune=None):
-    """count generations of K x N coefficients and N packets of L bytes, back to back on the device."""
-    ld = synth.padded(L)
-    S = device_bytes(torch, count * N * ld, seed)
-    Cm = device_bytes(torch, count * K * N, seed + 1, 1 << n)
-    Y = torch.empty(count * K * ld, dtype=torch.uint8, device="cuda")
+def uniform_plan(gf, torch, b, tune=None):
+    """The generations of a same-shape batch (``synth.uniform_batch`` / ``synth.sweep_batch``
+    layout) back to back on the device, inputs drawn there from the batch's seeded streams;
+    returns an autotuned plan, the source, coefficient and output blobs and the row pitch."""
+    S, Cm = b.device_blobs(torch)
+    Y = torch.empty(b.y_bytes, dtype=torch.uint8, device="cuda")
+    count = len(b.Ns)
+    K, N, L, ld = int(b.Ks[0]), int(b.Ns[0]), int(b.Ls[0]), int(b.lds[0])
     descs = (gf.gf_gen * count)()
     s0, c0, y0 = S.data_ptr(), Cm.data_ptr(), Y.data_ptr()
     for i in range(count):
-        descs[i] = gf.gf_gen(c0 + i * K * N, s0 + i * N * ld, y0 + i * K * ld, K, N, L, ld, ld)
-    plan = gf.gf_plan_encode_desc(n, descs, count, tune=tune if tune is not None else {"form": 0},
+        descs[i] = gf.gf_gen(c0 + int(b.c_off[i]), s0 + int(b.s_off[i]), y0 + int(b.y_off[i]), K, N, L, ld, ld)
+    plan = gf.gf_plan_encode_desc(b.n, descs, count, tune=tune if tune is not None else {"form": 0},
                                   keep=(S, Cm, Y))
     return plan, S, Cm, Y, ld
 
@@ -394,12 +385,11 @@ def relay_batch(gf, torch, count: int, keep_host: bool = False) -> dict:
     """The relay workload: the uneven GF(256) shapes, each relay holding M = N received packets and
     sending Kout = N recoded ones, packets stored as rows [N coefficients | payload] at a 16-byte
     pitch; returns the recode plan (autotuned), the device buffers and the layout."""
-    b = synth.uneven_batch(8, count, seed_off=7)
+    rl = synth.relay_batch(count)
+    b, lds, offs = rl.batch, rl.lds, rl.offs
     Ns, Ls = b.Ns.astype(np.int64), b.Ls.astype(np.int64)
-    lds = np.array([synth.padded(int(N + L)) for N, L in zip(Ns, Ls)], dtype=np.int64)
-    offs = np.concatenate([[0], np.cumsum(Ns * lds)])
-    In_host = synth.random_bytes(synth.key(b.seed, 14), int(offs[-1]))
-    R_host = b.coef_blob()
+    In_host = rl.in_blob()
+    R_host = rl.R_blob()
     In_dev = torch.from_numpy(In_host).to("cuda")
     Out_dev = torch.empty(int(offs[-1]), dtype=torch.uint8, device="cuda")
     R_dev = torch.from_numpy(R_host).to("cuda")
@@ -482,7 +472,7 @@ def part_sweep(gf, torch, args) -> dict:
     count = 4096
     for n in (1, 2, 4, 8):
         for L in (1500, 9000, 65536):
-            plan, S, Cm, Y, ld = uniform_plan(gf, torch, n, 64, 64, L, count, synth.BASE_SEED + 1 + 100 * n + L)
+            plan, S, Cm, Y, ld = uniform_plan(gf, torch, synth.sweep_batch(n, L, count))
             ms = time_ms(torch, lambda: gf.gf_plan_launch_graph(plan), reps=3, warm=1)
             src = count * 64 * L
             t = plan.tuning()
@@ -625,7 +615,8 @@ def part_k_sweep(gf, torch, args) -> dict:
     ks = []
     for K in (1, 2, 4, 8, 16, 32, 64, 128, 256):
         count = int(np.ceil(1e9 / (K * 9000)))
-        plan, S, Cm, Y, ld = uniform_plan(gf, torch, 8, K, K, 9000, count, synth.BASE_SEED + 5 + K)
+        plan, S, Cm, Y, ld = uniform_plan(gf, torch, synth.uniform_batch(8, K, K, 9000, count,
+                                                                     synth.key(synth.BASE_SEED + 5, K)))
         ms = time_ms(torch, lambda: gf.gf_plan_launch_graph(plan), reps=3, warm=1)
         src = count * K * 9000
         hbm = HBM_PEAK_GBS * (K * 9000) / (2 * K * 9000 + K * K)
@@ -655,6 +646,98 @@ def part_host_alg1(gf, torch, args) -> dict:
 EXTRA_PARTS = (("single_generation", part_single_generation), ("sweep", part_sweep),
                ("uneven_gf16", part_uneven_gf16), ("recode", part_recode), ("decode", part_decode),
                ("k_sweep", part_k_sweep), ("host_alg1", part_host_alg1))
+
+
+def stream_copy_gbs(torch, nbytes: int = 4 << 30, reps: int = 5) -> float:
+    """HBM bandwidth a plain device-to-device copy reaches (bytes read + written per second)."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = 0.0
+    for _ in range(reps):
+        e0, e1 = _events(torch)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        best = max(best, 2 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del src, dst
+    torch.cuda.empty_cache()
+    return best
+
+
+def host_cpu() -> dict:
+    """Host cores and CPU model, for the CPU baseline."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model,
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
+def cpu_oracle_baseline(oracle, b, S_host, C_host, Y_host, args) -> dict:
+    """The plain oracle on a bounded sample of the batch: all host cores (OpenMP over generations,
+    the thread count of OMP_NUM_THREADS or the usable cores, at most 16) and one core (the paper's
+    protocol); the GPU's bytes are checked against the oracle's on the sample."""
+    hc = host_cpu()
+    threads = int(os.environ.get("OMP_NUM_THREADS") or 0) or hc["affinity"] or hc["nproc"] or 1
+    threads = max(1, min(threads, 16))
+    order = np.argsort(synth.words(synth.key(synth.BASE_SEED + 2, 99), len(b.Ns)))
+
+    def pick(budget):
+        picked, acc = [], 0
+        for i in order:
+            w = int(b.Ks[i] * b.Ns[i] * b.Ls[i])
+            if acc + w > budget and picked:
+                continue
+            picked.append(int(i))
+            acc += w
+            if acc >= budget:
+                break
+        return picked, acc
+
+    def run(picked, nthreads):
+        Cs = [b.generation(i, S_host, C_host) for i in picked]
+        desc, c_parts, s_parts, co, so, yo = [], [], [], 0, 0, 0
+        for i, (Cm, S) in zip(picked, Cs):
+            K, N, L = int(b.Ks[i]), int(b.Ns[i]), int(b.Ls[i])
+            desc.append([co, so, yo, L, L, L, K, N])
+            c_parts.append(np.ascontiguousarray(Cm).reshape(-1))
+            s_parts.append(np.ascontiguousarray(S).reshape(-1))
+            co, so, yo = co + K * N, so + N * L, yo + K * L
+        Cb, Sb = np.concatenate(c_parts), np.concatenate(s_parts)
+        Yb = np.zeros(yo, np.uint8)
+        t0 = time.perf_counter()
+        used = oracle.encode_batch(b.n, np.array(desc, np.int64), Cb, Sb, Yb, nthreads)
+        dt = time.perf_counter() - t0
+        ok = True
+        for (i, d) in zip(picked, desc):
+            K, L, ld = int(b.Ks[i]), int(b.Ls[i]), int(b.lds[i])
+            got = Y_host[b.y_off[i]:b.y_off[i] + K * ld].reshape(K, ld)[:, :L]
+            ok = ok and bool((got == Yb[d[2]:d[2] + K * L].reshape(K, L)).all())
+        return used, dt, so, ok
+
+    # about 4e7 byte-madds per second per core for the plain oracle
+    picked, acc = pick(args.cpu_seconds * 4e7 * threads)
+    used, dt, src, ok = run(picked, threads)
+    p1, acc1 = pick(max(2.0, args.cpu_seconds / 3) * 4e7)
+    _, dt1, src1, ok1 = run(p1, 1)
+    out = {"value": round(src / dt / 1e9, 6), "unit": "GB/s", "cores": used, "kind": "oracle",
+           "sample": "%d of %d generations (%.3g byte-madds, %.1f MB of source), plain C oracle, OpenMP over "
+                     "generations on %d threads" % (len(picked), len(b.Ns), acc, src / 1e6, used),
+           "seconds": round(dt, 2), "gpu_output_bit_exact_on_sample": ok and ok1, **hc,
+           "one_core": {"value": round(src1 / dt1 / 1e9, 6), "unit": "GB/s", "cores": 1,
+                        "sample": "%d generations (%.3g byte-madds)" % (len(p1), acc1), "seconds": round(dt1, 2)}}
+    log("cpu oracle: %.4f GB/s on %d threads (%s), %.4f GB/s on one; GPU bit-exact on sample: %s"
+        % (out["value"], used, hc["cpu_model"], out["one_core"]["value"], ok and ok1))
+    return out
 
 
 def single_generation_oracle(gf, torch, oracle) -> dict:

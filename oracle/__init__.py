@@ -31,7 +31,7 @@ def build(force: bool = True) -> str:
             os.path.getmtime(_SRC), os.path.getmtime(_HDR)):
         return _LIB
     tmp = _LIB + ".tmp%d" % os.getpid()
-    subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Werror", "-shared", "-fPIC",
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Werror", "-fopenmp", "-shared", "-fPIC",
                            "-o", tmp, _SRC])
     os.replace(tmp, _LIB)
     return _LIB
@@ -61,6 +61,7 @@ def lib():
             "gfo_region_mul": (C.c_int, [C.c_int, _u8p, _u8p, C.c_int, C.c_size_t]),
             "gfo_encode": (C.c_int, [C.c_int, _u8p, C.c_int, C.c_int, _u8p, C.c_size_t,
                                      _u8p, C.c_size_t, C.c_size_t]),
+            "gfo_encode_batch": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int64), _u8p, _u8p, _u8p, C.c_int]),
             "gfo_matmul": (C.c_int, [C.c_int, _u8p, _u8p, _u8p, C.c_int, C.c_int, C.c_int]),
             "gfo_recode": (C.c_int, [C.c_int, _u8p, C.c_int, C.c_int, C.c_int, _u8p, _u8p, C.c_size_t,
                                      _u8p, _u8p, C.c_size_t, C.c_size_t]),
@@ -184,6 +185,24 @@ def encode(n: int, Cm: np.ndarray, S: np.ndarray) -> np.ndarray:
     rc = lib().gfo_encode(n, _p(Cm), K, N, _p(S), length, _p(Y), length, length)
     assert rc == 0
     return Y
+
+
+def encode_batch(n: int, desc: np.ndarray, C_blob: np.ndarray, S_blob: np.ndarray, Y_blob: np.ndarray,
+                 threads: int = 1) -> int:
+    """Eq. (1) for every generation of a batch, written into Y_blob in place.
+
+    desc: int64[count, 8] rows {C offset, S offset, Y offset, ld_s, ld_y, len, K, N}
+    (byte offsets into the blobs).  Generations are shared among ``threads``
+    OpenMP threads.  Returns the number of threads that ran."""
+    desc = np.ascontiguousarray(desc, dtype=np.int64)
+    assert desc.ndim == 2 and desc.shape[1] == 8
+    for b in (C_blob, S_blob, Y_blob):
+        assert b.dtype == np.uint8 and b.flags.c_contiguous
+    used = lib().gfo_encode_batch(n, desc.shape[0], desc.ctypes.data_as(C.POINTER(C.c_int64)), _p(C_blob),
+                                  _p(S_blob), _p(Y_blob), threads)
+    if used < 0:
+        raise ValueError("gfo_encode_batch: bad argument")
+    return used
 
 
 def matmul(n: int, P: np.ndarray, Q: np.ndarray) -> np.ndarray:

@@ -36,6 +36,10 @@
 
 #include "gforacle.h"
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 /* ------------------------------------------------------------------ field */
 
 int gfo_valid_field(int n) { return n == 1 || n == 2 || n == 4 || n == 8; }
@@ -214,6 +218,31 @@ int gfo_encode(int n, const uint8_t *C, int K, int N,
             Y[(size_t)k * ld_y + j] = (uint8_t)acc;
         }
     return 0;
+}
+
+/* Eq. (1) for many generations at once: generation g is gfo_encode of its
+ * own coefficient matrix and sources, found through desc[8 g .. 8 g + 7] =
+ * {C offset, S offset, Y offset, ld_s, ld_y, len, K, N} (byte offsets into
+ * the C, S and Y blobs).  Generations are independent, so they are dealt to
+ * `threads` OpenMP threads one at a time; each is the plain loop above.
+ * Returns the number of threads that ran, or -1 on a bad argument. */
+int gfo_encode_batch(int n, int count, const int64_t *desc, const uint8_t *C, const uint8_t *S, uint8_t *Y,
+                     int threads)
+{
+    if (!gfo_valid_field(n) || count < 0 || threads < 1)
+        return -1;
+    int used = 1, bad = 0;
+#pragma omp parallel for num_threads(threads) schedule(dynamic, 1) reduction(| : bad)
+    for (int g = 0; g < count; g++) {
+        const int64_t *d = desc + 8 * (size_t)g;
+#ifdef _OPENMP
+        if (g == 0)
+            used = omp_get_num_threads();
+#endif
+        bad |= gfo_encode(n, C + d[0], (int)d[6], (int)d[7], S + d[1], (size_t)d[3], Y + d[2], (size_t)d[4],
+                          (size_t)d[5]) != 0;
+    }
+    return bad ? -1 : used;
 }
 
 /* Matrix product over the field: R (a x c) = P (a x b) * Q (b x c). */

@@ -31,6 +31,8 @@ int gfo_region_madd(int n, uint8_t *y, const uint8_t *x, int c, size_t len);
 int gfo_region_mul(int n, uint8_t *y, const uint8_t *x, int c, size_t len);
 int gfo_encode(int n, const uint8_t *C, int K, int N,
                const uint8_t *S, size_t ld_s, uint8_t *Y, size_t ld_y, size_t len);
+int gfo_encode_batch(int n, int count, const int64_t *desc, const uint8_t *C, const uint8_t *S, uint8_t *Y,
+                     int threads);
 int gfo_matmul(int n, const uint8_t *P, const uint8_t *Q, uint8_t *R, int a, int b, int c);
 int gfo_recode(int n, const uint8_t *R, int Kout, int M, int N, const uint8_t *Cin,
                const uint8_t *Bin, size_t ld_b, uint8_t *Cout, uint8_t *Yout, size_t ld_y, size_t len);

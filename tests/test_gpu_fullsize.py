@@ -1,15 +1,22 @@
 """The workloads at their full sizes, in the launch configuration bench.py
-times (autotuned plan, one graph-replayed persistent launch), checked against
-the oracle on sampled outputs (each sampled byte is Eq. (1) over the
-generation's whole column) or, for decoding, by the output equalling the
-sources everywhere.
+times (autotuned plan, one graph-replayed persistent launch), checked on every
+output byte: each generation's output rows are hashed and compared with the
+digest of the oracle's Eq. (1) (Sec. II) stored under tests/golden/ by
+tests/golden/make_digests.py (which calls only the oracle and the seeded input
+generators).  Row padding must keep the fill the output was given, and every
+kernel form the autotuner can pick must give the same bytes.
 
 Workloads: the uneven batch (10,000 generations, N ~ U{8..256}, packets
 log-uniform in [64, 9000] B, K = N) over GF(16) and GF(256); the plain sweep
-(4096 generations, N = K = 64, 1500 / 9000 / 65536 B) over all four fields;
-the batched decode (2,048 systems, N in {32, 64, 128}, 1500 B) over GF(256);
-recoding at 10,000 relays; the 4000-request serving stream.
+(4096 generations, N = K = 64) over all four fields at 1500 and 9000 B (every
+generation) and at 64 KiB (one generation from each block of 64); recoding at
+10,000 relays; the batched decode (2,048 systems, N in {32, 64, 128}, 1500 B)
+with the coefficient draws the oracle finds invertible (and the oracle's rank
+for every draw it rejects); the 4000-request serving stream.
 """
+import os
+import sys
+
 import numpy as np
 import pytest
 
@@ -18,7 +25,12 @@ import oracle
 import synth
 from gpu_util import torch_cuda
 
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+import digests  # noqa: E402
+
 pytestmark = pytest.mark.gpu
+
+FIELD_NAME = {1: "gf2", 2: "gf4", 4: "gf16", 8: "gf256"}
 
 
 @pytest.fixture(scope="module")
@@ -29,6 +41,13 @@ def gf():
     return g
 
 
+def _want(name):
+    """The stored digests of a workload (skipped while its file has not been written)."""
+    if not os.path.exists(digests.path(name)):
+        pytest.skip("digest file %s not written yet (tests/golden/make_digests.py %s)" % (name, name))
+    return digests.read(name)
+
+
 def _sample_cols(rng, L, extra=3):
     return sorted({0, L - 1, *(int(x) for x in rng.integers(0, L, extra))})
 
@@ -37,112 +56,145 @@ def _sample_rows(rng, K):
     return sorted({0, K - 1, int(rng.integers(0, K))})
 
 
-@pytest.mark.parametrize("n", [8, 4])
-def test_uneven_batch_full_size(gf, n):
-    torch = torch_cuda()
-    count = 10000
-    b = synth.uneven_batch(n, count)
-    S_host, C_host = b.source_blob(), b.coef_blob()
-    S_dev = torch.from_numpy(S_host).to("cuda")
-    C_dev = torch.from_numpy(C_host).to("cuda")
-    Y_dev = torch.full((b.y_bytes,), 0xA5, dtype=torch.uint8, device="cuda")
+def _check_batch_output(b, Y_host, want, fill, indices=None, useful=None):
+    """Digest of every generation's rows against the stored ones; padding bytes keep `fill`.
+
+    Returns the indices of generations that differ."""
+    bad = []
+    for i in (range(len(b.Ns)) if indices is None else indices):
+        K, L, ld = int(b.Ks[i]), int(b.Ls[i]), int(b.lds[i])
+        rows = Y_host[b.y_off[i]:b.y_off[i] + K * ld].reshape(K, ld)
+        if digests.digest_rows(rows[:, :L]) != want[i] or (ld > L and not (rows[:, L:] == fill).all()):
+            bad.append(i)
+    return bad
+
+
+def _encode_batch_plan(gf, torch, b, S_dev, C_dev, Y_dev, tune):
+    count = len(b.Ns)
     descs = (gf.gf_gen * count)()
     s0, c0, y0 = S_dev.data_ptr(), C_dev.data_ptr(), Y_dev.data_ptr()
     for i in range(count):
         descs[i] = gf.gf_gen(c0 + int(b.c_off[i]), s0 + int(b.s_off[i]), y0 + int(b.y_off[i]), int(b.Ks[i]),
                              int(b.Ns[i]), int(b.Ls[i]), int(b.lds[i]), int(b.lds[i]))
-    plan = gf.gf_plan_encode_desc(n, descs, count, tune={"form": 0}, keep=(S_dev, C_dev, Y_dev))
-    Y_dev.fill_(0xA5)
-    torch.cuda.synchronize()
-    for _ in range(2):
-        gf.gf_plan_launch_graph(plan)
-    torch.cuda.synchronize()
-    Y_host = Y_dev.cpu().numpy()
-    rng = np.random.default_rng(synth.key(60, n))
-    for g in sorted({0, count - 1, *(int(x) for x in rng.integers(0, count, 46))}):
-        Cm, S = b.generation(g, S_host, C_host)
-        K, L, ld = int(b.Ks[g]), int(b.Ls[g]), int(b.lds[g])
-        rows, cols = _sample_rows(rng, K), _sample_cols(rng, L)
-        want = oracle.encode(n, Cm[rows], np.ascontiguousarray(S[:, cols]))
-        Y = Y_host[b.y_off[g]:b.y_off[g] + K * ld].reshape(K, ld)
-        assert (Y[np.ix_(rows, cols)] == want).all(), (g, rows, cols)
-    plan.destroy()
+    return gf.gf_plan_encode_desc(b.n, descs, count, tune=tune, keep=(S_dev, C_dev, Y_dev))
+
+
+@pytest.mark.parametrize("n", [8, 4])
+def test_uneven_batch_full_size(gf, n):
+    """Every byte of the 10,000 generations: the autotuned plan twice (fills 0xA5
+    and 0x5A, graph replays), then each kernel form on its own."""
+    torch = torch_cuda()
+    want = _want("uneven_%s" % FIELD_NAME[n])
+    b = synth.uneven_batch(n, 10000)
+    S_dev, C_dev = b.device_blobs(torch)
+    Y_dev = torch.empty(b.y_bytes, dtype=torch.uint8, device="cuda")
+    assert len(want) == len(b.Ns)
+    forms = [0, 1, 2] + ([3] if n <= 4 else [])
+    for form in forms:
+        plan = _encode_batch_plan(gf, torch, b, S_dev, C_dev, Y_dev, {"form": form})
+        for fill in ((0xA5, 0x5A) if form == 0 else (0xA5,)):
+            print("uneven", n, "form", form, plan.tuning()["form"], "fill", hex(fill), flush=True)
+            Y_dev.fill_(fill)
+            torch.cuda.synchronize()
+            for _ in range(2):
+                gf.gf_plan_launch_graph(plan)
+            torch.cuda.synchronize()
+            bad = _check_batch_output(b, Y_dev.cpu().numpy(), want, fill)
+            assert not bad, ("form", form, "fill", fill, len(bad), bad[:10])
+        plan.destroy()
 
 
 @pytest.mark.parametrize("n", [1, 2, 4, 8])
-@pytest.mark.parametrize("L", [1500, 9000, 65536])
+@pytest.mark.parametrize("L", [1500, 9000])
 def test_sweep_full_size(gf, n, L):
+    """Every generation of the 4096-generation sweep point."""
     torch = torch_cuda()
-    count, N = 4096, 64
-    plan, S, Cm, Y, ld = bench.uniform_plan(gf, torch, n, N, N, L, count, synth.BASE_SEED + 1 + 100 * n + L)
+    want = _want("sweep_%s_%d" % (FIELD_NAME[n], L))
+    b = synth.sweep_batch(n, L)
+    plan, S, Cm, Y, ld = bench.uniform_plan(gf, torch, b)
+    print("sweep", n, L, "form", plan.tuning()["form"], flush=True)
     Y.fill_(0xA5)
     torch.cuda.synchronize()
     gf.gf_plan_launch_graph(plan)
     torch.cuda.synchronize()
-    S3 = S.view(count, N, ld)
-    C3 = Cm.view(count, N, N)
-    Y3 = Y.view(count, N, ld)
-    rng = np.random.default_rng(synth.key(61, n, L))
-    for g in sorted({0, count - 1, *(int(x) for x in rng.integers(0, count, 14))}):
-        rows, cols = _sample_rows(rng, N), _sample_cols(rng, L)
-        cidx = torch.tensor(cols, device="cuda")
-        Sg = S3[g].index_select(1, cidx).cpu().numpy()
-        want = oracle.encode(n, C3[g].cpu().numpy()[rows], Sg)
-        got = Y3[g].index_select(1, cidx).cpu().numpy()[rows]
-        assert (got == want).all(), (g, rows, cols)
+    bad = _check_batch_output(b, Y.cpu().numpy(), want, 0xA5)
+    assert not bad, (len(bad), bad[:10])
     plan.destroy()
     del plan, S, Cm, Y
     torch.cuda.empty_cache()
 
 
-def test_decode_batch_full_size(gf):
-    """2,048 systems; singular draws are redrawn (as the bench does, by the
-    device's own rank); every decoded byte equals its source."""
+@pytest.mark.parametrize("n", [1, 2, 4, 8])
+def test_sweep_64k_full_size(gf, n):
+    """The 64 KiB sweep point (17 GB of sources): every byte of one generation
+    from each block of 64, the rest of the launch as in the bench."""
     torch = torch_cuda()
+    want = _want("sweep_%s_65536_sample" % FIELD_NAME[n])
+    b = synth.sweep_batch(n, 65536)
+    plan, S, Cm, Y, ld = bench.uniform_plan(gf, torch, b)
+    print("sweep 64 KiB", n, "form", plan.tuning()["form"], flush=True)
+    Y.fill_(0xA5)
+    torch.cuda.synchronize()
+    gf.gf_plan_launch_graph(plan)
+    torch.cuda.synchronize()
+    K, L = 64, 65536
+    Y3 = Y.view(len(b.Ns), K, ld)
+    bad = [i for i in sorted(want) if digests.digest_rows(Y3[i][:, :L].cpu().numpy()) != want[i]]
+    assert len(want) == 64 and not bad, bad[:10]
+    plan.destroy()
+    del plan, S, Cm, Y, Y3
+    torch.cuda.empty_cache()
+
+
+def _decode_draws():
+    """{system: (attempt the oracle accepts, [(rejected attempt, oracle rank), ...])}."""
+    out = {}
+    with open(digests.path("decode_2048")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            parts = line.split()
+            rej = [tuple(int(v) for v in p.split(":")) for p in parts[2:]]
+            out[int(parts[0])] = (int(parts[1]), rej)
+    return out
+
+
+def test_decode_batch_full_size(gf):
+    """2,048 systems built from the draws the oracle finds invertible: the device
+    reports rank N for every one and every decoded byte equals its source; the
+    draws the oracle rejected, decoded as a batch of their own, get the oracle's
+    rank from the device and leave their outputs untouched."""
+    torch = torch_cuda()
+    _want("decode_2048")
+    draws = _decode_draws()
     db = synth.decode_batch(2048, 1500)
     count = len(db.Ns)
+    assert len(draws) == count
+    C_host = np.zeros(db.c_bytes, dtype=np.uint8)
+    for i in range(count):
+        Nn = int(db.Ns[i])
+        C_host[db.c_off[i]:db.c_off[i] + Nn * Nn] = synth.decode_candidate(i, draws[i][0], Nn).reshape(-1)
     S_dev = torch.from_numpy(db.source_blob()).to("cuda")
     B_dev = torch.empty_like(S_dev)
-    R_dev = torch.empty_like(S_dev)
-    attempt = np.zeros(count, dtype=np.int64)
-    C_host = np.zeros(db.c_bytes, dtype=np.uint8)
-
-    def fill(i):
-        Nn = int(db.Ns[i])
-        C_host[db.c_off[i]:db.c_off[i] + Nn * Nn] = synth.decode_candidate(i, int(attempt[i]), Nn).reshape(-1)
-
+    R_dev = torch.full_like(S_dev, 0x3C)
+    C_dev = torch.from_numpy(C_host).to("cuda")
+    sysd = (gf.gf_sys * count)()
+    encd = (gf.gf_gen * count)()
     for i in range(count):
-        fill(i)
-    rank = torch.zeros(count, dtype=torch.int32, device="cuda")
-    for _ in range(8):
-        C_dev = torch.from_numpy(C_host).to("cuda")
-        sysd = (gf.gf_sys * count)()
-        encd = (gf.gf_gen * count)()
-        for i in range(count):
-            Nn, L, ld = int(db.Ns[i]), int(db.Ls[i]), int(db.lds[i])
-            cp = C_dev.data_ptr() + int(db.c_off[i])
-            sp, bp, rp = (t.data_ptr() + int(db.s_off[i]) for t in (S_dev, B_dev, R_dev))
-            encd[i] = gf.gf_gen(cp, sp, bp, Nn, Nn, L, ld, ld)
-            sysd[i] = gf.gf_sys(cp, bp, rp, Nn, 0, L, ld, ld)
-        eplan = gf.gf_plan_encode_desc(8, encd, count, keep=(C_dev, S_dev, B_dev))
-        gf.gf_encode_batched(eplan)
-        dplan = gf.gf_plan_decode_desc(8, sysd, count, keep=(C_dev, B_dev, R_dev))
-        R_dev.fill_(0x3C)
-        torch.cuda.synchronize()
-        gf.gf_plan_launch_graph(dplan, rank)
-        torch.cuda.synchronize()
-        ranks = rank.cpu().numpy()
-        bad = np.nonzero(ranks != db.Ns)[0]
-        if len(bad) == 0:
-            break
-        for i in bad:
-            attempt[i] += 1
-            fill(int(i))
-        eplan.destroy()
-        dplan.destroy()
-    else:
-        pytest.fail("singular systems left after 8 redraws")
-    # the coded rows are the oracle's encode of the sources (sampled), and the decode returns the sources
+        Nn, L, ld = int(db.Ns[i]), int(db.Ls[i]), int(db.lds[i])
+        cp = C_dev.data_ptr() + int(db.c_off[i])
+        sp, bp, rp = (t.data_ptr() + int(db.s_off[i]) for t in (S_dev, B_dev, R_dev))
+        encd[i] = gf.gf_gen(cp, sp, bp, Nn, Nn, L, ld, ld)
+        sysd[i] = gf.gf_sys(cp, bp, rp, Nn, 0, L, ld, ld)
+    eplan = gf.gf_plan_encode_desc(8, encd, count, tune={"form": 1}, keep=(C_dev, S_dev, B_dev))
+    gf.gf_encode_batched(eplan)
+    dplan = gf.gf_plan_decode_desc(8, sysd, count, keep=(C_dev, B_dev, R_dev))
+    rank = torch.full((count,), -1, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    gf.gf_plan_launch_graph(dplan, rank)
+    torch.cuda.synchronize()
+    assert (rank.cpu().numpy() == db.Ns).all()
+    # the coded rows are the oracle's encode of the sources (sampled systems)
     rng = np.random.default_rng(synth.key(62))
     S_host = S_dev.cpu().numpy()
     B_host = B_dev.cpu().numpy()
@@ -157,35 +209,51 @@ def test_decode_batch_full_size(gf):
         Nn, L, ld, so = int(db.Ns[i]), int(db.Ls[i]), int(db.lds[i]), int(db.s_off[i])
         valid[so:so + Nn * ld].view(Nn, ld)[:, :L] = True
     assert torch.equal(R_dev[valid], S_dev[valid])
+    assert (R_dev[~valid] == 0x3C).all()
     eplan.destroy()
     dplan.destroy()
+    # the rejected draws: the device's rank is the oracle's, the outputs stay as they were
+    rej = [(i, a, r) for i, (_, lst) in draws.items() for a, r in lst]
+    assert rej, "the workload has singular draws"
+    Cs = [synth.decode_candidate(i, a, int(db.Ns[i])) for i, a, _ in rej]
+    Cr = torch.from_numpy(np.concatenate([c.reshape(-1) for c in Cs])).to("cuda")
+    offs = np.concatenate([[0], np.cumsum([c.size for c in Cs])])
+    out = torch.full((len(rej), 128 * 16), 0x77, dtype=torch.uint8, device="cuda")
+    sysr = (gf.gf_sys * len(rej))()
+    for j, (i, a, r) in enumerate(rej):
+        Nn = int(db.Ns[i])
+        bp = S_dev.data_ptr() + int(db.s_off[i])
+        sysr[j] = gf.gf_sys(Cr.data_ptr() + int(offs[j]), bp, out[j].data_ptr(), Nn, 0, 16, int(db.lds[i]), 16)
+    rplan = gf.gf_plan_decode_desc(8, sysr, len(rej), keep=(Cr, S_dev, out))
+    rk = torch.full((len(rej),), -1, dtype=torch.int32, device="cuda")
+    gf.gf_decode_batched(rplan, rk)
+    torch.cuda.synchronize()
+    assert rk.cpu().numpy().tolist() == [r for _, _, r in rej]
+    assert (out == 0x77).all()
+    rplan.destroy()
 
 
 def test_recode_relay_full_size(gf):
     """10,000 relays (the uneven GF(256) shapes, M = N received packets stored as rows
-    [coefficients | payload], Kout = N): sampled header and payload bytes of the
-    recoded packets against the oracle's recode; the row padding stays untouched."""
+    [coefficients | payload], Kout = N): every relay's output rows, header and
+    payload, against the oracle's recode; the row padding stays untouched."""
     torch = torch_cuda()
-    rb = bench.relay_batch(gf, torch, 10000, keep_host=True)
+    want = _want("relay_gf256")
+    rb = bench.relay_batch(gf, torch, 10000)
     b, Ns, Ls, lds, offs = rb["batch"], rb["Ns"], rb["Ls"], rb["lds"], rb["offs"]
+    assert len(want) == 10000
     rb["Out"].fill_(0xA5)
     torch.cuda.synchronize()
     gf.gf_plan_launch_graph(rb["plan"])
     torch.cuda.synchronize()
     Out = rb["Out"].cpu().numpy()
-    In, Rh = rb["In_host"], rb["R_host"]
-    rng = np.random.default_rng(synth.key(63))
-    for g in sorted({0, 9999, *(int(x) for x in rng.integers(0, 10000, 30))}):
+    bad = []
+    for g in range(10000):
         N, L, ld, off = int(Ns[g]), int(Ls[g]), int(lds[g]), int(offs[g])
-        rows_in = In[off:off + N * ld].reshape(N, ld)
-        R = Rh[b.c_off[g]:b.c_off[g] + N * N].reshape(N, N)
-        rows, hcols, pcols = _sample_rows(rng, N), _sample_cols(rng, N), _sample_cols(rng, L)
-        wantC, wantY = oracle.recode(8, R[rows], np.ascontiguousarray(rows_in[:, hcols]),
-                                     np.ascontiguousarray(rows_in[:, [N + c for c in pcols]]))
-        got = Out[off:off + N * ld].reshape(N, ld)[rows]
-        assert (got[:, hcols] == wantC).all(), g
-        assert (got[:, [N + c for c in pcols]] == wantY).all(), g
-        assert (got[:, N + L:] == 0xA5).all(), g
+        rows = Out[off:off + N * ld].reshape(N, ld)
+        if digests.digest_rows(rows[:, :N + L]) != want[g] or not (rows[:, N + L:] == 0xA5).all():
+            bad.append(g)
+    assert not bad, (len(bad), bad[:10])
     rb["plan"].destroy()
 
 

@@ -293,3 +293,23 @@ def test_recode_header_consistent_with_payload(n):
     Cin = synth.uniform_field(62, M * N, n).reshape(M, N)
     Cout, _ = oracle.recode(n, R, Cin, np.zeros((M, 0), np.uint8))
     assert (Cout == oracle.encode(n, R, Cin)).all()
+
+
+def test_encode_batch_is_the_per_generation_encode():
+    """The OpenMP batch entry computes each generation exactly as the single
+    encode does (generations are independent), with any thread count, and
+    leaves the row padding alone."""
+    b = synth.uniform_batch(8, 5, 3, 37, 4, synth.key(4242))
+    b2 = synth._layout(4, [3, 9, 1, 4], [2, 5, 3, 1], [17, 40, 1, 64], synth.key(4243))
+    for bt in (b, b2):
+        S_blob, C_blob = bt.source_blob(), bt.coef_blob()
+        desc = np.stack([bt.c_off, bt.s_off, bt.y_off, bt.lds, bt.lds, bt.Ls, bt.Ks, bt.Ns], axis=1)
+        for threads in (1, 3):
+            Y = np.full(bt.y_bytes, 0xA5, np.uint8)
+            assert oracle.encode_batch(bt.n, desc, C_blob, S_blob, Y, threads) >= 1
+            for i in range(len(bt.Ns)):
+                Cm, S = bt.generation(i, S_blob, C_blob)
+                K, L, ld = int(bt.Ks[i]), int(bt.Ls[i]), int(bt.lds[i])
+                got = Y[bt.y_off[i]:bt.y_off[i] + K * ld].reshape(K, ld)
+                assert (got[:, :L] == oracle.encode(bt.n, Cm, S)).all()
+                assert (got[:, L:] == 0xA5).all()

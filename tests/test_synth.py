@@ -49,3 +49,27 @@ def test_serving_stream():
     assert abs(t[-1] - 2.0) < 0.3
     frac = np.mean([r.kind == "decode" for r in reqs])
     assert abs(frac - 0.3) < 0.05
+
+
+def test_stream_slices_equal_the_whole_stream():
+    whole = synth.random_bytes(77, 1000)
+    for off, n in [(0, 1000), (1, 7), (8, 16), (13, 500), (999, 1), (500, 0)]:
+        assert (synth.random_bytes_at(77, off, n) == whole[off:off + n]).all(), (off, n)
+    b = synth.sweep_batch(4, 1500, count=6)
+    S_blob, C_blob = b.source_blob(), b.coef_blob()
+    for i in (0, 3, 5):
+        C, S = b.generation(i, S_blob, C_blob)
+        assert (b.source_rows(i) == S).all() and (b.coef_rows(i) == C).all()
+
+
+def test_device_generator_equals_host_stream():
+    """The torch generator (int64 arithmetic, run here on the CPU) yields the host stream's bytes."""
+    import torch
+    for seed in (0, 5, synth.key(1, 2, 3), (1 << 64) - 1):
+        for n in (0, 1, 7, 8, 9, 1001):
+            want = synth.random_bytes(seed, n)
+            got = synth.device_random_bytes(torch, seed, n, device="cpu", chunk_words=3).numpy()
+            assert (got == want).all(), (seed, n)
+    b = synth.uniform_batch(2, 5, 7, 100, 3, synth.key(9))
+    S, Cb = b.device_blobs(torch, device="cpu")
+    assert (S.numpy() == b.source_blob()).all() and (Cb.numpy() == b.coef_blob()).all()
