@@ -133,6 +133,19 @@ int gf_decode(int field, const uint8_t *C, const uint8_t *B, size_t ld_b, int N,
  * [1, GF_MAX_N] or count < 1. */
 size_t gf_decode_workspace(int field, int max_N, int count);
 
+/* gf_decode without the workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  It allocates nothing: C^-1, and the rank when
+ * d_rank is NULL, go to a fixed scratch array in the library's device memory
+ * of GF_MAX_N^2 + 256 bytes (64.25 KiB), one per device, held until the
+ * process ends.  gf_init() must have run with this device current (else
+ * GF_ENOTINIT).  Every call on a device shares its scratch array, so calls
+ * that overlap on one device (other streams, other threads) race: serialise
+ * them, e.g. on one stream.  Arguments, errors and results as gf_decode;
+ * N > GF_MAX_N is GF_ERANGE. */
+int gf_decode_noalloc(int field, const uint8_t *C, const uint8_t *B, size_t ld_b, int N, uint8_t *S,
+                      size_t ld_s, size_t len, int *d_rank, void *stream);
+
 /* Invert one N x N matrix: Cinv (device, N x N) := C^-1; *d_rank := rank(C).
  * Cinv is written only if C is invertible.  Uses no workspace. */
 int gf_invert(int field, const uint8_t *C, int N, uint8_t *Cinv, int *d_rank, void *stream);

@@ -79,6 +79,8 @@ _SIGS = {
     "gf_decode_workspace": (C.c_size_t, [C.c_int, C.c_int, C.c_int]),
     "gf_decode": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p, C.c_size_t,
                             C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
+    "gf_decode_noalloc": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p, C.c_size_t,
+                                    C.c_size_t, C.c_void_p, C.c_void_p]),
     "gf_invert": (C.c_int, [C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "gf_plan_encode": (C.c_int, [C.c_int, C.POINTER(gf_gen), C.c_int, C.POINTER(gf_tuning),
                                  C.POINTER(C.c_void_p)]),
@@ -249,6 +251,21 @@ def gf_decode(field: int, Cm, B, S, ws=None, d_rank=None, length: Optional[int] 
     _check(lib().gf_decode(field, Cm.data_ptr(), B.data_ptr(), ld_b, N, S.data_ptr(), ld_s, L, ws.data_ptr(),
                            ws.numel(), rp, _stream(stream)), "gf_decode")
     return ws
+
+
+def gf_decode_noalloc(field: int, Cm, B, S, d_rank=None, length: Optional[int] = None, stream=None):
+    """gf_decode with the library's fixed device scratch instead of a workspace (allocates nothing)."""
+    N, N2, _ = _rows(Cm, "C")
+    if N != N2 or not Cm.is_contiguous():
+        raise ValueError("C must be a contiguous N x N matrix")
+    nB, lB, ld_b = _rows(B, "B")
+    nS, lS, ld_s = _rows(S, "S")
+    L = min(lB, lS) if length is None else length
+    if nB < N or nS < N or L > lB or L > lS:
+        raise ValueError("shape mismatch")
+    rp = _rank_ptr(d_rank, 1)
+    _check(lib().gf_decode_noalloc(field, Cm.data_ptr(), B.data_ptr(), ld_b, N, S.data_ptr(), ld_s, L, rp,
+                                   _stream(stream)), "gf_decode_noalloc")
 
 
 def gf_invert(field: int, Cm, Cinv, d_rank=None, stream=None):

@@ -33,10 +33,19 @@ namespace {
 
 constexpr int kMaxDevices = 64;
 
+// Scratch memory of gf_decode_noalloc: the inverse of up to GF_MAX_N x
+// GF_MAX_N, then the rank.  Every device holds its own copy until the process
+// ends.  In host code this name is only a handle for hipGetSymbolAddress; the
+// device address found at set-up (DevState::scratch) is what kernels get.
+constexpr size_t kScratchInverse = (size_t)GF_MAX_N * GF_MAX_N;
+constexpr size_t kScratchBytes = kScratchInverse + 256;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
 struct DevState {
     bool ready = false;
     DevTables t{nullptr, nullptr, nullptr};
     int cus = 0;
+    uint8_t *scratch = nullptr;   // device address of `scratch` on this device
 };
 
 std::mutex g_mu;
@@ -67,9 +76,18 @@ int current_state(DevState **out)
             (void)hipFree(rw);
             return GF_EDEVICE;
         }
+        // this device's copy of the scratch array (the device is current here)
+        void *sp = nullptr;
+        if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp) {
+            (void)hipFree(pt);
+            (void)hipFree(iv);
+            (void)hipFree(rw);
+            return GF_EDEVICE;
+        }
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             cus = 256;
+        d.scratch = static_cast<uint8_t *>(sp);
         d.t.ptab = static_cast<uint32_t *>(pt);
         d.t.inv = static_cast<uint8_t *>(iv);
         d.t.rows = static_cast<uint8_t *>(rw);
@@ -77,6 +95,20 @@ int current_state(DevState **out)
         d.ready = true;
     }
     *out = &d;
+    return GF_OK;
+}
+
+// The state of the current device only if gf_init (or any other call) has
+// already set it up: GF_ENOTINIT otherwise.  Allocates nothing.
+int ready_state(DevState **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return GF_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_dev[dev].ready)
+        return GF_ENOTINIT;
+    *out = &g_dev[dev];
     return GF_OK;
 }
 
@@ -435,6 +467,22 @@ int gf_decode(int field, const uint8_t *C, const uint8_t *B, size_t ld_b, int N,
         return rc;
     uint8_t *cinv = static_cast<uint8_t *>(ws);
     int *rank = d_rank ? d_rank : reinterpret_cast<int *>(cinv + inverse_bytes(N));
+    return decode_impl(d, field, C, B, ld_b, N, S, ld_s, len, cinv, rank, stream);
+}
+
+int gf_decode_noalloc(int field, const uint8_t *C, const uint8_t *B, size_t ld_b, int N, uint8_t *S, size_t ld_s,
+                      size_t len, int *d_rank, void *stream)
+{
+    size_t es, eb, ec;
+    int rc = check_decode_args(field, C, B, ld_b, N, S, ld_s, len, &es, &eb, &ec);
+    if (rc)
+        return rc;
+    static_assert((size_t)GF_MAX_N * GF_MAX_N <= kScratchInverse, "scratch holds the largest inverse");
+    DevState *d;
+    if ((rc = ready_state(&d)))
+        return rc;
+    uint8_t *cinv = d->scratch;
+    int *rank = d_rank ? d_rank : reinterpret_cast<int *>(d->scratch + kScratchInverse);
     return decode_impl(d, field, C, B, ld_b, N, S, ld_s, len, cinv, rank, stream);
 }
 

@@ -101,6 +101,12 @@ def test_decode_argument_checks():
     assert L.gf_decode(8, P1, P2, 10, 4, P3, 10, 10, P4, ws - 1, None, None) == gf.GF_EINVAL  # small ws
     assert L.gf_decode(8, P1, P2, 10, 4, P2 + 3, 10, 10, P4, ws, None, None) == gf.GF_EINVAL  # S overlaps B
     assert L.gf_decode(8, P1, P2, 10, 4, P3, 10, 10, P3 + 8, ws, None, None) == gf.GF_EINVAL  # ws overlaps S
+    # the allocation-free decode checks the same arguments (no workspace)
+    assert L.gf_decode_noalloc(8, P1, P2, 10, 0, P3, 10, 10, None, None) == gf.GF_EINVAL
+    assert L.gf_decode_noalloc(8, P1, P2, 10, 257, P3, 10, 10, None, None) == gf.GF_ERANGE
+    assert L.gf_decode_noalloc(8, P1, P2, 10, 4, P2 + 3, 10, 10, None, None) == gf.GF_EINVAL  # S overlaps B
+    assert L.gf_decode_noalloc(8, P1, P2, 10, 4, P1 + 2, 10, 10, None, None) == gf.GF_EINVAL  # S overlaps C
+    assert L.gf_decode_noalloc(3, P1, P2, 10, 4, P3, 10, 10, None, None) == gf.GF_EINVAL
     assert L.gf_invert(8, P1, 4, P1 + 2, None, None) == gf.GF_EINVAL                          # Cinv overlaps C
     assert L.gf_invert(8, P1, 0, P2, None, None) == gf.GF_EINVAL
 
@@ -201,4 +207,5 @@ def test_spans_that_fit_still_pass_validation():
     assert L.gf_encode(8, P1, 1, 2, P2, 10, P3, 1 << 63, 10, None) == gf.GF_EDEVICE   # one row: pitch unused
     ws = L.gf_decode_workspace(8, 4, 1)
     assert L.gf_decode(8, P1, P2, 10, 4, P3, 10, 10, P4, ws, None, None) == gf.GF_EDEVICE
+    assert L.gf_decode_noalloc(8, P1, P2, 10, 4, P3, 10, 10, None, None) == gf.GF_EDEVICE
     assert L.gf_invert(8, P1, 4, P2, None, None) == gf.GF_EDEVICE
