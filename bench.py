@@ -131,7 +131,7 @@ def make_parser() -> argparse.ArgumentParser:
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--bytes-per-lane", type=int, default=0)
     ap.add_argument("--form", type=int, default=0, help="0 autotune, 1 table, 2 bit-matrix MFMA")
-    ap.add_argument("--serve-requests", type=int, default=4000, help="requests per serving run (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=20000, help="requests per serving run (0: skip)")
     ap.add_argument("--serve-budget-gib", type=float, default=4.0)
     ap.add_argument("--serve-burst", type=int, default=0,
                     help="packets a decode request absorbs per step (0: the library default)")
@@ -222,7 +222,7 @@ def main():
         pf.destroy()
     log("forms: %s" % forms)
 
-    launch = (lambda: gf.gf_encode_batched(plan)) if args.no_graph else (lambda: gf.gf_plan_launch_graph(plan))
+    launch = (lambda: gf.gf_plan_launch(plan)) if args.no_graph else (lambda: gf.gf_plan_launch_graph(plan))
 
     # ------------------------------------------------------------ batched
     for _ in range(args.warmup):
@@ -297,11 +297,14 @@ def main():
         got = madds / (kern_ms * 1e-3) / 1e12
         roofline["compute"] = {"bound": "alu", "achieved": round(got, 3), "peak": round(peak, 3),
                                "unit": "T byte-madd/s", "frac": round(got / peak, 4)}
-    copy_gbs = stream_copy_gbs(torch)
-    roofline["measured_copy_gbs"] = round(copy_gbs, 1)
-    roofline["frac_of_measured_copy"] = round(achieved / copy_gbs, 4)
-    log("roofline: %.1f GB/s of algorithmic HBM bytes = %.3f of 8 TB/s (device copy measures %.0f GB/s)"
-        % (achieved, achieved / HBM_PEAK_GBS, copy_gbs))
+    ceil = measure_ceilings(gf, torch)
+    ceil["torch_copy_gbs"] = round(stream_copy_gbs(torch), 1)
+    roofline["measured_ceilings"] = ceil
+    roofline["frac_of_measured_copy"] = round(achieved / ceil["copy_gbs"], 4)
+    if tuning["form"] == 2:
+        roofline["compute"]["frac_of_measured_fp4"] = round(roofline["compute"]["achieved"] / ceil["fp4_mfma_tflops"], 4)
+    log("roofline: %.1f GB/s of algorithmic HBM bytes = %.3f of 8 TB/s; measured ceilings %s"
+        % (achieved, achieved / HBM_PEAK_GBS, ceil))
 
     # ------------------------------------------------------------ CPU oracle
     cpu = None
@@ -581,9 +584,9 @@ def part_decode(gf, torch, args) -> dict:
             encd[i] = gf.gf_gen(cp, sp, bp, N, N, L, ld, ld)
             sysd[i] = gf.gf_sys(cp, bp, rp, N, 0, L, ld, ld)
         eplan = gf.gf_plan_encode_desc(8, encd, count, tune={"form": 1}, keep=(C_dev, S_dev, B_dev))
-        gf.gf_encode_batched(eplan)
+        gf.gf_plan_launch(eplan)
         dplan = gf.gf_plan_decode_desc(8, sysd, count, keep=(C_dev, B_dev, R_dev))
-        gf.gf_decode_batched(dplan, rank)
+        gf.gf_plan_launch(dplan, rank)
         torch.cuda.synchronize()
         ranks = rank.cpu().numpy()
         bad = np.nonzero(ranks != db.Ns)[0]
@@ -665,6 +668,39 @@ def stream_copy_gbs(torch, nbytes: int = 4 << 30, reps: int = 5) -> float:
     del src, dst
     torch.cuda.empty_cache()
     return best
+
+
+def measure_ceilings(gf, torch) -> dict:
+    """What the chip delivers for each kernel form's instruction mix, by the library's
+    microbenchmarks (gf_ceiling): device copy bandwidth, byte-madds/s of the table form's
+    lookup step, dense FP4 MFMA TFLOP/s, and 3-input bit operations/s of the bit-plane step."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    out = {}
+
+    def timed(what, buf, blocks, iters):
+        gf.gf_ceiling(what, buf, blocks, max(1, iters // 10))        # warm-up
+        e0, e1 = _events(torch)
+        e0.record()
+        gf.gf_ceiling(what, buf, blocks, iters)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3
+
+    buf = torch.empty(4 << 30, dtype=torch.uint8, device="cuda")
+    t = min(timed(0, buf, cus * 32, 0) for _ in range(3))
+    out["copy_gbs"] = round(buf.numel() / t / 1e9, 1)                  # half read + half written
+    small = torch.empty(cus * 64 * 1024, dtype=torch.uint8, device="cuda")
+    blocks, iters = cus * 8, 4000
+    t = timed(1, small, blocks, iters)
+    out["table_byte_madds_per_s"] = round(blocks * 256 * iters * 64 / t, 1)
+    blocks_m, iters_m = cus * 2, 4000
+    t = timed(2, small, blocks_m, iters_m)
+    out["fp4_mfma_tflops"] = round(blocks_m * 4 * iters_m * 8 * 2 * 32 * 32 * 64 / t / 1e12, 1)
+    t = timed(3, small, blocks, iters)
+    out["bitplane_ops_per_s"] = round(blocks * 256 * iters * 64 / t, 1)
+    del buf, small
+    torch.cuda.empty_cache()
+    return out
 
 
 def host_cpu() -> dict:
@@ -759,28 +795,31 @@ def single_generation_oracle(gf, torch, oracle) -> dict:
             "decode_equals_source": bool(r == 16 and R is not None and (R == g.S).all())}
 
 
+SENDER_POOL = 3          # a decode's sender can emit up to 3 N coded packets
+
+
 def serving_trace(gf, torch, count: int, n: int = 8) -> dict:
     """The serving workload's requests: 70% encode / 30% decode over GF(2^n), N uniform in
-    {8..256}, packet length log-uniform in [64, 9000] B; a decode request receives the coded
-    packets of a rateless sender (fresh uniform coefficient vectors, 1.5 N emitted, 10% lost
-    i.i.d., random order), released one every microsecond from the request's arrival.  Arrival
-    times are left at 0 (the caller scales `unit_gaps`).  Also returns, per request, where its
-    coefficients and sources sit in the host and device blobs."""
+    {8..256}, packet length log-uniform in [64, 9000] B.  A decode request's sender is rateless:
+    it emits coded packets with fresh uniform coefficient vectors, one every microsecond from the
+    request's arrival, in a random order of its pool of 3 N, each lost i.i.d. with probability
+    0.1, until the server reports the generation decoded (the replay stops it there).  Sources
+    and coefficients are drawn on the device from the seeded streams.  Arrival times are left at
+    0 (the caller scales `unit_gaps`).  Also returns, per request, where its coefficients and
+    sources sit in the device blobs."""
     from paper_1909_02871_amd.serving import TraceRequest
 
     reqs = synth.serving_stream(count, 1.0)          # shapes and kinds; arrival times are rescaled later
     unit_gaps = np.array([r.arrival_s for r in reqs])
     enc = [r for r in reqs if r.kind == "encode"]
     dec = [r for r in reqs if r.kind == "decode"]
-    pkt_per = {r.rid: int(np.ceil(1.5 * r.N)) for r in dec}
+    pool = {r.rid: SENDER_POOL * r.N for r in dec}
     s_need = sum(r.N * synth.padded(r.length) for r in reqs)
-    c_need = sum(r.N * r.N for r in enc) + sum(pkt_per[r.rid] * r.N for r in dec)
+    c_need = sum(r.N * r.N for r in enc) + sum(pool[r.rid] * r.N for r in dec)
     base = synth.key(synth.BASE_SEED + 4, 99)
-    S_host = synth.random_bytes(synth.key(base, 1), s_need)
-    C_host = synth.uniform_field(synth.key(base, 2), c_need, n)
-    S_dev = torch.from_numpy(S_host).to("cuda")
-    C_dev = torch.from_numpy(C_host).to("cuda")
-    b_need = sum(pkt_per[r.rid] * synth.padded(r.length) for r in dec)
+    S_dev = synth.device_random_bytes(torch, synth.key(base, 1), s_need)
+    C_dev = device_bytes(torch, c_need, synth.key(base, 2), 1 << n)
+    b_need = sum(pool[r.rid] * synth.padded(r.length) for r in dec)
     B_dev = torch.empty(max(b_need, 16), dtype=torch.uint8, device="cuda")
     s_off = c_off = b_off = 0
     trace, where = [], {}
@@ -797,7 +836,7 @@ def serving_trace(gf, torch, count: int, n: int = 8) -> dict:
             trace.append(TraceRequest(r.rid, 0.0, "encode", r.N, r.length, C=Cm.data_ptr(), S=S.data_ptr(), K=r.N,
                                       ld_s=ld))
         else:
-            P = pkt_per[r.rid]
+            P = pool[r.rid]
             Cp = C_dev[c_off:c_off + P * r.N].view(P, r.N)
             c_off += P * r.N
             Bp = B_dev[b_off:b_off + P * ld].view(P, ld)
@@ -809,29 +848,30 @@ def serving_trace(gf, torch, count: int, n: int = 8) -> dict:
             trace.append(TraceRequest(r.rid, 0.0, "decode", r.N, r.length, packets=pk))
     torch.cuda.synchronize()
     return {"trace": trace, "unit_gaps": unit_gaps, "src_bytes": src_bytes, "enc": enc, "where": where,
-            "S_host": S_host, "C_host": C_host, "S_dev": S_dev, "C_dev": C_dev, "B_dev": B_dev}
+            "S_dev": S_dev, "C_dev": C_dev, "B_dev": B_dev}
 
 
 def serve_bench(gf, torch, args) -> dict:
     """Serving: Poisson arrivals of 70% encode / 30% decode requests over GF(256).
 
     N uniform in {8..256}, packet length log-uniform in [64, 9000] B; a decode
-    request receives the coded packets of a rateless sender (fresh uniform
-    coefficient vectors, 1.5 N emitted, 10% lost i.i.d., random order),
-    released one every microsecond from the request's arrival.  The server
-    admits requests by an HBM budget.  First a run with every request
-    arriving at once gives the saturation throughput; then runs at 50% and
-    80% of it give the latency percentiles.
+    request is fed by a rateless sender (see serving_trace) that stops once the
+    server reports the generation decoded.  The server admits requests by an HBM
+    budget.  For each budget (4 GiB and a tight 512 MiB) a run with every request
+    arriving at once gives the saturation throughput, then runs at 50%, 80% and
+    95% of it give the latency percentiles.
     """
     from paper_1909_02871_amd.serving import percentile, replay
 
     n = 8
     count = args.serve_requests
+    t0 = time.perf_counter()
     st_ = serving_trace(gf, torch, count)
     trace, unit_gaps, src_bytes, enc = st_["trace"], st_["unit_gaps"], st_["src_bytes"], st_["enc"]
-    budget = int(args.serve_budget_gib * (1 << 30))
+    log("serving trace of %d requests built in %.1f s" % (count, time.perf_counter() - t0))
+    sum_N_dec = sum(tr.N for tr in trace if tr.kind == "decode")
 
-    def run(rate):
+    def run(rate, budget):
         for tr, g in zip(trace, unit_gaps):
             tr.arrival = 0.0 if rate is None else float(g) / rate
         srv = gf.Server(field=n, budget_bytes=budget, burst=args.serve_burst)
@@ -840,31 +880,45 @@ def serve_bench(gf, torch, args) -> dict:
         wall = time.perf_counter() - t0
         st = srv.stats()
         srv.close()
-        lat = [d["latency"] * 1e3 for d in done]
-        lat_e = [d["latency"] * 1e3 for d in done if d["kind"] == "encode"]
-        lat_d = [d["latency"] * 1e3 for d in done if d["kind"] == "decode"]
-        return {"offered_rps": None if rate is None else round(rate, 1), "completed": len(done),
-                "wall_s": round(wall, 3), "throughput_rps": round(len(done) / wall, 1),
+        ok = [d for d in done if d["status"] == 0]
+        lat = [d["latency"] * 1e3 for d in ok]
+        lat_e = [d["latency"] * 1e3 for d in ok if d["kind"] == "encode"]
+        lat_d = [d["latency"] * 1e3 for d in ok if d["kind"] == "decode"]
+        sent = sum(d["packets_sent"] for d in done if d["kind"] == "decode")
+        return {"offered_rps": None if rate is None else round(rate, 1), "completed": len(ok),
+                "cancelled": len(done) - len(ok),
+                "decodes_complete": all(d["rank"] == d_N for d, d_N in
+                                        ((d, where_N[d["id"]]) for d in done if d["kind"] == "decode")),
+                "wall_s": round(wall, 3), "throughput_rps": round(len(ok) / wall, 1),
                 "source_gbs": round(src_bytes / wall / 1e9, 3),
                 "p50_ms": round(percentile(lat, 50), 3), "p99_ms": round(percentile(lat, 99), 3),
                 "encode_p50_ms": round(percentile(lat_e, 50), 3), "encode_p99_ms": round(percentile(lat_e, 99), 3),
                 "decode_p50_ms": round(percentile(lat_d, 50), 3), "decode_p99_ms": round(percentile(lat_d, 99), 3),
                 "steps": st["steps"], "arena_peak_gib": round(st["arena_peak"] / (1 << 30), 3),
-                "packets_pushed": st["packets_pushed"], "packets_absorbed": st["packets_absorbed"]}
+                "packets_sent_per_N": round(sent / max(1, sum_N_dec), 3),
+                "packets_absorbed": st["packets_absorbed"]}
 
-    sat = run(None)
-    log("serve saturation: %s" % sat)
-    cap = sat["throughput_rps"]
-    loads = []
-    for frac in (0.5, 0.8):
-        res = run(cap * frac)
-        res["load_fraction"] = frac
-        loads.append(res)
-        log("serve at %.0f%%: %s" % (100 * frac, res))
+    where_N = {rid: w["N"] for rid, w in st_["where"].items()}
+    budgets = [4.0, 0.5] if args.serve_budget_gib == 4.0 else [args.serve_budget_gib]
+    runs = []
+    for gib in budgets:
+        budget = int(gib * (1 << 30))
+        sat = run(None, budget)
+        sat.update(budget_gib=gib, load_fraction=None)
+        log("serve %.1f GiB saturation: %s" % (gib, sat))
+        runs.append(sat)
+        cap = sat["throughput_rps"]
+        for frac in (0.5, 0.8, 0.95):
+            res = run(cap * frac, budget)
+            res.update(budget_gib=gib, load_fraction=frac)
+            runs.append(res)
+            log("serve %.1f GiB at %.0f%%: %s" % (gib, 100 * frac, res))
+    head = next(r for r in runs if r["budget_gib"] == budgets[0] and r["load_fraction"] == 0.8)
     return {"workload": "mixed_serving_gf256", "requests": count, "encode_fraction": round(len(enc) / count, 3),
             "N": "U{8..256}", "packet_bytes": "log-U[64, 9000]", "loss": 0.1, "packet_gap_us": 1.0,
-            "budget_gib": args.serve_budget_gib, "saturation": sat, "loads": loads,
-            "p50_ms": loads[-1]["p50_ms"], "p99_ms": loads[-1]["p99_ms"]}
+            "sender": "rateless: up to %d N packets, stops when the server reports rank N" % SENDER_POOL,
+            "runs": runs, "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
+            "p50_p99_at": "%.1f GiB budget, 80%% of saturation" % budgets[0]}
 
 
 if __name__ == "__main__":

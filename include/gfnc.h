@@ -54,7 +54,8 @@ enum {
                             calls (they write the rank to d_rank); for callers that synchronise
                             and find rank < N */
     GF_ENOMEM = -5,      /* device or host allocation failed (plan and server creation, serving steps) */
-    GF_ERANGE = -6       /* size above a documented limit */
+    GF_ERANGE = -6,      /* size above a documented limit */
+    GF_ECANCELED = -7    /* serving: the request was cancelled before it completed */
 };
 
 /* Initialise the field tables on the current device.  Idempotent and
@@ -150,15 +151,14 @@ int gf_decode_noalloc(int field, const uint8_t *C, const uint8_t *B, size_t ld_b
  * Cinv is written only if C is invertible.  Uses no workspace. */
 int gf_invert(int field, const uint8_t *C, int N, uint8_t *Cinv, int *d_rank, void *stream);
 
-/* ----------------------------------------------------- batched (plans)
- * A plan describes many uneven generations once; launching it is a single
- * persistent kernel (encode) or an elimination kernel plus a persistent
- * apply kernel (decode).  Plans own their device schedule and workspace;
- * creating one allocates and synchronises, launching one does neither.
- * A plan runs on the device that was current when it was created (launching
- * it with another device current is GF_EINVAL).  Launches of one plan share
- * its work-queue counters, so they must not overlap: launch a plan again only
- * on the same stream, or after the previous launch has completed. */
+/* ----------------------------------------------------- batched calls
+ * Many uneven generations in one launch.  The batched calls read their
+ * descriptors from DEVICE memory when they run, so the same call serves new
+ * buffers without host work, allocates nothing and can be captured in a HIP
+ * graph.  The descriptors are not validated on the host (they live on the
+ * device): every generation must obey the rules of gf_encode / gf_decode
+ * (pitches >= len, outputs disjoint from every input and from each other,
+ * entries < q), and what the kernels can check they do (see each call). */
 typedef struct {
     const uint8_t *C;   /* device, K x N */
     const uint8_t *S;   /* device, N rows, ld_s apart */
@@ -183,37 +183,96 @@ typedef struct {
  *         coefficient split into its bits, Sec. IV-B's decomposition; one
  *         3-input bit operation per row, source, plane and dword);
  *         GF_EINVAL for GF(256).
- * form 0 on an encode plan: every form that applies is timed on the plan's
- * own batch while the plan is created (which writes the plan's outputs) and
- * the fastest is kept (form 2 is skipped if a packet is too long for it); on
- * a decode plan form 0 means form 2 when every coded row starts 4-byte
- * aligned, else 1. */
+ * form 4: small generations streamed at 16 payload bytes per lane, every
+ *         generation's K x N tables staged once per tile and the next strip's
+ *         loads in flight during the current one's lookups; only when every
+ *         generation has K <= 8 and N <= 8 (GF_EINVAL otherwise).
+ * form 0 on an encode plan made with pointers: every form that applies is
+ * timed on the plan's own batch while the plan is created (which writes the
+ * plan's outputs) and the fastest is kept (form 2 is skipped if a packet is
+ * too long for it); on a plan made from shapes alone, or a decode plan, form 0
+ * means form 2 when every source row starts 4-byte aligned, else 1. */
 typedef struct {
-    int form;           /* 0 auto, 1 table, 2 bit-matrix, 3 bit-plane */
+    int form;           /* 0 auto, 1 table, 2 bit-matrix, 3 bit-plane, 4 small-generation stream */
     int bytes_per_lane; /* 0 = per tile; else 4, 8 or 16 payload bytes per lane everywhere */
     int grid_blocks;    /* persistent workgroups; 0 = as many as fit on the GPU at once */
     int reserved;       /* must be 0 */
 } gf_tuning;
 
+/* A plan is the tuned schedule (tiles, work queues, kernel form) of a list of
+ * generation shapes.  Creating one allocates and synchronises; launching one
+ * does neither.  A plan runs on the device that was current when it was
+ * created (GF_EINVAL with another device current).  Launches of one plan
+ * share its work-queue counters and tables, so they must not overlap: launch
+ * a plan again only on the same stream, or after the previous launch has
+ * completed. */
 typedef struct gf_plan gf_plan;
 
-/* gens: HOST array of `count` descriptors (pointers inside are device). */
+/* gens: HOST array of `count` descriptors giving the shapes (K, N, len,
+ * ld_s, ld_y).  Their pointers are either all present (device memory: the
+ * plan can then run on them with gf_plan_launch, and form 0 is tuned on them)
+ * or all NULL (a plan for shapes only: rows are taken to start 16-byte
+ * aligned, and it runs only through gf_encode_batched). */
 int gf_plan_encode(int field, const gf_gen *gens, int count, const gf_tuning *tune,
                    gf_plan **out);
-/* sys: HOST array of `count` systems. */
+
+/* Eq. (1) for every generation of d_gens in one persistent launch of the
+ * plan's schedule (Sec. II; the madd of Sec. IV-A, Alg. 1, per coefficient).
+ * d_gens: DEVICE array of `count` descriptors, count == the plan's count,
+ * field == the plan's field.  d_gens[i] must have the shape of the plan's
+ * i-th generation and rows at least as aligned as the plan assumed; a
+ * descriptor that differs (or lacks a pointer) is skipped, its output left
+ * as it was, and counted for gf_plan_errors.  d_gens NULL runs the plan on
+ * the pointers it was made with (as gf_plan_launch).  Allocates nothing. */
+int gf_encode_batched(int field, const gf_gen *d_gens, int count, gf_plan *plan, void *stream);
+
+/* Descriptors gf_encode_batched skipped since the last call (synchronises the
+ * device; the count is then reset). */
+int gf_plan_errors(gf_plan *plan, uint64_t *out);
+
+/* Gauss-Jordan decoding of `count` systems, S_i = C_i^-1 B_i, read from the
+ * DEVICE array d_sys when the work runs, with no plan: the device sorts the
+ * systems into size classes for the elimination and lays out the product's
+ * work queues itself, all inside `ws`.
+ * ws: device workspace, 256-byte aligned, of at least
+ *     gf_decode_workspace(field, max_N, count) bytes, where max_N bounds every
+ *     N; it is overwritten.
+ * d_rank: device, `count` ints (may be NULL): rank(C_i); a singular system's
+ *     S_i is left untouched, and a system the kernels reject (N outside
+ *     [1, max_N the workspace allows], a pitch < len, a NULL pointer, or
+ *     len > 2^34) gets rank -1 and no output.
+ * Allocates nothing; every launch goes on `stream`. */
+int gf_decode_batched(int field, const gf_sys *d_sys, int count, int *d_rank, void *ws, size_t ws_bytes,
+                      void *stream);
+
+/* A decode plan: the same decoding for a fixed list of systems (sys: HOST
+ * array with device pointers), with the size classes' eliminations running
+ * side by side on the plan's own streams; it owns its inverses and ranks. */
 int gf_plan_decode(int field, const gf_sys *sys, int count, const gf_tuning *tune,
                    gf_plan **out);
-/* Encode every generation of the plan in one persistent launch. */
-int gf_encode_batched(gf_plan *plan, void *stream);
-/* Decode every system: d_rank (device, `count` ints, may be NULL) gets each rank. */
-int gf_decode_batched(gf_plan *plan, int *d_rank, void *stream);
-/* Same work as the plan's batched call, replayed from a HIP graph captured on
- * first use (d_rank as for gf_decode_batched; must be the same pointer on
- * every replay of a decode plan). */
+
+/* Run a plan on the descriptors it was made with (encode, recode or decode;
+ * d_rank: device, `count` ints, for a decode plan, may be NULL; ignored
+ * otherwise).  GF_EINVAL for a plan made from shapes alone. */
+int gf_plan_launch(gf_plan *plan, int *d_rank, void *stream);
+/* Same work as gf_plan_launch, replayed from a HIP graph captured on first
+ * use (d_rank must be the same pointer on every replay of a decode plan). */
 int gf_plan_launch_graph(gf_plan *plan, int *d_rank, void *stream);
 /* The schedule the plan uses (after autotuning). */
 int gf_plan_tuning(const gf_plan *plan, gf_tuning *out);
 void gf_plan_destroy(gf_plan *plan);
+
+/* Diagnostic microbenchmarks for roofline reports (no part of the coding
+ * path): what 0 copies the first half of d_buf (bytes long) to the second half
+ * with 16-byte non-temporal accesses (blocks x 256 threads, grid-stride); what
+ * 1 runs the table form's inner step (byte-select lookups and 3-input XORs on
+ * register data: 8 coded rows x 2 sources x 4 bytes = 64 byte-madds per thread
+ * and iteration), 2 back-to-back FP4 32x32x64 MFMAs (8 per wave and
+ * iteration), 3 the bit-plane form's step (64 three-input bit operations per
+ * thread and iteration), each on blocks x 256 threads for `iters` iterations,
+ * writing one word per thread to d_buf (bytes >= blocks * 1024).  Time it on
+ * `stream` with events. */
+int gf_ceiling(int what, void *d_buf, size_t bytes, int blocks, int iters, void *stream);
 
 /* Per-generation launches of the same work (the unbatched baseline): one
  * gf_encode per descriptor, on `stream`.  gens is a HOST array. */
@@ -252,7 +311,7 @@ typedef struct {
 } gf_recode_desc;
 
 /* Plan for many recodings at once (descs: HOST array).  Launched with
- * gf_encode_batched or gf_plan_launch_graph: one persistent launch over the
+ * gf_plan_launch or gf_plan_launch_graph: one persistent launch over the
  * headers that are not stored in front of their payloads (if any), then one
  * over the payloads (with the headers that are), each autotuned like
  * gf_plan_encode (form 0 runs trials that write the outputs).
@@ -306,7 +365,7 @@ typedef struct {
 typedef struct {
     uint64_t id;
     int kind;                /* 0 encode, 1 decode */
-    int status;              /* GF_OK */
+    int status;              /* GF_OK, or GF_ECANCELED (gf_serve_cancel) */
     int rank;                /* decode: N; encode: K */
     int packets_seen;        /* decode: packets taken into the echelon state */
     int packets_dropped;     /* decode: of those, not innovative */
@@ -342,11 +401,38 @@ int gf_serve_step(gf_server *sv, double now);
 int gf_serve_poll(gf_server *sv, gf_serve_done *out, int max);
 /* Copy a polled request's output rows (K for encode, N for decode; len
  * bytes each) to dst (device, rows ld_dst apart).  The copy is enqueued on
- * `stream` (the caller's), after the caller's earlier work on it. */
+ * `stream` (the caller's), after the caller's earlier work on it.  GF_EINVAL
+ * for a cancelled request (it has no output). */
 int gf_serve_copy_out(gf_server *sv, uint64_t id, uint8_t *dst, size_t ld_dst, void *stream);
-/* Return a polled request's memory to the arena (deferred until no step in
- * flight refers to it). */
+/* Return a polled request's memory to the arena.  The memory is reused only
+ * after no step in flight refers to it and every copy_out of the request has
+ * run on its stream, so a release right after an (unfinished) copy_out is
+ * safe. */
 int gf_serve_release(gf_server *sv, uint64_t id);
+/* What the server knows of a request that has not been released: its state
+ * (0 queued, 1 admitted, 2 completed), the rank of a decode's echelon state as
+ * of the last collected step (an encode: K once completed), the packets pushed
+ * but not yet taken into a step, and the packets taken so far and dropped as
+ * not innovative.  A sender uses it as the receiver's feedback.  GF_EINVAL for
+ * an unknown or released id. */
+typedef struct {
+    int state;
+    int rank;
+    int packets_pending;
+    int packets_seen;
+    int packets_dropped;
+} gf_serve_status;
+int gf_serve_query(gf_server *sv, uint64_t id, gf_serve_status *out);
+
+/* Give up on a request that has not completed, e.g. a decode whose sender
+ * stopped before rank N.  A queued request completes at once; an admitted
+ * decode takes no more packets and completes as soon as no step in flight
+ * refers to it (a decode that reaches rank N in a step already in flight
+ * completes normally).  It is then polled with status GF_ECANCELED and its
+ * rank so far, has no output, and is released as usual.  GF_EINVAL for an
+ * unknown, completed or already cancelled request, and for an admitted
+ * encode (it completes in the step it is in). */
+int gf_serve_cancel(gf_server *sv, uint64_t id, double now);
 /* Wait for every step in flight and collect it. */
 int gf_serve_drain(gf_server *sv, double now);
 int gf_serve_stats(gf_server *sv, gf_serve_counters *out);

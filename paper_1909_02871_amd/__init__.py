@@ -13,9 +13,11 @@ CPU fallback.
 
 Names match the C entry points: ``gf_init``, ``gf_region_madd``,
 ``gf_region_mul``, ``gf_region_madd_batched``, ``gf_encode``, ``gf_decode``,
-``gf_invert``, ``gf_plan_encode``/``gf_plan_decode`` with
-``gf_encode_batched``/``gf_decode_batched``/``gf_plan_launch_graph``, and
-``gf_encode_each``.
+``gf_decode_noalloc``, ``gf_invert``, ``gf_encode_batched`` (device descriptors, with a
+plan from ``gf_plan_encode``), ``gf_decode_batched`` (device descriptors and a
+workspace, no plan), ``gf_plan_decode``/``gf_plan_recode`` with
+``gf_plan_launch``/``gf_plan_launch_graph``, ``gf_encode_each`` and the serving
+runtime ``Server``.
 """
 from __future__ import annotations
 
@@ -29,6 +31,7 @@ LIB_PATH = os.environ.get("GFNC_LIB") or os.path.join(_HERE, "libgfnc.so")
 GF_2, GF_4, GF_16, GF_256 = 1, 2, 4, 8
 FIELDS = (GF_2, GF_4, GF_16, GF_256)
 GF_OK, GF_EINVAL, GF_ENOTINIT, GF_EDEVICE, GF_ESINGULAR, GF_ENOMEM, GF_ERANGE = 0, -1, -2, -3, -4, -5, -6
+GF_ECANCELED = -7
 GF_MAX_N = 256
 GF_MAX_K = 65535
 
@@ -86,10 +89,14 @@ _SIGS = {
                                  C.POINTER(C.c_void_p)]),
     "gf_plan_decode": (C.c_int, [C.c_int, C.POINTER(gf_sys), C.c_int, C.POINTER(gf_tuning),
                                  C.POINTER(C.c_void_p)]),
-    "gf_encode_batched": (C.c_int, [C.c_void_p, C.c_void_p]),
-    "gf_decode_batched": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gf_encode_batched": (C.c_int, [C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "gf_plan_errors": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64)]),
+    "gf_decode_batched": (C.c_int, [C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_size_t,
+                                    C.c_void_p]),
+    "gf_plan_launch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "gf_plan_launch_graph": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "gf_plan_tuning": (C.c_int, [C.c_void_p, C.POINTER(gf_tuning)]),
+    "gf_ceiling": (C.c_int, [C.c_int, C.c_void_p, C.c_size_t, C.c_int, C.c_int, C.c_void_p]),
     "gf_plan_destroy": (None, [C.c_void_p]),
     "gf_encode_each": (C.c_int, [C.c_int, C.POINTER(gf_gen), C.c_int, C.POINTER(gf_tuning), C.c_void_p]),
     "gf_recode": (C.c_int, [C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p,
@@ -284,13 +291,20 @@ def _tuning(t: Optional[dict]):
 
 
 class Plan:
-    """A batched plan (encode or decode) over many uneven generations."""
+    """A batched plan (encode, recode or decode) over many uneven generations."""
 
-    def __init__(self, handle: int, kind: str, count: int, keep):
+    def __init__(self, handle: int, kind: str, count: int, keep, field: int = 0):
         self._h = C.c_void_p(handle)
         self.kind = kind
         self.count = count
+        self.field = field
         self._keep = keep   # tensors the plan points into
+
+    def errors(self) -> int:
+        """Descriptors gf_encode_batched skipped since the last call (synchronises)."""
+        v = C.c_uint64()
+        _check(lib().gf_plan_errors(self._h, C.byref(v)), "gf_plan_errors")
+        return int(v.value)
 
     def tuning(self) -> dict:
         t = gf_tuning()
@@ -324,14 +338,14 @@ def gf_plan_encode(field: int, gens: Sequence[tuple], tune: Optional[dict] = Non
     arr = (gf_gen * len(gens))(*[_gen_desc(*g) for g in gens])
     h = C.c_void_p()
     _check(lib().gf_plan_encode(field, arr, len(gens), _tuning(tune), C.byref(h)), "gf_plan_encode")
-    return Plan(h.value, "encode", len(gens), list(gens))
+    return Plan(h.value, "encode", len(gens), list(gens), field)
 
 
 def gf_plan_encode_desc(field: int, arr, count: int, tune: Optional[dict] = None, keep=None) -> Plan:
     """Plan from a ctypes array of gf_gen built by the caller."""
     h = C.c_void_p()
     _check(lib().gf_plan_encode(field, arr, count, _tuning(tune), C.byref(h)), "gf_plan_encode")
-    return Plan(h.value, "encode", count, keep)
+    return Plan(h.value, "encode", count, keep, field)
 
 
 def gf_plan_decode(field: int, systems: Sequence[tuple], tune: Optional[dict] = None) -> Plan:
@@ -353,21 +367,72 @@ def gf_plan_decode(field: int, systems: Sequence[tuple], tune: Optional[dict] = 
 def gf_plan_decode_desc(field: int, arr, count: int, tune: Optional[dict] = None, keep=None) -> Plan:
     h = C.c_void_p()
     _check(lib().gf_plan_decode(field, arr, count, _tuning(tune), C.byref(h)), "gf_plan_decode")
-    return Plan(h.value, "decode", count, keep)
+    return Plan(h.value, "decode", count, keep, field)
 
 
-def gf_encode_batched(plan: Plan, stream=None):
-    _check(lib().gf_encode_batched(plan._h, _stream(stream)), "gf_encode_batched")
+def _device_array(arr, name: str):
+    """A ctypes array of descriptors copied into a CUDA uint8 tensor."""
+    torch = _torch()
+    return torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8).to("cuda")
 
 
-def gf_decode_batched(plan: Plan, d_rank=None, stream=None):
-    rp = _rank_ptr(d_rank, plan.count)
-    _check(lib().gf_decode_batched(plan._h, rp, _stream(stream)), "gf_decode_batched")
+def make_gens(arr):
+    """Device copy of a ctypes array of gf_gen (for gf_encode_batched)."""
+    return _device_array(arr, "gens")
+
+
+def make_systems(arr):
+    """Device copy of a ctypes array of gf_sys (for gf_decode_batched)."""
+    return _device_array(arr, "systems")
+
+
+def gf_encode_batched(field: int, d_gens, count: int, plan: Plan, stream=None):
+    """Encode the generations of the device descriptor array d_gens (a CUDA uint8 tensor of
+    ``count`` gf_gen, e.g. from make_gens; None: the plan's own) with the plan's schedule."""
+    if d_gens is not None:
+        _dev_u8(d_gens, "d_gens")
+        if not d_gens.is_contiguous() or d_gens.numel() < count * C.sizeof(gf_gen):
+            raise ValueError("d_gens must be contiguous with %d descriptors" % count)
+    _check(lib().gf_encode_batched(field, None if d_gens is None else d_gens.data_ptr(), count, plan._h,
+                                   _stream(stream)), "gf_encode_batched")
+
+
+def gf_decode_batched(field: int, d_sys, count: int, d_rank=None, ws=None, max_N: int = GF_MAX_N, stream=None):
+    """Decode the systems of the device descriptor array d_sys (a CUDA uint8 tensor of ``count``
+    gf_sys, e.g. from make_systems), no plan; ws: CUDA uint8 workspace (allocated for max_N if None).
+    Returns the workspace."""
+    torch = _torch()
+    _dev_u8(d_sys, "d_sys")
+    if not d_sys.is_contiguous() or d_sys.numel() < count * C.sizeof(gf_sys):
+        raise ValueError("d_sys must be contiguous with %d descriptors" % count)
+    if ws is None:
+        ws = torch.empty(max(1, gf_decode_workspace(field, max_N, max(count, 1))), dtype=torch.uint8,
+                         device=d_sys.device)
+    _dev_u8(ws, "ws")
+    if not ws.is_contiguous():
+        raise ValueError("ws must be contiguous")
+    rp = _rank_ptr(d_rank, count)
+    _check(lib().gf_decode_batched(field, d_sys.data_ptr(), count, rp, ws.data_ptr(), ws.numel(),
+                                   _stream(stream)), "gf_decode_batched")
+    return ws
+
+
+def gf_plan_launch(plan: Plan, d_rank=None, stream=None):
+    """Run a plan on the descriptors it was made with (d_rank: decode plans)."""
+    rp = _rank_ptr(d_rank, plan.count) if plan.kind == "decode" else None
+    _check(lib().gf_plan_launch(plan._h, rp, _stream(stream)), "gf_plan_launch")
 
 
 def gf_plan_launch_graph(plan: Plan, d_rank=None, stream=None):
     rp = _rank_ptr(d_rank, plan.count) if plan.kind == "decode" else None
     _check(lib().gf_plan_launch_graph(plan._h, rp, _stream(stream)), "gf_plan_launch_graph")
+
+
+def gf_ceiling(what: int, buf, blocks: int, iters: int, stream=None):
+    """Diagnostic microbenchmark (0 copy, 1 table step, 2 FP4 MFMA, 3 bit-plane step) on the CUDA
+    uint8 tensor ``buf`` (enqueued; time it with events)."""
+    _dev_u8(buf, "buf")
+    _check(lib().gf_ceiling(what, buf.data_ptr(), buf.numel(), blocks, iters, _stream(stream)), "gf_ceiling")
 
 
 def gf_encode_each(field: int, gens, count: Optional[int] = None, tune: Optional[dict] = None, stream=None):
@@ -430,6 +495,11 @@ class gf_serve_done(C.Structure):
                 ("ld_out", C.c_uint64), ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
 
 
+class gf_serve_status(C.Structure):
+    _fields_ = [("state", C.c_int), ("rank", C.c_int), ("packets_pending", C.c_int), ("packets_seen", C.c_int),
+                ("packets_dropped", C.c_int)]
+
+
 class gf_serve_counters(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("steps", "submitted", "admitted", "completed", "queued", "active",
                                            "inflight_steps", "arena_bytes", "arena_used", "arena_peak",
@@ -448,6 +518,8 @@ _SERVE_SIGS = {
     "gf_serve_poll": (C.c_int, [C.c_void_p, C.POINTER(gf_serve_done), C.c_int]),
     "gf_serve_release": (C.c_int, [C.c_void_p, C.c_uint64]),
     "gf_serve_copy_out": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "gf_serve_cancel": (C.c_int, [C.c_void_p, C.c_uint64, C.c_double]),
+    "gf_serve_query": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(gf_serve_status)]),
     "gf_serve_drain": (C.c_int, [C.c_void_p, C.c_double]),
     "gf_serve_stats": (C.c_int, [C.c_void_p, C.POINTER(gf_serve_counters)]),
 }
@@ -531,6 +603,17 @@ class Server:
     def release(self, rid: int):
         _check(lib().gf_serve_release(self._h, rid), "gf_serve_release")
         self._shape.pop(rid, None)
+
+    def query(self, rid: int) -> dict:
+        """State (0 queued, 1 admitted, 2 completed), rank so far and packet counts of a request."""
+        st = gf_serve_status()
+        _check(lib().gf_serve_query(self._h, rid, C.byref(st)), "gf_serve_query")
+        return {"state": st.state, "rank": st.rank, "packets_pending": st.packets_pending,
+                "packets_seen": st.packets_seen, "packets_dropped": st.packets_dropped}
+
+    def cancel(self, rid: int, now: float):
+        """Give up on a request that has not completed (polled later with status GF_ECANCELED)."""
+        _check(lib().gf_serve_cancel(self._h, rid, now), "gf_serve_cancel")
 
     def copy_out(self, rid: int, dst, stream=None):
         """Copy a completed request's output rows into the 2-D CUDA uint8 tensor `dst`

@@ -32,7 +32,8 @@ HIP_FLAGS = [
     "-I", os.path.join(ROOT, "include"),
 ]
 
-SOURCES = ["gf_kernels.hip", "gf_mfma.hip", "gf_tables.cpp", "gf_api.cpp", "gf_serve.cpp"]
+SOURCES = ["gf_kernels.hip", "gf_mfma.hip", "gf_sched.hip", "gf_ceiling.hip", "gf_tables.cpp", "gf_tune.cpp",
+           "gf_api.cpp", "gf_serve.cpp"]
 
 
 def hipcc() -> str:

@@ -150,6 +150,12 @@ bool span_of(const void *p, size_t rows, size_t ld, size_t len, size_t *out)
     return true;
 }
 
+// Stand-in addresses for validating a shape-only descriptor: 16-byte aligned,
+// 2^60 bytes apart so that no legal shape makes them overlap; never used.
+const uint8_t *const kShapeC = reinterpret_cast<const uint8_t *>(uintptr_t(1) << 60);
+const uint8_t *const kShapeS = reinterpret_cast<const uint8_t *>(uintptr_t(2) << 60);
+uint8_t *const kShapeY = reinterpret_cast<uint8_t *>(uintptr_t(3) << 60);
+
 struct Single {
     int D;
     int nsplit;
@@ -195,10 +201,16 @@ struct gf_plan {
     int fixed_D = 0;   // 0: lane width chosen per tile
     int form = 1;      // 1 table (VALU byte-select), 2 bit-matrix on the matrix cores, 3 bit-plane (VALU)
     bool src_aligned4 = false;   // every generation's source rows start 4-byte aligned
-    double tune_ms[4] = {0, 0, 0, 0};   // autotuning trial times per form (0: not timed)
+    std::vector<TuneChoice> trials;     // the autotuner's timed candidates
+    bool tuned_from_cache = false;
     int grid = 0;
     int ntiles = 0;
-    DevGen *d_gens = nullptr;
+    DevGen *d_gens = nullptr;       // the generations as described when the plan was made
+    DevGen *d_bound = nullptr;      // the same shapes with the pointers of gf_encode_batched's descriptors
+    unsigned *d_err = nullptr;      // [0] descriptors refused by that call, [1] = 1 (status of a refused one)
+    bool shape_only = false;        // made from shapes alone (no pointers to run on)
+    bool small_ok = false;          // every generation has K, N <= STREAM_MAX (form 4 applies)
+    int small_max = 0;              // the largest K or N of the batch
     DevTile *d_tiles = nullptr;
     unsigned *d_runs = nullptr;     // first tile of each run, then the queue bounds
     unsigned *d_bounds = nullptr;   // inside d_runs
@@ -264,6 +276,7 @@ const char *gf_strerror(int code)
     case GF_ESINGULAR: return "coefficient matrix is singular";
     case GF_ENOMEM: return "out of memory";
     case GF_ERANGE: return "size above the supported maximum";
+    case GF_ECANCELED: return "request cancelled";
     default: return "unknown error";
     }
 }
@@ -391,11 +404,41 @@ int gf_encode_each(int field, const gf_gen *gens, int count, const gf_tuning *tu
 // Bytes of one inverse of up to max_N x max_N, rounded to 256.
 static size_t inverse_bytes(int max_N) { return (((size_t)max_N * max_N + 255) / 256) * 256; }
 
+static size_t r256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Where gf_decode_batched keeps its tables in the workspace (byte offsets),
+// before the inverses; `fixed` is their total.
+struct DecWsLayout {
+    size_t hdr, ctr, lists, gens, tiles, rank, fixed;
+    uint64_t tile_cap;
+};
+
+static DecWsLayout dec_ws_layout(size_t count)
+{
+    DecWsLayout L;
+    size_t off = 0;
+    L.hdr = off;     // class counts [4], queue bounds [2][MF_QUEUES + 1]
+    off += 256;
+    L.ctr = off;
+    off += r256(2 * GF_QUEUE_CTR_WORDS * sizeof(unsigned));
+    L.lists = off;
+    off += r256(4 * count * sizeof(DevSys));
+    L.gens = off;
+    off += r256(count * sizeof(DevGen));
+    L.tile_cap = (uint64_t)count * ((GF_MAX_N + MF_ROWS - 1) / MF_ROWS);
+    L.tiles = off;
+    off += r256(2 * L.tile_cap * sizeof(DevTile));
+    L.rank = off;
+    off += r256(count * sizeof(int));
+    L.fixed = off;
+    return L;
+}
+
 size_t gf_decode_workspace(int field, int max_N, int count)
 {
     if (!valid_field(field) || max_N < 1 || max_N > GF_MAX_N || count < 1)
         return 0;
-    return (size_t)count * inverse_bytes(max_N) + (((size_t)count * sizeof(int) + 255) / 256) * 256;
+    return dec_ws_layout((size_t)count).fixed + (size_t)count * inverse_bytes(max_N);
 }
 
 int gf_invert(int field, const uint8_t *C, int N, uint8_t *Cinv, int *d_rank, void *stream)
@@ -497,6 +540,8 @@ static void plan_free_device(gf_plan *p)
     if (p->cap)
         (void)hipStreamDestroy(p->cap);
     (void)hipFree(p->d_gens);
+    (void)hipFree(p->d_bound);
+    (void)hipFree(p->d_err);
     (void)hipFree(p->d_tiles);
     (void)hipFree(p->d_runs);
     (void)hipFree(p->d_ctr);
@@ -642,29 +687,70 @@ void build_tiles_mfma(const DevGen *g, size_t n, TileQueues &q)
     build_queues(tiles, 48.0, q);
 }
 
+// Small-generation streaming form: per generation, tiles of up to
+// STREAM_STRIPS strips of 1 KiB over its whole length (every coded row in one
+// tile); a tile's cost is the bytes it moves, and runs hold >= 2^18 of it.
+void build_tiles_stream(const DevGen *g, size_t n, TileQueues &q)
+{
+    std::vector<std::pair<DevTile, double>> tiles;
+    for (size_t i = 0; i < n; i++) {
+        const DevGen &x = g[i];
+        if (x.K == 0 || x.len == 0)
+            continue;
+        const uint64_t nstrips = (x.len + 1023) / 1024;
+        for (uint64_t s0 = 0; s0 < nstrips; s0 += STREAM_STRIPS) {
+            const uint64_t ns = std::min<uint64_t>(STREAM_STRIPS, nstrips - s0);
+            const double bytes = (double)std::min<uint64_t>(x.len - s0 * 1024, ns * 1024);
+            tiles.push_back({DevTile{(uint32_t)i, 0, (uint16_t)(4 | ((ns - 1) << 8)), s0 * 1024},
+                             bytes * (double)(x.N + x.K)});
+        }
+    }
+    build_queues(tiles, 262144.0, q);
+}
+
 }  // namespace gfnc
 
-static int launch_schedule(gf_plan *p, DevState *d, hipStream_t s)
+// One launch of the plan's persistent kernel over the generation table
+// `gens` (the plan's own, or the one gf_encode_batched bound).
+static int launch_schedule(gf_plan *p, DevState *d, hipStream_t s, const DevGen *gens = nullptr)
 {
     const int f = p->field;
+    if (!gens)
+        gens = p->d_gens;
     hipError_t e;
     if (p->form == 2)
-        e = launch_encode_mfma(p->d_gens, p->d_tiles, p->d_runs, p->d_bounds, p->ntiles, p->d_ctr, p->grid,
+        e = launch_encode_mfma(gens, p->d_tiles, p->d_runs, p->d_bounds, p->ntiles, p->d_ctr, p->grid,
                                field_rows(d, f), p->src_aligned4, s);
     else if (p->form == 3)
-        e = launch_encode_planes(f, p->d_gens, p->d_tiles, p->d_runs, p->d_bounds, p->ntiles, p->d_ctr, p->grid, s);
+        e = launch_encode_planes(f, gens, p->d_tiles, p->d_runs, p->d_bounds, p->ntiles, p->d_ctr, p->grid, s);
+    else if (p->form == 4)
+        e = launch_encode_stream(p->small_max, gens, p->d_tiles, p->d_runs, p->d_bounds, p->ntiles, p->d_ctr,
+                                 p->grid, field_ptab(d, f), s);
     else
-        e = launch_encode_persistent(p->d_gens, p->d_tiles, p->d_runs, p->d_bounds, p->ntiles, p->d_ctr, p->grid,
+        e = launch_encode_persistent(gens, p->d_tiles, p->d_runs, p->d_bounds, p->ntiles, p->d_ctr, p->grid,
                                      field_ptab(d, f), s);
     return dev_err(e);
 }
 
 // Tile list, grid and device copies for one form.
-static int make_schedule(gf_plan *p, DevState *d, const std::vector<DevGen> &g, int form, const gf_tuning *tune)
+// Workgroups of the full persistent grid of a form (as many as fit at once).
+static int full_grid(const gf_plan *p, const DevState *d, int form)
+{
+    return d->cus * (form == 2   ? encode_mfma_blocks_per_cu(p->src_aligned4)
+                     : form == 3 ? encode_planes_blocks_per_cu(p->field)
+                     : form == 4 ? encode_stream_blocks_per_cu(p->small_max)
+                                 : encode_blocks_per_cu());
+}
+
+// grid_pct: share of the full grid (100 unless the tuner tries less).
+static int make_schedule(gf_plan *p, DevState *d, const std::vector<DevGen> &g, int form, const gf_tuning *tune,
+                         int grid_pct = 100)
 {
     TileQueues tq;
     if (form == 2)
         build_tiles_mfma(g.data(), g.size(), tq);
+    else if (form == 4)
+        build_tiles_stream(g.data(), g.size(), tq);
     else
         build_tiles(g.data(), g.size(), p->fixed_D, tq);
     (void)hipFree(p->d_tiles);
@@ -681,9 +767,7 @@ static int make_schedule(gf_plan *p, DevState *d, const std::vector<DevGen> &g, 
     if (rc)
         return rc;
     p->d_bounds = p->d_runs + tq.runs.size();
-    int grid = d->cus * (form == 2   ? encode_mfma_blocks_per_cu(p->src_aligned4)
-                         : form == 3 ? encode_planes_blocks_per_cu(p->field)
-                                     : encode_blocks_per_cu());
+    int grid = std::max(1, full_grid(p, d, form) * grid_pct / 100);
     if (tune && tune->grid_blocks > 0)
         grid = tune->grid_blocks;
     const int per_block = form == 2 ? 1 : 4;
@@ -691,24 +775,150 @@ static int make_schedule(gf_plan *p, DevState *d, const std::vector<DevGen> &g, 
     return GF_OK;
 }
 
-// Milliseconds of one launch of the current schedule (after one untimed launch).
-static double time_schedule(gf_plan *p, DevState *d)
+// Median milliseconds of `reps` launches of the current schedule over the
+// generation table `gens`, after one untimed launch; -1 on an error.
+static double time_schedule(gf_plan *p, DevState *d, const DevGen *gens, int reps = 3)
 {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    double ms = -1;
+    std::vector<double> ms;
     if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
-        launch_schedule(p, d, p->cap) == GF_OK && hipEventRecord(e0, p->cap) == hipSuccess &&
-        launch_schedule(p, d, p->cap) == GF_OK && hipEventRecord(e1, p->cap) == hipSuccess &&
-        hipEventSynchronize(e1) == hipSuccess) {
-        float f = 0;
-        if (hipEventElapsedTime(&f, e0, e1) == hipSuccess)
-            ms = f;
+        launch_schedule(p, d, p->cap, gens) == GF_OK) {
+        for (int r = 0; r < reps; r++) {
+            float f = 0;
+            if (hipEventRecord(e0, p->cap) != hipSuccess || launch_schedule(p, d, p->cap, gens) != GF_OK ||
+                hipEventRecord(e1, p->cap) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&f, e0, e1) != hipSuccess)
+                break;
+            ms.push_back(f);
+        }
     }
     if (e0)
         (void)hipEventDestroy(e0);
     if (e1)
         (void)hipEventDestroy(e1);
-    return ms;
+    if ((int)ms.size() < reps)
+        return -1;
+    std::sort(ms.begin(), ms.end());
+    return ms[ms.size() / 2];
+}
+
+// Scratch memory the tuning trials run on, so that they never write the
+// caller's outputs (and a plan of shapes has inputs to read): every trial's
+// generation table points its outputs, and for a plan of shapes its inputs,
+// into these buffers at the same offsets the rows have relative to each other.
+struct TrialBuffers {
+    uint8_t *y = nullptr, *s = nullptr, *c = nullptr;
+    ~TrialBuffers()
+    {
+        (void)hipFree(y);
+        (void)hipFree(s);
+        (void)hipFree(c);
+    }
+};
+
+static int trial_table(gf_plan *p, const std::vector<DevGen> &g, TrialBuffers &tb)
+{
+    size_t ny = 0, ns = 0, nc = 0;
+    std::vector<DevGen> t = g;
+    for (const DevGen &x : g) {
+        ny += r256(envelope(x.K, x.ld_y, x.len));
+        ns += r256(envelope(x.N, x.ld_s, x.len));
+        nc += r256((size_t)x.K * x.N);
+    }
+    if (hipMalloc(reinterpret_cast<void **>(&tb.y), std::max<size_t>(ny, 256)) != hipSuccess)
+        return GF_ENOMEM;
+    if (p->shape_only) {
+        if (hipMalloc(reinterpret_cast<void **>(&tb.s), std::max<size_t>(ns, 256)) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void **>(&tb.c), std::max<size_t>(nc, 256)) != hipSuccess)
+            return GF_ENOMEM;
+        // coefficient 1 is a field element of every field; payload bytes are whatever is there
+        if (hipMemset(tb.c, 1, std::max<size_t>(nc, 256)) != hipSuccess)
+            return GF_EDEVICE;
+    }
+    size_t oy = 0, os = 0, oc = 0;
+    for (DevGen &x : t) {
+        x.Y = tb.y + oy;
+        oy += r256(envelope(x.K, x.ld_y, x.len));
+        if (p->shape_only) {
+            x.S = tb.s + os;
+            x.C = tb.c + oc;
+            os += r256(envelope(x.N, x.ld_s, x.len));
+            oc += r256((size_t)x.K * x.N);
+        }
+    }
+    if (!t.empty() && hipMemcpy(p->d_bound, t.data(), t.size() * sizeof(DevGen), hipMemcpyHostToDevice) != hipSuccess)
+        return GF_EDEVICE;
+    return GF_OK;
+}
+
+// The autotuner: every schedule candidate (kernel form, and for the vector-ALU
+// forms the payload bytes per lane) is timed on the batch's own shapes, the
+// median of three launches each; the fastest then also tries 3/4 and 1/2 of
+// the full persistent grid.  A candidate replaces the current best only when
+// it is more than 3% faster, so near-ties resolve the same way every time.
+// The choice is cached per class of batch (gf_tune.cpp).
+static int autotune(gf_plan *p, DevState *d, const std::vector<DevGen> &g, const gf_tuning *tune)
+{
+    const std::string key = tune_key(p->field, g, p->src_aligned4, 0, tune ? tune->bytes_per_lane : 0,
+                                     tune ? tune->grid_blocks : 0);
+    TuneChoice c;
+    if (tune_cache_get(key, &c) && (c.form != 3 || p->field <= 4) && (c.form != 4 || p->small_ok)) {
+        p->tuned_from_cache = true;
+        p->fixed_D = (tune && tune->bytes_per_lane) ? tune->bytes_per_lane / 4 : c.fixed_D;
+        return make_schedule(p, d, g, c.form, tune, c.grid_pct);
+    }
+    TrialBuffers tb;
+    int rc = trial_table(p, g, tb);
+    if (rc)
+        return rc;
+    struct Cand {
+        int form, D;
+    };
+    std::vector<Cand> cands;
+    const bool fixed_bpl = tune && tune->bytes_per_lane;
+    const int D0 = fixed_bpl ? tune->bytes_per_lane / 4 : 0;
+    cands.push_back({p->src_aligned4 ? 2 : 1, p->src_aligned4 ? 0 : D0});   // the rule's choice first
+    for (int D : fixed_bpl ? std::vector<int>{D0} : std::vector<int>{0, 4, 2, 1})
+        cands.push_back({1, D});
+    cands.push_back({2, 0});
+    if (p->small_ok)
+        cands.push_back({4, 0});
+    if (p->field <= 4)
+        for (int D : fixed_bpl ? std::vector<int>{D0} : std::vector<int>{0, 4})
+            cands.push_back({3, D});
+    TuneChoice best{0, 0, 100, -1};
+    auto consider = [&](int form, int D, int pct) -> int {
+        for (const TuneChoice &t : p->trials)
+            if (t.form == form && t.fixed_D == D && t.grid_pct == pct)
+                return GF_OK;   // already timed
+        p->fixed_D = D;
+        int r = make_schedule(p, d, g, form, tune, pct);
+        if (r)
+            return r;
+        const double ms = time_schedule(p, d, p->d_bound);
+        p->trials.push_back(TuneChoice{form, D, pct, ms});
+        if (ms > 0 && (best.ms < 0 || ms < 0.97 * best.ms))
+            best = TuneChoice{form, D, pct, ms};
+        return GF_OK;
+    };
+    for (const Cand &x : cands)
+        if ((rc = consider(x.form, x.D, 100)))
+            return rc;
+    if (best.ms < 0)
+        return GF_EDEVICE;
+    if (!(tune && tune->grid_blocks > 0)) {
+        const TuneChoice top = best;
+        for (int pct : {75, 50})
+            if ((rc = consider(top.form, top.fixed_D, pct)))
+                return rc;
+    }
+    p->fixed_D = best.fixed_D;
+    if ((rc = make_schedule(p, d, g, best.form, tune, best.grid_pct)))
+        return rc;
+    if (hipDeviceSynchronize() != hipSuccess)
+        return GF_EDEVICE;
+    tune_cache_put(key, best);
+    return GF_OK;
 }
 
 // form: 1 table, 2 bit-matrix, 3 bit-plane (n <= 4); 0 = time each on the
@@ -726,12 +936,16 @@ static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, co
         p->fixed_D = tune->bytes_per_lane / 4;
     }
     int form = tune ? tune->form : 0;
-    if (form < 0 || form > 3 || (form == 3 && p->field > 4))
+    if (form < 0 || form > 4 || (form == 3 && p->field > 4))
         return GF_EINVAL;
     std::vector<DevGen> g = gens;
     p->src_aligned4 = true;
     bool mf_ok = true;   // the bit-matrix kernels count a tile's steps in 32 bits
+    p->small_ok = true;  // every generation fits the streaming form
     for (DevGen &x : g) {
+        if (x.K > STREAM_MAX || x.N > STREAM_MAX)
+            p->small_ok = false;
+        p->small_max = std::max<int>(p->small_max, (int)std::max(x.K, x.N));
         if (x.len > (1ull << 34))
             mf_ok = false;
         x.align = row_align(x.S, x.N > 1 ? x.ld_s : 0, x.Y, x.K > 1 ? x.ld_y : 0);
@@ -740,6 +954,14 @@ static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, co
     }
     if ((rc = upload(&p->d_gens, g)))
         return rc;
+    const unsigned err_init[2] = {0, 1};
+    if (!g.empty() &&
+        hipMalloc(reinterpret_cast<void **>(&p->d_bound), g.size() * sizeof(DevGen)) != hipSuccess)
+        return GF_ENOMEM;
+    if (hipMalloc(reinterpret_cast<void **>(&p->d_err), sizeof err_init) != hipSuccess)
+        return GF_ENOMEM;
+    if (hipMemcpy(p->d_err, err_init, sizeof err_init, hipMemcpyHostToDevice) != hipSuccess)
+        return GF_EDEVICE;
     if (hipMalloc(reinterpret_cast<void **>(&p->d_ctr), GF_QUEUE_CTR_WORDS * sizeof(unsigned)) != hipSuccess)
         return GF_ENOMEM;
     if (hipMemset(p->d_ctr, 0, GF_QUEUE_CTR_WORDS * sizeof(unsigned)) != hipSuccess)
@@ -750,30 +972,13 @@ static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, co
         return GF_EDEVICE;
     if (form == 2 && !mf_ok)
         return GF_ERANGE;
-    if (form == 0 && !mf_ok)
-        form = 1;
-    if (form == 0 && !may_run)   // no trial launches: the bit-matrix form when its DMA path applies
-        form = p->src_aligned4 ? 2 : 1;
+    if (form == 4 && !p->small_ok)
+        return GF_EINVAL;
+    if (form == 0 && (!may_run || !mf_ok))   // no trial launches: the bit-matrix form when its DMA path applies
+        form = p->src_aligned4 && mf_ok ? 2 : 1;
     if (form != 0)
         return make_schedule(p, d, g, form, tune);
-    // autotune: every form that applies, on the real batch
-    double best = -1;
-    int best_form = 1;
-    for (int f : {1, 2, 3}) {
-        if (f == 3 && p->field > 4)
-            continue;
-        if ((rc = make_schedule(p, d, g, f, tune)))
-            return rc;
-        const double ms = time_schedule(p, d);
-        p->tune_ms[f] = ms;
-        if (ms > 0 && (best < 0 || ms < best)) {
-            best = ms;
-            best_form = f;
-        }
-    }
-    if (best_form != p->form && (rc = make_schedule(p, d, g, best_form, tune)))
-        return rc;
-    return hipDeviceSynchronize() == hipSuccess ? GF_OK : GF_EDEVICE;
+    return autotune(p, d, g, tune);
 }
 
 static int plan_encode_impl(int field, const gf_gen *gens, int count, const gf_tuning *tune, gf_plan **out)
@@ -784,11 +989,22 @@ static int plan_encode_impl(int field, const gf_gen *gens, int count, const gf_t
     if (!valid_field(field) || count < 0 || (count > 0 && !gens))
         return GF_EINVAL;
     std::vector<DevGen> g(count);
+    bool shape_only = count > 0;
     for (int i = 0; i < count; i++) {
         const gf_gen &x = gens[i];
         if (x.K > GF_MAX_K)
             return GF_ERANGE;
-        int rc = check_encode_args(field, x.C, (int)x.K, (int)x.N, x.S, x.ld_s, x.Y, x.ld_y, x.len);
+        const bool no_ptr = !x.C && !x.S && !x.Y;
+        if (i > 0 && no_ptr != shape_only)
+            return GF_EINVAL;            // all descriptors carry pointers, or none does
+        shape_only = no_ptr;
+        int rc;
+        if (no_ptr) {
+            // a shape: the rows are taken to start 16-byte aligned
+            rc = check_encode_args(field, kShapeC, (int)x.K, (int)x.N, kShapeS, x.ld_s, kShapeY, x.ld_y, x.len);
+        } else {
+            rc = check_encode_args(field, x.C, (int)x.K, (int)x.N, x.S, x.ld_s, x.Y, x.ld_y, x.len);
+        }
         if (rc)
             return rc;
         g[i] = DevGen{x.C, x.S, x.Y, x.len, x.ld_s, x.ld_y, x.K, x.N, nullptr, 0, 1};
@@ -799,6 +1015,7 @@ static int plan_encode_impl(int field, const gf_gen *gens, int count, const gf_t
     p->kind = 0;
     p->field = field;
     p->count = count;
+    p->shape_only = shape_only;
     (void)hipGetDevice(&p->dev);
     p->gens.assign(gens, gens + count);
     int rc = build_encode_schedule(p, g, tune, true);
@@ -1058,23 +1275,105 @@ static int run_plan(gf_plan *p, int *d_rank, hipStream_t s)
     return GF_OK;
 }
 
-int gf_encode_batched(gf_plan *p, void *stream)
+int gf_plan_launch(gf_plan *p, int *d_rank, void *stream)
 {
-    if (!p || p->kind == 1)
+    if (!p || p->shape_only)
         return GF_EINVAL;
-    return run_plan(p, nullptr, (hipStream_t)stream);
+    return run_plan(p, p->kind == 1 ? d_rank : nullptr, (hipStream_t)stream);
 }
 
-int gf_decode_batched(gf_plan *p, int *d_rank, void *stream)
+int gf_encode_batched(int field, const gf_gen *d_gens, int count, gf_plan *p, void *stream)
 {
-    if (!p || p->kind != 1)
+    if (!p || p->kind == 1 || field != p->field || count != p->count)
         return GF_EINVAL;
-    return run_plan(p, d_rank, (hipStream_t)stream);
+    if (!d_gens)
+        return gf_plan_launch(p, nullptr, stream);
+    if (p->kind != 0)
+        return GF_EINVAL;    // recode plans run on their own descriptors
+    DevState *d;
+    int rc = plan_device_ok(p);
+    if (rc || (rc = current_state(&d)))
+        return rc;
+    if (count == 0)
+        return GF_OK;
+    const hipStream_t s = (hipStream_t)stream;
+    if (launch_bind_gens(d_gens, p->d_gens, p->d_bound, count, p->d_err,
+                         reinterpret_cast<const int *>(p->d_err + 1), s) != hipSuccess)
+        return GF_EDEVICE;
+    return launch_schedule(p, d, s, p->d_bound);
+}
+
+int gf_plan_errors(gf_plan *p, uint64_t *out)
+{
+    if (!p || !out)
+        return GF_EINVAL;
+    if (int rc = plan_device_ok(p))
+        return rc;
+    unsigned v = 0;
+    const unsigned zero = 0;
+    if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(&v, p->d_err, sizeof v, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(p->d_err, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess)
+        return GF_EDEVICE;
+    *out = v;
+    return GF_OK;
+}
+
+int gf_decode_batched(int field, const gf_sys *d_sys, int count, int *d_rank, void *ws, size_t ws_bytes,
+                      void *stream)
+{
+    if (!valid_field(field) || count < 0)
+        return GF_EINVAL;
+    if (count == 0)
+        return GF_OK;
+    if (!d_sys || !ws || (uintptr_t)ws % 256 != 0)
+        return GF_EINVAL;
+    const DecWsLayout L = dec_ws_layout((size_t)count);
+    if (ws_bytes < L.fixed || (ws_bytes - L.fixed) / (size_t)count < 256)
+        return GF_EINVAL;
+    const uint64_t slot = ((ws_bytes - L.fixed) / (size_t)count) / 256 * 256;
+    size_t ew, es;
+    if (!span_of(ws, 1, 0, ws_bytes, &ew) || !span_of(d_sys, 1, 0, (size_t)count * sizeof(gf_sys), &es) ||
+        overlap(ws, ew, d_sys, es) || (d_rank && overlap(ws, ew, d_rank, (size_t)count * sizeof(int))))
+        return GF_EINVAL;
+    DevState *d;
+    int rc = current_state(&d);
+    if (rc)
+        return rc;
+    uint8_t *w8 = static_cast<uint8_t *>(ws);
+    DecSched w;
+    w.cls_count = reinterpret_cast<unsigned *>(w8 + L.hdr);
+    w.bounds = w.cls_count + 4;
+    w.ctr = reinterpret_cast<unsigned *>(w8 + L.ctr);
+    w.lists = reinterpret_cast<DevSys *>(w8 + L.lists);
+    w.gens = reinterpret_cast<DevGen *>(w8 + L.gens);
+    w.tiles = reinterpret_cast<DevTile *>(w8 + L.tiles);
+    w.tile_cap = L.tile_cap;
+    w.rank = d_rank ? d_rank : reinterpret_cast<int *>(w8 + L.rank);
+    w.inv = w8 + L.fixed;
+    w.slot = slot;
+    const hipStream_t s = (hipStream_t)stream;
+    if (launch_dec_schedule(d_sys, count, w, s) != hipSuccess)
+        return GF_EDEVICE;
+    static const int kClassN[4] = {32, 64, 128, 256};
+    for (int c = 3; c >= 0; c--)
+        if (launch_invert(w.lists + (size_t)c * count, count, nullptr, kClassN[c], nullptr, nullptr,
+                          field_ptab(d, field), field_inv(d, field), s, w.cls_count + c) != hipSuccess)
+            return GF_EDEVICE;
+    // the product: systems with 4-byte aligned coded rows on the direct-to-LDS
+    // kernel, the others on the byte-load one (a kernel with an empty queue
+    // has every workgroup leave at once)
+    const int grid_dma = d->cus * encode_mfma_blocks_per_cu(true);
+    if (launch_encode_mfma(w.gens, w.tiles, nullptr, w.bounds, 1, w.ctr, grid_dma, field_rows(d, field), true, s) !=
+            hipSuccess ||
+        launch_encode_mfma(w.gens, w.tiles + L.tile_cap, nullptr, w.bounds + MF_QUEUES + 1, 1,
+                           w.ctr + GF_QUEUE_CTR_WORDS, d->cus, field_rows(d, field), false, s) != hipSuccess)
+        return GF_EDEVICE;
+    return GF_OK;
 }
 
 int gf_plan_launch_graph(gf_plan *p, int *d_rank, void *stream)
 {
-    if (!p)
+    if (!p || p->shape_only)
         return GF_EINVAL;
     if (int rc = plan_device_ok(p))
         return rc;
@@ -1107,6 +1406,19 @@ int gf_plan_launch_graph(gf_plan *p, int *d_rank, void *stream)
         p->graph_rank = d_rank;
     }
     return dev_err(hipGraphLaunch(p->exec, (hipStream_t)stream));
+}
+
+int gf_ceiling(int what, void *d_buf, size_t bytes, int blocks, int iters, void *stream)
+{
+    if (what < 0 || what > 3 || !d_buf || blocks < 1 || iters < 0)
+        return GF_EINVAL;
+    if (what == 0 ? bytes < 64 : bytes < (size_t)blocks * 256 * sizeof(uint32_t))
+        return GF_EINVAL;
+    DevState *d;
+    int rc = current_state(&d);
+    if (rc)
+        return rc;
+    return dev_err(launch_ceiling(what, d_buf, bytes, blocks, iters, (hipStream_t)stream));
 }
 
 int gf_plan_tuning(const gf_plan *p, gf_tuning *out)

@@ -1,0 +1,150 @@
+// Measured ceilings for the roofline report: the same instruction mixes as the
+// encode kernels' inner loops, run on register-resident data with no memory
+// traffic, and a plain device copy for the memory side.  The results stand
+// next to the spec-sheet peaks (8 TB/s HBM, 10.1 PFLOP/s dense FP4) so that
+// each kernel's fraction can be read against what the chip delivers.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+namespace gfnc {
+
+namespace {
+
+typedef int gf_v8i __attribute__((ext_vector_type(8)));
+typedef float gf_v16f __attribute__((ext_vector_type(16)));
+typedef uint32_t gf_u32x4 __attribute__((ext_vector_type(4)));
+
+// Copy `n16` 16-byte words from src to dst, two in flight per thread.
+__global__ __launch_bounds__(256) void k_ceil_copy(const gf_u32x4 *__restrict__ src, gf_u32x4 *__restrict__ dst,
+                                                   uint64_t n16)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * 256u;
+    uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+    for (; i + stride < n16; i += 2 * stride) {
+        const gf_u32x4 a = __builtin_nontemporal_load(src + i);
+        const gf_u32x4 b = __builtin_nontemporal_load(src + i + stride);
+        __builtin_nontemporal_store(a, dst + i);
+        __builtin_nontemporal_store(b, dst + i + stride);
+    }
+    for (; i < n16; i += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+// The table form's inner step: per dword of 4 payload bytes and per pair of
+// sources, three byte-select products each, folded into an accumulator with
+// three 3-input XORs (4.5 lane-ops per 4 byte-madds), for 8 coded rows.
+// Tables and data live in registers; `iters` steps of 8 rows x 2 sources.
+__global__ __launch_bounds__(256) void k_ceil_table(uint32_t *out, int iters, uint32_t seed)
+{
+    uint32_t t[5], x0 = seed ^ threadIdx.x, x1 = x0 * 0x9E3779B9u;
+    for (int i = 0; i < 5; i++)
+        t[i] = seed * (i + 3) + threadIdx.x;
+    uint32_t acc[8] = {};
+    for (int it = 0; it < iters; it++) {
+        const uint32_t a0 = x0 & 0x07070707u, b0 = (x0 >> 3) & 0x07070707u, c0 = (x0 >> 6) & 0x03030303u;
+        const uint32_t a1 = x1 & 0x07070707u, b1 = (x1 >> 3) & 0x07070707u, c1 = (x1 >> 6) & 0x03030303u;
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const uint32_t p0 = __builtin_amdgcn_perm(t[1] ^ k, t[0], a0);
+            const uint32_t p1 = __builtin_amdgcn_perm(t[3], t[2] ^ k, b0);
+            const uint32_t p2 = __builtin_amdgcn_perm(t[4], t[4] ^ k, c0);
+            const uint32_t q0 = __builtin_amdgcn_perm(t[0] ^ k, t[1], a1);
+            const uint32_t q1 = __builtin_amdgcn_perm(t[2], t[3] ^ k, b1);
+            const uint32_t q2 = __builtin_amdgcn_perm(t[4] ^ k, t[4], c1);
+            acc[k] = xor3(xor3(xor3(acc[k], p0, p1), p2, q0), q1, q2);
+        }
+        x0 = acc[0] ^ x1;   // the next step's data depend on this step's results
+        x1 = acc[3] ^ x0;
+    }
+    uint32_t r = 0;
+    for (int k = 0; k < 8; k++)
+        r ^= acc[k];
+    out[blockIdx.x * 256 + threadIdx.x] = r;
+}
+
+// The bit-matrix form's product: back-to-back FP4 x FP4 32x32x64 MFMAs into
+// eight independent accumulators (one 32-row tile by eight 32-column tiles).
+__global__ __launch_bounds__(256) void k_ceil_mfma(float *out, int iters, uint32_t seed)
+{
+    gf_v8i a, b;
+    for (int i = 0; i < 8; i++) {
+        a[i] = (int)((seed + threadIdx.x * 7 + i) & 0x11111111u);
+        b[i] = (int)((seed * 3 + threadIdx.x + i) & 0x22222222u);
+    }
+    gf_v16f acc[8];
+    for (int j = 0; j < 8; j++)
+        for (int v = 0; v < 16; v++)
+            acc[j][v] = 0.0f;
+    for (int it = 0; it < iters; it++) {
+#pragma unroll
+        for (int j = 0; j < 8; j++)
+            acc[j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, acc[j], 4, 4, 0, 0, 0, 0);
+    }
+    float r = 0.0f;
+    for (int j = 0; j < 8; j++)
+        for (int v = 0; v < 16; v++)
+            r += acc[j][v];
+    out[blockIdx.x * 256 + threadIdx.x] = r;
+}
+
+// The bit-plane form's step: one 3-input bit operation acc ^= plane & mask per
+// (row, source, plane, dword), for 8 rows x 8 planes of one source dword.
+__global__ __launch_bounds__(256) void k_ceil_planes(uint32_t *out, int iters, uint32_t seed)
+{
+    uint32_t pl[8], m[8], acc[8] = {};
+    for (int i = 0; i < 8; i++) {
+        pl[i] = seed * (i + 1) + threadIdx.x;
+        m[i] = (seed >> i) & 1 ? ~0u : 0u;
+    }
+    for (int it = 0; it < iters; it++) {
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+#pragma unroll
+            for (int b = 0; b < 8; b++)
+                acc[k] = __builtin_amdgcn_bitop3_b32(acc[k], pl[b], m[(b + k) & 7], 0x78);   // acc ^ (pl & m)
+#pragma unroll
+        for (int b = 0; b < 8; b++)
+            pl[b] ^= acc[b];
+    }
+    uint32_t r = 0;
+    for (int k = 0; k < 8; k++)
+        r ^= acc[k];
+    out[blockIdx.x * 256 + threadIdx.x] = r;
+}
+
+}  // namespace
+
+// what: 0 copy (the first half of buf to the second), 1 table-form step,
+// 2 FP4 MFMA, 3 bit-plane step; blocks x 256 threads, `iters` steps each.
+hipError_t launch_ceiling(int what, void *buf, uint64_t bytes, int blocks, int iters, hipStream_t s)
+{
+    const uint32_t seed = 0x2545F491u;
+    switch (what) {
+    case 0: {
+        const uint64_t n16 = bytes / 32;
+        hipLaunchKernelGGL(k_ceil_copy, dim3(blocks), dim3(256), 0, s, static_cast<const gf_u32x4 *>(buf),
+                           static_cast<gf_u32x4 *>(buf) + n16, n16);
+        break;
+    }
+    case 1:
+        hipLaunchKernelGGL(k_ceil_table, dim3(blocks), dim3(256), 0, s, static_cast<uint32_t *>(buf), iters, seed);
+        break;
+    case 2:
+        hipLaunchKernelGGL(k_ceil_mfma, dim3(blocks), dim3(256), 0, s, static_cast<float *>(buf), iters, seed);
+        break;
+    case 3:
+        hipLaunchKernelGGL(k_ceil_planes, dim3(blocks), dim3(256), 0, s, static_cast<uint32_t *>(buf), iters, seed);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gfnc

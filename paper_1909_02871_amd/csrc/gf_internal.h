@@ -5,6 +5,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <string>
 #include <vector>
 
 #include "gf_types.h"
@@ -60,8 +61,8 @@ struct DevSys {
 // Device state of one generation being decoded progressively (serving).
 struct DevDecSlot {
     uint8_t *R;      // reduced echelon rows of the innovative coefficient vectors, row stride rs
-    uint8_t *Csel;   // the innovative coefficient vectors as received, N x N (stride N)
-    uint8_t *Cinv;   // Csel^-1 once the rank reaches N, N x N
+    uint8_t *T;      // R = T Csel: weights of the accepted packets in each row of R, row stride rs
+    uint8_t *Cinv;   // Csel^-1 once the rank reaches N, N x N (Csel: the accepted vectors as received)
     uint8_t *Bsel;   // payloads of the innovative packets, row i at Bsel + i*ld
     int *meta;       // [0] rank, [1] step that completed it (-1 before), [2] packets seen,
                      // [3] packets that were not innovative, [4 .. 4+N) pivot column of row i
@@ -80,6 +81,33 @@ struct DevPacket {
     const uint8_t *coef;      // N coefficients
     const uint8_t *payload;   // len bytes
 };
+
+// Tables of a batched decode that its descriptors are read into on the device
+// (all inside the caller's workspace): see k_dec_schedule.
+struct DecSched {
+    unsigned *cls_count;   // [4] systems per elimination size class
+    unsigned *bounds;      // [2][MF_QUEUES + 1] queue bounds of the two product kernels
+    unsigned *ctr;         // [2][GF_QUEUE_CTR_WORDS] their queue counters
+    DevSys *lists;         // [4][count] systems of each size class
+    DevGen *gens;          // [count] product S = C^-1 B of each system
+    DevTile *tiles;        // [2][tile_cap] tiles of each product kernel
+    uint64_t tile_cap;
+    int *rank;             // [count]
+    uint8_t *inv;          // [count][slot] inverses
+    uint64_t slot;
+};
+
+// The autotuner's choice for a class of batches (gf_tune.cpp): kernel form,
+// dwords per lane (0: per tile), share of the full persistent grid in percent,
+// and the measured milliseconds.
+struct TuneChoice {
+    int form, fixed_D, grid_pct;
+    double ms;
+};
+std::string tune_key(int field, const std::vector<DevGen> &g, bool aligned4, int req_form, int req_bpl,
+                     int req_grid);
+bool tune_cache_get(const std::string &key, TuneChoice *out);
+void tune_cache_put(const std::string &key, const TuneChoice &c);
 
 constexpr int ENC_ROWS = GF_ENC_ROWS;   // coded rows per wave tile
 inline uint64_t wave_strip(int D) { return 256ull * (uint64_t)D; }
@@ -115,10 +143,25 @@ int encode_mfma_blocks_per_cu(bool aligned4);
 hipError_t launch_encode_planes(int field, const DevGen *gens, const DevTile *tiles, const unsigned *runs,
                                 const unsigned *bounds, int ntiles, unsigned *counters, int grid, hipStream_t s);
 int encode_planes_blocks_per_cu(int field);
+// Small-generation streaming form (every generation K <= 8 and N <= 8): wave
+// tiles of up to STREAM_STRIPS strips of 1 KiB, tables staged once per tile.
+constexpr int STREAM_MAX = 8;
+constexpr int STREAM_STRIPS = 64;
+void build_tiles_stream(const DevGen *g, size_t n, TileQueues &q);
+// sk: the batch's largest K or N (the kernel is instantiated for 1, 2, 4 and 8).
+hipError_t launch_encode_stream(int sk, const DevGen *gens, const DevTile *tiles, const unsigned *runs,
+                                const unsigned *bounds, int ntiles, unsigned *counters, int grid,
+                                const uint32_t *ptab_field, hipStream_t s);
+int encode_stream_blocks_per_cu(int sk);
 // One matrix (sys == nullptr: C, N, Cinv, rank) or `count` systems of one size
 // class (N <= 32, 64, 128 or 256; N names the class), one workgroup each.
 hipError_t launch_invert(const DevSys *sys, int count, const uint8_t *C, int N, uint8_t *Cinv, int *rank,
-                         const uint32_t *ptab_field, const uint8_t *inv_field, hipStream_t s);
+                         const uint32_t *ptab_field, const uint8_t *inv_field, hipStream_t s,
+                         const unsigned *d_count = nullptr);
+// Device-side set-up of the descriptor-driven batched calls (gf_sched.hip).
+hipError_t launch_bind_gens(const void *d_ext, const DevGen *shape, DevGen *out, int count, unsigned *err,
+                            const int *skip, hipStream_t s);
+hipError_t launch_dec_schedule(const void *d_sys, int count, const DecSched &w, hipStream_t s);
 int encode_blocks_per_cu();
 // One small generation in one launch (N, K <= 32, len <= 8192, rows 4-byte
 // aligned: align from row_align): Y = C S, or for a decode (K = N) S = C^-1 B
@@ -132,6 +175,9 @@ uint32_t row_align(const void *S, uint64_t ld_s, const void *Y, uint64_t ld_y);
 // Device tables of `field` on the current device (initialising it if needed).
 int gfnc_field_tables(int field, const uint32_t **ptab, const uint8_t **inv);
 const uint8_t *gfnc_field_rows(int field);
+// Instruction-mix microbenchmarks (gf_ceiling.hip): 0 device copy, 1 table
+// step, 2 FP4 MFMA, 3 bit-plane step.
+hipError_t launch_ceiling(int what, void *buf, uint64_t bytes, int blocks, int iters, hipStream_t s);
 hipError_t launch_absorb(const DevAbsorb *items, int n, const DevPacket *pkts, const uint32_t *ptab_field,
                          const uint8_t *inv_field, hipStream_t s);
 hipError_t launch_meta_init(int *const *metas, int n, hipStream_t s);

@@ -185,22 +185,13 @@ struct RegionDesc {
     uint32_t reserved;
 };
 
-constexpr int REGION_CHUNK = 256 * 16;   // bytes per block per region
-
-// Batched madd: block (bx, r) handles bytes [bx*REGION_CHUNK, ...) of region r.
-__global__ __launch_bounds__(256) void k_region_batched(const RegionDesc *__restrict__ regs,
-                                                        const uint4 *__restrict__ ptab4, int q)
+// One 16-byte piece of a batched region madd: piece v of region r.  Aligned
+// regions take one vector load of x and of y; others (and a region's last
+// partial piece) go byte by byte.
+__device__ __forceinline__ void region_piece(const RegionDesc &d, uint64_t p, const uint4 ta, uint32_t tb)
 {
-    const RegionDesc d = regs[blockIdx.y];
-    const uint64_t start = (uint64_t)blockIdx.x * REGION_CHUNK;
-    if (d.c == 0 || d.c >= (uint32_t)q || start >= d.len)
-        return;
-    const uint4 ta = ptab4[d.c * 2];
-    const uint32_t tb = ptab4[d.c * 2 + 1].x;
-    const uint64_t end = min(d.len, start + REGION_CHUNK);
-    const bool vec = (((uintptr_t)d.y | (uintptr_t)d.x) & 15u) == 0;
-    const uint64_t p = start + threadIdx.x * 16u;
-    if (vec && p + 16 <= end) {
+    const bool vec = ((((uintptr_t)d.y | (uintptr_t)d.x) & 15u) == 0) && p + 16 <= d.len;
+    if (vec) {
         const uint4 a = *reinterpret_cast<const uint4 *>(d.x + p);
         uint4 yv = *reinterpret_cast<const uint4 *>(d.y + p);
         yv.x ^= prod4(ta, tb, a.x);
@@ -208,10 +199,67 @@ __global__ __launch_bounds__(256) void k_region_batched(const RegionDesc *__rest
         yv.z ^= prod4(ta, tb, a.z);
         yv.w ^= prod4(ta, tb, a.w);
         *reinterpret_cast<uint4 *>(d.y + p) = yv;
-    } else if (p < end) {
-        for (uint64_t b = p; b < min(end, p + 16); b++)
+    } else {
+        const uint64_t end = min(d.len, p + 16);
+        for (uint64_t b = p; b < end; b++)
             d.y[b] ^= (uint8_t)(prod4(ta, tb, (uint32_t)d.x[b]) & 0xFFu);
     }
+}
+
+// Batched madd of regions shorter than 4 KiB over a flat index of 16-byte
+// pieces: piece f is piece f % vpr of region f / vpr, vpr = the pieces of the
+// longest region, so every lane of a wave has work while regions are about
+// that long (a 1500-byte region is 94 lanes, not a 256-thread block).  Each thread keeps two pieces in flight:
+// both descriptor loads, then both pieces' data.
+// f / d for f < 2^52 without an integer division: the double quotient is at
+// most one off, then corrected.
+__device__ __forceinline__ uint64_t div_small(uint64_t f, uint64_t d, double inv)
+{
+    uint64_t r = (uint64_t)((double)f * inv);
+    if (r * d > f)
+        r--;
+    else if ((r + 1) * d <= f)
+        r++;
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_region_batched(const RegionDesc *__restrict__ regs,
+                                                        const uint4 *__restrict__ ptab4, int q, uint64_t total,
+                                                        uint32_t vpr, double inv_vpr)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * 256u;
+    for (uint64_t f0 = (uint64_t)blockIdx.x * 256u + threadIdx.x; f0 < total; f0 += 2 * stride) {
+        const uint64_t f1 = f0 + stride;
+        const bool two = f1 < total;
+        const uint64_t r0 = div_small(f0, vpr, inv_vpr), r1 = two ? div_small(f1, vpr, inv_vpr) : r0;
+        const RegionDesc d0 = regs[r0];
+        const RegionDesc d1 = regs[r1];
+        const uint64_t p0 = (f0 - r0 * vpr) * 16u, p1 = (f1 - r1 * vpr) * 16u;
+        const bool w0 = d0.c != 0 && d0.c < (uint32_t)q && p0 < d0.len;
+        const bool w1 = two && d1.c != 0 && d1.c < (uint32_t)q && p1 < d1.len;
+        if (w0)
+            region_piece(d0, p0, ptab4[d0.c * 2], ptab4[d0.c * 2 + 1].x);
+        if (w1)
+            region_piece(d1, p1, ptab4[d1.c * 2], ptab4[d1.c * 2 + 1].x);
+    }
+}
+
+// Regions of 4 KiB and more: block (bx, r) handles bytes [bx*REGION_CHUNK, ...)
+// of region r, with the region's descriptor and tables loaded once per block.
+constexpr int REGION_CHUNK = 256 * 16;   // bytes per block per region
+
+__global__ __launch_bounds__(256) void k_region_chunks(const RegionDesc *__restrict__ regs,
+                                                       const uint4 *__restrict__ ptab4, int q)
+{
+    const RegionDesc d = regs[blockIdx.y];
+    const uint64_t start = (uint64_t)blockIdx.x * REGION_CHUNK;
+    if (d.c == 0 || d.c >= (uint32_t)q || start >= d.len)
+        return;
+    const uint4 ta = ptab4[d.c * 2];
+    const uint32_t tb = ptab4[d.c * 2 + 1].x;
+    const uint64_t p = start + threadIdx.x * 16u;
+    if (p < d.len)
+        region_piece(d, p, ta, tb);
 }
 
 // ------------------------------------------------------------------ encode
@@ -376,6 +424,151 @@ __device__ __forceinline__ void wave_tile(const uint8_t *__restrict__ C, int K, 
     for (int kk = 0; kk < KW; kk++)
         if (kk < kv)
             store_row<D>(Y + (uint64_t)(k0 + kk) * ld_y + p, avail, vec, acc[kk]);
+}
+
+// ----------------------------------------------------- small generations
+//
+// Batches whose generations all have K <= 8 coded rows and N <= 8 sources do
+// little arithmetic per byte (K byte-madds), so they are bound by memory
+// latency and bandwidth, not by the lookups.  A wave here takes a tile of up
+// to STREAM_STRIPS strips of 1 KiB (16 bytes per lane) of one generation,
+// stages the generation's K x N product tables in its LDS once, and streams
+// the strips through a software pipeline DEPTH strips deep: the loads of
+// strip s + DEPTH - 1 are issued before strip s is multiplied.  SK (the batch's
+// largest K or N, rounded up to 1, 2, 4 or 8) sizes the registers, and DEPTH
+// grows as SK shrinks, so every wave keeps about the same bytes in flight.
+
+template <int SK>
+struct SmallStage {
+    uint4 t[SK][SK][2];   // [coded row][source][tables]
+};
+
+// The N source dwords x 4 of one strip (zero past the packet or past N).
+template <int SK>
+__device__ __forceinline__ void small_load(const uint8_t *S, uint64_t ld_s, int N, uint64_t p, uint64_t len, bool vec,
+                                           uint32_t (&x)[SK][4])
+{
+    const uint64_t avail = p < len ? len - p : 0;
+#pragma unroll
+    for (int i = 0; i < SK; i++) {
+        if (i < N)
+            load_lane<4>(S + (uint64_t)i * ld_s + p, avail, vec, x[i]);
+        else
+#pragma unroll
+            for (int d = 0; d < 4; d++)
+                x[i][d] = 0;
+    }
+}
+
+// All K coded rows of one strip: the sources go two at a time (their byte
+// splits computed once), each pair multiplied into every row's accumulators.
+template <int SK>
+__device__ __forceinline__ void small_strip(const SmallStage<SK> &st, int K, int N, uint8_t *Y, uint64_t ld_y,
+                                            uint64_t p, uint64_t len, bool vec, const uint32_t (&x)[SK][4])
+{
+    const uint64_t avail = p < len ? len - p : 0;
+    if (avail == 0)
+        return;
+    uint32_t acc[SK][4];
+#pragma unroll
+    for (int k = 0; k < SK; k++)
+#pragma unroll
+        for (int d = 0; d < 4; d++)
+            acc[k][d] = 0;
+#pragma unroll
+    for (int i = 0; i < SK; i += 2) {
+        if (i >= N)
+            break;
+        const bool two = i + 1 < SK;
+        Sel sa[4], sb[4];
+#pragma unroll
+        for (int d = 0; d < 4; d++) {
+            sa[d] = split(x[i][d]);
+            sb[d] = split(two ? x[i + 1 < SK ? i + 1 : i][d] : 0u);   // zero past N, with zero tables
+        }
+#pragma unroll
+        for (int k = 0; k < SK; k++) {
+            if (k >= K)
+                break;
+            const uint4 a = st.t[k][i][0];
+            const uint32_t b = st.t[k][i][1].x;
+            const uint4 a2 = two ? st.t[k][i + 1 < SK ? i + 1 : i][0] : uint4{0, 0, 0, 0};
+            const uint32_t b2 = two ? st.t[k][i + 1 < SK ? i + 1 : i][1].x : 0u;
+#pragma unroll
+            for (int d = 0; d < 4; d++) {
+                const uint32_t p0 = __builtin_amdgcn_perm(a.y, a.x, sa[d].a);
+                const uint32_t p1 = __builtin_amdgcn_perm(a.w, a.z, sa[d].b);
+                const uint32_t p2 = __builtin_amdgcn_perm(b, b, sa[d].c);
+                if (two) {
+                    const uint32_t q0 = __builtin_amdgcn_perm(a2.y, a2.x, sb[d].a);
+                    const uint32_t q1 = __builtin_amdgcn_perm(a2.w, a2.z, sb[d].b);
+                    const uint32_t q2 = __builtin_amdgcn_perm(b2, b2, sb[d].c);
+                    acc[k][d] = xor3(xor3(xor3(acc[k][d], p0, p1), p2, q0), q1, q2);
+                } else {
+                    acc[k][d] = xor3(acc[k][d], p0, p1) ^ p2;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < SK; k++)
+        if (k < K)
+            store_row<4>(Y + (uint64_t)k * ld_y + p, avail, vec, acc[k]);
+}
+
+template <int SK, int DEPTH>
+__global__ __launch_bounds__(256) void k_encode_stream(const DevGen *__restrict__ gens,
+                                                       const DevTile *__restrict__ tiles,
+                                                       const unsigned *__restrict__ runs,
+                                                       const unsigned *__restrict__ bounds, unsigned *counters,
+                                                       const uint4 *__restrict__ ptab4)
+{
+    __shared__ SmallStage<SK> stage[WAVES];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    SmallStage<SK> &st = stage[wave];
+    QueueCursor cursor;
+    for (;;) {
+        int t = 0;
+        if (lane == 0)
+            t = queue_next_tile(counters, runs, bounds, cursor);
+        t = __builtin_amdgcn_readlane(t, 0);
+        if (t < 0)
+            break;
+        const DevTile tl = tiles[t];
+        const DevGen g = gens[tl.gen];
+        if (g.status && *g.status != g.need)
+            continue;
+        const int K = (int)g.K, N = (int)g.N, strips = (tl.D >> 8) + 1;
+        wave_sync();
+        if (lane < SK * SK) {   // tables of the K x N coefficients, one (row, source) pair per lane
+            const int k = lane / SK, i = lane % SK;
+            const uint32_t c = (k < K && i < N) ? (uint32_t)gld<uint8_t>(g.C + (uint64_t)k * N + i) : 0u;
+            st.t[k][i][0] = ptab4[c * 2];
+            st.t[k][i][1] = ptab4[c * 2 + 1];
+        }
+        wave_sync();
+        const bool vec = g.align >= 16;
+        const uint64_t p0 = tl.p0 + (uint64_t)lane * 16u;
+        uint32_t x[DEPTH][SK][4];
+#pragma unroll
+        for (int u = 0; u + 1 < DEPTH; u++)
+            if (u < strips)
+                small_load<SK>(g.S, g.ld_s, N, p0 + (uint64_t)u * 1024u, g.len, vec, x[u]);
+        for (int q = 0; q < strips; q += DEPTH) {
+#pragma unroll
+            for (int u = 0; u < DEPTH; u++) {
+                const int sidx = q + u;
+                if (sidx >= strips)
+                    break;
+                const int nxt = sidx + DEPTH - 1;
+                if (nxt < strips)
+                    small_load<SK>(g.S, g.ld_s, N, p0 + (uint64_t)nxt * 1024u, g.len, vec, x[(u + DEPTH - 1) % DEPTH]);
+                small_strip<SK>(st, K, N, g.Y, g.ld_y, p0 + (uint64_t)sidx * 1024u, g.len, vec, x[u]);
+            }
+        }
+    }
+    if (lane == 0)
+        queue_retire(counters, gridDim.x * WAVES);
 }
 
 // Single generation: wave w of block b takes tile b*WAVES + w; tiles run
@@ -884,11 +1077,16 @@ __global__ __launch_bounds__(256) void k_invert_one(const uint8_t *__restrict__ 
     invert_body<MAXN>(C, N, Cinv, rank, ptab4, invg);
 }
 
+// d_count (if not null): the number of systems in `sys`, known only on the
+// device; workgroups past it have nothing to do.
 template <int MAXN>
 __global__ __launch_bounds__(256) void k_invert_batched(const DevSys *__restrict__ sys,
                                                         const uint4 *__restrict__ ptab4,
-                                                        const uint8_t *__restrict__ invg)
+                                                        const uint8_t *__restrict__ invg,
+                                                        const unsigned *__restrict__ d_count)
 {
+    if (d_count && blockIdx.x >= *d_count)
+        return;
     const DevSys s = sys[blockIdx.x];
     if ((int)s.N > MAXN || (MAXN > 32 && (int)s.N <= MAXN / 2))
         return;   // handled by the launch of another size class
@@ -980,20 +1178,23 @@ __global__ __launch_bounds__(256) void k_small(const uint8_t *__restrict__ C, in
 
 // Progressive decoding of one generation (one workgroup per generation).
 // The innovative coefficient vectors received so far are kept in reduced row
-// echelon form R.  An arriving vector c is reduced against R in one pass:
-// since every row of R is zero in the other rows' pivot columns, subtracting
-// c[pivot(r)] * R[r] for all r at once clears every pivot column.  If nothing
-// is left the packet carried no new information.  Otherwise c is scaled to a
-// leading 1, its pivot column is cleared from the rows of R, and it is stored
-// with its raw coefficients and payload.  At rank N the completion step is
-// recorded; k_absorb_invert, launched next, inverts the raw coefficient
-// matrix (Gauss-Jordan, as in gf_invert), which releases the payload product
-// S = Csel^-1 * Bsel of the step.
+// echelon form R, together with the transform T that produced it from the
+// accepted packets' raw vectors Csel (R = T Csel; row j of T has weights on the
+// packets accepted so far).  An arriving vector c is reduced against R in one
+// pass: since every row of R is zero in the other rows' pivot columns,
+// subtracting c[pivot(r)] * R[r] for all r at once clears every pivot column,
+// and the same multiples of T's rows (plus the unit weight of the new packet)
+// give its transform row t.  If nothing is left of c the packet carried no new
+// information.  Otherwise c and t are scaled to a leading 1, c's pivot column
+// is cleared from R (T's rows take the same updates), and the payload is
+// stored.  At rank N, R is the identity with its rows in pivot order, so
+// row pivot(j) of Csel^-1 is row j of T: the kernel writes Csel^-1 directly and
+// the step's payload product S = Csel^-1 * Bsel needs no separate inversion.
 //
-// During a step R lives in LDS; packet descriptors are cached 64 at a time and the next packet's
+// During a step R and T live in LDS; packet descriptors are cached 64 at a time and the next packet's
 // coefficients are fetched while the current one is reduced, so the loop over
 // packets touches device memory only for those prefetches.  The innovative
-// packets' raw coefficients and payloads are copied out after the loop.
+// packets' payloads are copied out after the loop.
 constexpr int ABSORB_PKC = 64;
 // One workgroup per generation of 16 waves: the passes over R of each packet
 // split its rows 16 ways (a step has at most a few dozen such workgroups, so
@@ -1005,14 +1206,14 @@ __global__ __launch_bounds__(ABSORB_THREADS) void k_absorb(const DevAbsorb *__re
                                                 const uint8_t *__restrict__ invg)
 {
     __shared__ uint32_t Rl[256 * 65];   // row r at Rl + 65 r (odd stride)
-    __shared__ uint32_t cw[64];
-    __shared__ uint32_t part[ABSORB_WAVES][64];
-    __shared__ uint4 T[256][2];
+    __shared__ uint32_t Tl[256 * 65];   // transform rows, the same layout
+    __shared__ uint32_t cw[64], tw[64];
+    __shared__ uint32_t part[ABSORB_WAVES][64], tpart[ABSORB_WAVES][64];
+    __shared__ uint4 TB[256][2];
     __shared__ uint8_t IV[256];
     __shared__ uint8_t fcol[256];
     __shared__ int pivc[256];
-    __shared__ const uint8_t *row_coef[256];   // raw coefficients of the rows added in this step
-    __shared__ const uint8_t *row_pay[256];
+    __shared__ const uint8_t *row_pay[256];   // payloads of the rows added in this step
     __shared__ DevPacket pkc[ABSORB_PKC];
     __shared__ int cand[4];
     const DevAbsorb it = items[blockIdx.x];
@@ -1020,13 +1221,14 @@ __global__ __launch_bounds__(ABSORB_THREADS) void k_absorb(const DevAbsorb *__re
     const int N = (int)s.N, NW = (N + 3) >> 2;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint8_t *Rb = reinterpret_cast<const uint8_t *>(Rl);   // row r at byte 260 r
+    const uint8_t *Tb = reinterpret_cast<const uint8_t *>(Tl);
 
     int rank = s.meta[0];
     if (rank >= N || N > 256)
         return;
     const int rank0 = rank;
     for (int i = tid; i < 512; i += ABSORB_THREADS)
-        T[i >> 1][i & 1] = ptab4[i];
+        TB[i >> 1][i & 1] = ptab4[i];
     if (tid < 256)
         IV[tid] = invg[tid];
     for (int i = tid; i < rank; i += ABSORB_THREADS)
@@ -1034,6 +1236,7 @@ __global__ __launch_bounds__(ABSORB_THREADS) void k_absorb(const DevAbsorb *__re
     for (int i = tid; i < rank * NW; i += ABSORB_THREADS) {
         const int r = i / NW, w = i - r * NW;
         Rl[r * 65 + w] = reinterpret_cast<const uint32_t *>(s.R + (uint64_t)r * s.rs)[w];
+        Tl[r * 65 + w] = reinterpret_cast<const uint32_t *>(s.T + (uint64_t)r * s.rs)[w];
     }
     // coefficient dword tid of a packet (lanes tid < NW)
     auto coef_dword = [&](const uint8_t *c) {
@@ -1068,22 +1271,29 @@ __global__ __launch_bounds__(ABSORB_THREADS) void k_absorb(const DevAbsorb *__re
             fcol[r] = (uint8_t)(cw[pc >> 2] >> (8 * (pc & 3)));
         }
         __syncthreads();
-        if (lane < NW) {   // wave w sums rows w, w + W, ... of column dword `lane`
-            uint32_t acc = 0;
+        if (lane < NW) {   // wave w sums rows w, w + W, ... of column dword `lane`, in R and in T
+            uint32_t acc = 0, tacc = 0;
 #pragma unroll 4
             for (int r = wave; r < rank; r += ABSORB_WAVES) {   // a zero factor adds a zero product
                 const uint32_t f = fcol[r];
-                acc ^= prod4(T[f][0], T[f][1].x, Rl[r * 65 + lane]);
+                acc ^= prod4(TB[f][0], TB[f][1].x, Rl[r * 65 + lane]);
+                tacc ^= prod4(TB[f][0], TB[f][1].x, Tl[r * 65 + lane]);
             }
             part[wave][lane] = acc;
+            tpart[wave][lane] = tacc;
         }
         __syncthreads();
         if (tid < NW) {
-            uint32_t x = cw[tid];
+            uint32_t x = cw[tid], t = 0;
 #pragma unroll
-            for (int w = 0; w < ABSORB_WAVES; w++)
+            for (int w = 0; w < ABSORB_WAVES; w++) {
                 x ^= part[w][tid];
+                t ^= tpart[w][tid];
+            }
+            if (tid == (rank >> 2))
+                t ^= 1u << (8 * (rank & 3));   // the new packet's own unit weight
             cw[tid] = x;
+            tw[tid] = t;
         }
         __syncthreads();
         const bool nz = tid < N && ((cw[tid >> 2] >> (8 * (tid & 3))) & 0xFFu) != 0;
@@ -1101,38 +1311,39 @@ __global__ __launch_bounds__(ABSORB_THREADS) void k_absorb(const DevAbsorb *__re
         if (tid < NW) {   // wave 0 reads the leading entry before any lane rewrites it
             const uint32_t lv = (cw[lead >> 2] >> (8 * (lead & 3))) & 0xFFu;
             const uint32_t iv = IV[lv];
-            cw[tid] = prod4(T[iv][0], T[iv][1].x, cw[tid]);
+            cw[tid] = prod4(TB[iv][0], TB[iv][1].x, cw[tid]);
+            tw[tid] = prod4(TB[iv][0], TB[iv][1].x, tw[tid]);
         }
         for (int r = tid; r < rank; r += ABSORB_THREADS)
             fcol[r] = Rb[r * 260 + lead];
         __syncthreads();
-        if (lane < NW) {   // wave w clears the new pivot column from rows w, w + W, ...
-            const uint32_t c = cw[lane];
+        if (lane < NW) {   // wave w clears the new pivot column from rows w, w + W, ... (T alike)
+            const uint32_t c = cw[lane], t = tw[lane];
 #pragma unroll 4
             for (int r = wave; r < rank; r += ABSORB_WAVES) {
                 const uint32_t f = fcol[r];
-                Rl[r * 65 + lane] ^= prod4(T[f][0], T[f][1].x, c);
+                Rl[r * 65 + lane] ^= prod4(TB[f][0], TB[f][1].x, c);
+                Tl[r * 65 + lane] ^= prod4(TB[f][0], TB[f][1].x, t);
             }
         }
-        if (tid < NW)
+        if (tid < NW) {
             Rl[rank * 65 + tid] = cw[tid];
+            Tl[rank * 65 + tid] = tw[tid];
+        }
         if (tid == 0) {
             pivc[rank] = lead;
-            row_coef[rank] = pk.coef;
             row_pay[rank] = pk.payload;
         }
         rank++;
         __syncthreads();
     }
-    // R back to device memory; the new rows' raw coefficients and payloads
+    // R and T back to device memory; the new rows' payloads
     for (int i = tid; i < rank * NW; i += ABSORB_THREADS) {
         const int r = i / NW, w = i - r * NW;
         reinterpret_cast<uint32_t *>(s.R + (uint64_t)r * s.rs)[w] = Rl[r * 65 + w];
+        reinterpret_cast<uint32_t *>(s.T + (uint64_t)r * s.rs)[w] = Tl[r * 65 + w];
     }
     for (int rr = rank0; rr < rank; rr++) {
-        const uint8_t *pc = row_coef[rr];
-        for (int b = tid; b < N; b += ABSORB_THREADS)
-            s.Csel[(uint64_t)rr * N + b] = pc[b];
         const uint8_t *src = row_pay[rr];
         uint8_t *dst = s.Bsel + (uint64_t)rr * s.ld;
         if (((((uintptr_t)dst) | ((uintptr_t)src)) & 3u) == 0) {
@@ -1148,32 +1359,19 @@ __global__ __launch_bounds__(ABSORB_THREADS) void k_absorb(const DevAbsorb *__re
     }
     for (int i = tid; i < rank; i += ABSORB_THREADS)
         s.meta[4 + i] = pivc[i];
+    if (rank == N) {   // complete: row pivot(j) of Csel^-1 is row j of T
+        for (int i = tid; i < N * N; i += ABSORB_THREADS) {
+            const int j = i / N, b = i - j * N;
+            s.Cinv[(uint64_t)pivc[j] * N + b] = Tb[j * 260 + b];
+        }
+    }
     if (tid == 0) {
         s.meta[0] = rank;
         s.meta[2] += seen;
         s.meta[3] += dropped;
+        if (rank == N)
+            s.meta[1] = it.step;   // releases the step's payload product for this generation
     }
-    // complete: k_absorb_invert (launched next) inverts Csel before the step's product
-    if (rank == N && tid == 0)
-        s.meta[1] = it.step;
-}
-
-// The generations that reached full rank in this step: Cinv = Csel^-1 on 1024
-// threads (the pivot steps are latency-bound; four times the waves of the
-// absorb workgroup hide more of it).  Csel holds the innovative coefficient
-// vectors, so it is invertible.
-__global__ __launch_bounds__(1024) void k_absorb_invert(const DevAbsorb *__restrict__ items,
-                                                        const uint4 *__restrict__ ptab4,
-                                                        const uint8_t *__restrict__ invg)
-{
-    __shared__ uint32_t A[256 * 65];
-    __shared__ int inv_rank;
-    const DevAbsorb it = items[blockIdx.x];
-    const DevDecSlot &s = it.s;
-    const int N = (int)s.N;
-    if (N > 256 || s.meta[0] != N || s.meta[1] != it.step)
-        return;
-    invert_rows<256, 1024>(A, [&](int r) { return s.Csel + (uint64_t)r * N; }, N, s.Cinv, &inv_rank, ptab4, invg);
 }
 
 __global__ void k_meta_init(int *const *__restrict__ metas, int n)
@@ -1225,18 +1423,34 @@ hipError_t launch_region_batched(const void *d_regions, int count, uint64_t max_
 {
     if (count <= 0 || max_len == 0)
         return hipSuccess;
-    const uint64_t gx = (max_len + REGION_CHUNK - 1) / REGION_CHUNK;
-    // grid.y is limited to 65535: split the region list into slices
-    for (int base = 0; base < count; base += 65535) {
-        const int n = min(65535, count - base);
-        hipLaunchKernelGGL(k_region_batched, dim3((unsigned)gx, (unsigned)n), dim3(256), 0, s,
-                           reinterpret_cast<const RegionDesc *>(d_regions) + base,
-                           reinterpret_cast<const uint4 *>(ptab_field), q);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess)
-            return e;
+    if (max_len >= REGION_CHUNK) {
+        // long regions: a block per 4 KiB chunk keeps the descriptor and tables uniform
+        const uint64_t gx = (max_len + REGION_CHUNK - 1) / REGION_CHUNK;
+        if (gx > 0x7FFFFFFFull)
+            return hipErrorInvalidValue;
+        for (int base = 0; base < count; base += 65535) {   // grid.y is limited to 65535
+            const int n = min(65535, count - base);
+            hipLaunchKernelGGL(k_region_chunks, dim3((unsigned)gx, (unsigned)n), dim3(256), 0, s,
+                               reinterpret_cast<const RegionDesc *>(d_regions) + base,
+                               reinterpret_cast<const uint4 *>(ptab_field), q);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess)
+                return e;
+        }
+        return hipSuccess;
     }
-    return hipSuccess;
+    const uint64_t vpr = (max_len + 15) / 16;
+    const uint64_t total = vpr * (uint64_t)count;
+    if (total >= (1ull << 52))
+        return hipErrorInvalidValue;
+    // enough workgroups to keep every CU's waves busy; each thread then walks
+    // its pieces two at a time
+    const uint64_t want = (total + 511) / 512;
+    const unsigned blocks = (unsigned)std::min<uint64_t>(std::max<uint64_t>(want, 1), 256ull * 32);
+    hipLaunchKernelGGL(k_region_batched, dim3(blocks), dim3(256), 0, s,
+                       reinterpret_cast<const RegionDesc *>(d_regions), reinterpret_cast<const uint4 *>(ptab_field), q,
+                       total, (uint32_t)vpr, 1.0 / (double)vpr);
+    return hipGetLastError();
 }
 
 hipError_t launch_encode(int D, int nsplit, const uint8_t *C, int K, int N, const uint8_t *S, uint64_t ld_s,
@@ -1326,6 +1540,46 @@ hipError_t launch_encode_planes(int field, const DevGen *gens, const DevTile *ti
     return hipGetLastError();
 }
 
+// The streaming kernel for the batch's largest K or N (sk = 1, 2, 4 or 8).
+static const void *stream_kernel(int sk)
+{
+    return sk <= 1   ? reinterpret_cast<const void *>(&k_encode_stream<1, 8>)
+           : sk <= 2 ? reinterpret_cast<const void *>(&k_encode_stream<2, 6>)
+           : sk <= 4 ? reinterpret_cast<const void *>(&k_encode_stream<4, 4>)
+                     : reinterpret_cast<const void *>(&k_encode_stream<8, 2>);
+}
+
+hipError_t launch_encode_stream(int sk, const DevGen *gens, const DevTile *tiles, const unsigned *runs,
+                                const unsigned *bounds, int ntiles, unsigned *counters, int grid,
+                                const uint32_t *ptab_field, hipStream_t s)
+{
+    if (ntiles <= 0)
+        return hipSuccess;
+    const uint4 *pt = reinterpret_cast<const uint4 *>(ptab_field);
+    if (sk <= 1)
+        hipLaunchKernelGGL((k_encode_stream<1, 8>), dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters, pt);
+    else if (sk <= 2)
+        hipLaunchKernelGGL((k_encode_stream<2, 6>), dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters, pt);
+    else if (sk <= 4)
+        hipLaunchKernelGGL((k_encode_stream<4, 4>), dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters, pt);
+    else
+        hipLaunchKernelGGL((k_encode_stream<8, 2>), dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters, pt);
+    return hipGetLastError();
+}
+
+int encode_stream_blocks_per_cu(int sk)
+{
+    static int cached[4] = {0, 0, 0, 0};
+    const int ix = sk <= 1 ? 0 : sk <= 2 ? 1 : sk <= 4 ? 2 : 3;
+    if (cached[ix] > 0)
+        return cached[ix];
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stream_kernel(sk), 256, 0) != hipSuccess || nb < 1)
+        return 1;
+    cached[ix] = nb;
+    return nb;
+}
+
 int encode_planes_blocks_per_cu(int field)
 {
     const void *k = field == 1   ? reinterpret_cast<const void *>(&k_encode_planes<1>)
@@ -1348,7 +1602,8 @@ int encode_blocks_per_cu()
 }
 
 hipError_t launch_invert(const DevSys *sys, int count, const uint8_t *C, int N, uint8_t *Cinv, int *rank,
-                         const uint32_t *ptab_field, const uint8_t *inv_field, hipStream_t s)
+                         const uint32_t *ptab_field, const uint8_t *inv_field, hipStream_t s,
+                         const unsigned *d_count)
 {
     const uint4 *pt = reinterpret_cast<const uint4 *>(ptab_field);
     if (sys == nullptr) {
@@ -1366,13 +1621,13 @@ hipError_t launch_invert(const DevSys *sys, int count, const uint8_t *C, int N, 
         return hipSuccess;
     // `sys` holds systems of one size class (the class of N); a block skips any other.
     if (N <= 32)
-        hipLaunchKernelGGL(k_invert_batched<32>, dim3(count), dim3(256), 0, s, sys, pt, inv_field);
+        hipLaunchKernelGGL(k_invert_batched<32>, dim3(count), dim3(256), 0, s, sys, pt, inv_field, d_count);
     else if (N <= 64)
-        hipLaunchKernelGGL(k_invert_batched<64>, dim3(count), dim3(256), 0, s, sys, pt, inv_field);
+        hipLaunchKernelGGL(k_invert_batched<64>, dim3(count), dim3(256), 0, s, sys, pt, inv_field, d_count);
     else if (N <= 128)
-        hipLaunchKernelGGL(k_invert_batched<128>, dim3(count), dim3(256), 0, s, sys, pt, inv_field);
+        hipLaunchKernelGGL(k_invert_batched<128>, dim3(count), dim3(256), 0, s, sys, pt, inv_field, d_count);
     else
-        hipLaunchKernelGGL(k_invert_batched<256>, dim3(count), dim3(256), 0, s, sys, pt, inv_field);
+        hipLaunchKernelGGL(k_invert_batched<256>, dim3(count), dim3(256), 0, s, sys, pt, inv_field, d_count);
     return hipGetLastError();
 }
 
@@ -1383,8 +1638,6 @@ hipError_t launch_absorb(const DevAbsorb *items, int n, const DevPacket *pkts, c
         return hipSuccess;
     hipLaunchKernelGGL(k_absorb, dim3(n), dim3(ABSORB_THREADS), 0, s, items, pkts,
                        reinterpret_cast<const uint4 *>(ptab_field), inv_field);
-    hipLaunchKernelGGL(k_absorb_invert, dim3(n), dim3(1024), 0, s, items, reinterpret_cast<const uint4 *>(ptab_field),
-                       inv_field);
     return hipGetLastError();
 }
 

@@ -395,12 +395,13 @@ __device__ __forceinline__ void mf_mma(const MfOperands &o, gf_v16f (&acc)[4][2]
 
 constexpr int kMfRestart = 2048;
 
-// Instruction order for the last six products of a step and the unpacking of
+// Instruction order for the last NM products of a step and the unpacking of
 // the next step's operands, one MFMA after every six vector instructions.
+template <int NM>
 __device__ __forceinline__ void mf_step_schedule()
 {
 #pragma unroll
-    for (int i = 0; i < 6; i++) {
+    for (int i = 0; i < NM; i++) {
         __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);   // VALU
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
     }
@@ -530,6 +531,11 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
             uint32_t s[4];   // columns 2r, 2r + 1 of source rows 0..3 (one 16-bit read each)
             uint32_t y[4];
         };
+        // A tile's last 16 coded rows may be fewer: only the row tiles (of 4
+        // packets) that hold rows of the generation are multiplied (RTS).
+        const int rts = min(4, ((int)g.K - k0 + 3) >> 2);
+        auto run_tile = [&](auto rts_c) {
+        constexpr int RTS = decltype(rts_c)::value;
         auto fetch_issue = [&](int zf, int ksf, auto wait_imm) {
             __builtin_amdgcn_s_waitcnt(decltype(wait_imm)::value);
             asm volatile("" ::: "memory");
@@ -539,7 +545,7 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
             for (int q = 0; q < 4; q++)
                 w.s[q] = rows[q * 32 + r];
 #pragma unroll
-            for (int rt = 0; rt < 4; rt++)
+            for (int rt = 0; rt < RTS; rt++)
                 w.y[rt] = Ybuf[ksf][rt][lane];
             return w;
         };
@@ -549,7 +555,7 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
             o.b[0] = fp4_source(__builtin_amdgcn_perm(t23, t01, 0x05040100u));   // column 2r of rows 0..3
             o.b[1] = fp4_source(__builtin_amdgcn_perm(t23, t01, 0x07060302u));   // column 2r + 1
 #pragma unroll
-            for (int rt = 0; rt < 4; rt++)
+            for (int rt = 0; rt < RTS; rt++)
                 o.a[rt] = fp4_coef(w.y[rt]);
         };
         // One step: the next operands are read and unpacked while this step's
@@ -557,15 +563,24 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
         // products next, so the wait for the reads (the reads are kept as four
         // separate words, since packing them would need their values at once)
         // sits behind two MFMAs instead of in front of them.
-        auto step = [&](int zn, int ksn, const MfOperands &cur, MfOperands &nxt, auto wait_imm) {
+        // MMA false: this step's sources are the zero group that pads an odd
+        // group count, so only the next operands are fetched.
+        auto step = [&](int zn, int ksn, const MfOperands &cur, MfOperands &nxt, auto wait_imm, auto mma_c) {
             const Raw w = fetch_issue(zn, ksn, wait_imm);
-            __builtin_amdgcn_sched_barrier(0);
-            mf_mma<0, 1>(cur, acc);
-            __builtin_amdgcn_sched_barrier(0);
-            fetch_unpack(w, nxt);
-            mf_mma<1, 4>(cur, acc);
-            mf_step_schedule();
+            if constexpr (decltype(mma_c)::value) {
+                __builtin_amdgcn_sched_barrier(0);
+                mf_mma<0, 1>(cur, acc);
+                __builtin_amdgcn_sched_barrier(0);
+                fetch_unpack(w, nxt);
+                mf_mma<1, RTS>(cur, acc);
+                mf_step_schedule<2 * RTS - 2>();
+            } else {
+                fetch_unpack(w, nxt);
+            }
         };
+        using Mma = std::true_type;
+        using NoMma = std::false_type;
+        const bool odd_groups = ((N + 7) >> 3) & 1;   // the last step of each strip multiplies zeros
 
         // Before the pair starting at step z = 2q, copies are issued through
         // pair q + MF_PAIRS_AHEAD - 1.  Reading step 2q + 1 (after this pair's
@@ -584,11 +599,19 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
         uint32_t prev[4] = {0u, 0u, 0u, 0u};
         int z = 0;
         for (int strip = 0; strip < nstrips; strip++) {
-            for (int kp = 0; kp < npairs; kp++, z += 2) {
+            for (int kp = 0; kp + 1 < npairs; kp++, z += 2) {
                 copy_pair();              // pair q + MF_PAIRS_AHEAD, into the slots of pair q - 1
-                step(z + 1, 2 * kp + 1, opa, opb, WaitOdd{});
-                step(z + 2, kp + 1 == npairs ? 0 : 2 * kp + 2, opb, opa, WaitEven{});   // past the end: a zero slot
+                step(z + 1, 2 * kp + 1, opa, opb, WaitOdd{}, Mma{});
+                step(z + 2, 2 * kp + 2, opb, opa, WaitEven{}, Mma{});
             }
+            // the strip's last pair; its second step fetches the next strip's first (past the end: a zero slot)
+            copy_pair();
+            step(z + 1, nks - 1, opa, opb, WaitOdd{}, Mma{});
+            if (odd_groups)
+                step(z + 2, 0, opb, opa, WaitEven{}, NoMma{});
+            else
+                step(z + 2, 0, opb, opa, WaitEven{}, Mma{});
+            z += 2;
             mf_store<true>(g, k0, (uint64_t)strip * MF_STRIP + (uint64_t)wave * 64u + 2u * (uint64_t)r, acc, h,
                            prev, y_even && (uint64_t)(strip + 1) * MF_STRIP <= g.len);
             if ((strip & (kMfRestart - 1)) == kMfRestart - 1) {
@@ -598,6 +621,15 @@ __global__ __launch_bounds__(256, GF_MF_WAVES_PER_SIMD) void k_encode_mfma_dma(c
                     prev[i] = 0u;
             }
         }
+        };
+        if (rts >= 4)
+            run_tile(std::integral_constant<int, 4>{});
+        else if (rts == 3)
+            run_tile(std::integral_constant<int, 3>{});
+        else if (rts == 2)
+            run_tile(std::integral_constant<int, 2>{});
+        else
+            run_tile(std::integral_constant<int, 1>{});
         // the copies past the last step land before the slots are reused
         __builtin_amdgcn_s_waitcnt(kWaitAll);
         __syncthreads();   // every wave is done with Cl and Ybuf before the next tile
@@ -627,13 +659,17 @@ hipError_t launch_encode_mfma(const DevGen *gens, const DevTile *tiles, const un
 
 int encode_mfma_blocks_per_cu(bool aligned4)
 {
-    int nb = 0;
+    // the same for every gfx950 device; asked once (launches may be under graph capture)
+    static int cached[2] = {0, 0};
+    int &nb = cached[aligned4 ? 1 : 0];
+    if (nb > 0)
+        return nb;
+    int v = 0;
     const void *k = aligned4 ? reinterpret_cast<const void *>(&k_encode_mfma_dma)
                               : reinterpret_cast<const void *>(&k_encode_mfma);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, 0) !=
-            hipSuccess ||
-        nb < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k, 256, 0) != hipSuccess || v < 1)
         return 1;
+    nb = v;
     return nb;
 }
 

@@ -30,6 +30,7 @@ __device__ __forceinline__ int queue_take_run(unsigned *counters, const unsigned
 }
 
 // Tile cursor of a claimant: the rest of its current run, then the next run.
+// runs == nullptr means every run is one tile (run r is tile r).
 struct QueueCursor {
     int q = 0;
     unsigned next = 0, end = 0;
@@ -42,8 +43,8 @@ __device__ __forceinline__ int queue_next_tile(unsigned *counters, const unsigne
         const int r = queue_take_run(counters, bounds, c.q);
         if (r < 0)
             return -1;
-        c.next = runs[r];
-        c.end = runs[r + 1];
+        c.next = runs ? runs[r] : (unsigned)r;
+        c.end = runs ? runs[r + 1] : (unsigned)r + 1;
     }
     return (int)c.next++;
 }

@@ -97,7 +97,9 @@ struct Req {
     const uint8_t *C = nullptr, *S = nullptr;
     uint64_t ld_s = 0;
     int state = QUEUED;
-    bool launched = false, polled = false, release_asked = false;
+    int status = GF_OK;       // GF_ECANCELED once cancelled
+    bool launched = false, polled = false, release_asked = false, cancel = false;
+    std::vector<hipEvent_t> copies;   // recorded after each copy_out on the caller's stream
     uint64_t off = 0, bytes = 0;
     uint8_t *out = nullptr;
     DevDecSlot slot{};
@@ -155,7 +157,7 @@ uint64_t footprint(const Req &r)
     if (r.kind == 0)
         return round_up((uint64_t)r.K * r.ld, kAlign);
     const uint64_t N = (uint64_t)r.N, rs = round_up(N, 4);
-    return round_up(N * rs, kAlign) + 2 * round_up(N * N, kAlign) + 2 * round_up(N * r.ld, kAlign) +
+    return 2 * round_up(N * rs, kAlign) + round_up(N * N, kAlign) + 2 * round_up(N * r.ld, kAlign) +
            round_up((4 + N) * sizeof(int), kAlign);
 }
 
@@ -170,8 +172,8 @@ void layout(gf_server *sv, Req &r)
     DevDecSlot &s = r.slot;
     s.R = p;
     p += round_up(N * rs, kAlign);
-    s.Csel = p;
-    p += round_up(N * N, kAlign);
+    s.T = p;
+    p += round_up(N * rs, kAlign);
     s.Cinv = p;
     p += round_up(N * N, kAlign);
     s.Bsel = p;
@@ -185,11 +187,27 @@ void layout(gf_server *sv, Req &r)
     s.rs = (uint32_t)rs;
 }
 
+// True once every copy_out of the request (on the callers' streams) has run.
+bool copies_done(Req *r)
+{
+    while (!r->copies.empty()) {
+        const hipError_t q = hipEventQuery(r->copies.back());
+        if (q == hipErrorNotReady)
+            return false;
+        (void)hipEventDestroy(r->copies.back());   // finished (or failed: nothing left to wait for)
+        r->copies.pop_back();
+    }
+    return true;
+}
+
+// Return released requests' memory once no step in flight refers to it and
+// their copies out have completed, so a later request can never overwrite
+// bytes a copy still reads.
 void free_ready(gf_server *sv, int64_t completed_step)
 {
     std::vector<Req *> keep;
     for (Req *r : sv->to_free) {
-        if (r->last_step <= completed_step) {
+        if (r->last_step <= completed_step && copies_done(r)) {
             if (r->bytes)
                 sv->arena.release(r->off, r->bytes);
             sv->reqs.erase(r->id);
@@ -201,11 +219,18 @@ void free_ready(gf_server *sv, int64_t completed_step)
     sv->to_free.swap(keep);
 }
 
-void finish(gf_server *sv, Req *r, double now)
+// The last step whose kernels have all completed.
+int64_t retired_step(const gf_server *sv)
+{
+    return sv->inflight.empty() ? sv->next_step - 1 : sv->inflight.front().step - 1;
+}
+
+void finish(gf_server *sv, Req *r, double now, int status = GF_OK)
 {
     if (r->state == DONE)
         return;
     r->state = DONE;
+    r->status = status;
     r->t_done = now;
     sv->active.erase(std::remove(sv->active.begin(), sv->active.end(), r), sv->active.end());
     sv->done_fifo.push_back(r);
@@ -240,6 +265,8 @@ void retire(gf_server *sv, double now)
         r->dropped = dropped;
         if (done_step >= 0)
             finish(sv, r, now);
+        else if (r->cancel && r->last_step <= f.step)
+            finish(sv, r, now, GF_ECANCELED);
     }
     free_ready(sv, f.step);
 }
@@ -382,6 +409,9 @@ void gf_serve_destroy(gf_server *sv)
     if (!sv->cfg.dry_run) {
         if (sv->stream)
             (void)hipStreamSynchronize(sv->stream);
+        for (auto &kv : sv->reqs)   // copies out still reading the arena
+            for (hipEvent_t ev : kv.second->copies)
+                (void)hipEventSynchronize(ev);
         for (StepBuf &b : sv->bufs) {
             if (b.host)
                 (void)hipHostFree(b.host);
@@ -399,8 +429,11 @@ void gf_serve_destroy(gf_server *sv)
         (void)hipFree(sv->ctr);
         (void)hipFree(sv->base);
     }
-    for (auto &kv : sv->reqs)
+    for (auto &kv : sv->reqs) {
+        for (hipEvent_t ev : kv.second->copies)
+            (void)hipEventDestroy(ev);
         delete kv.second;
+    }
     delete sv;
 }
 
@@ -476,7 +509,7 @@ int gf_serve_push_packet(gf_server *sv, uint64_t id, const uint8_t *coef, const 
     if (sv->err)
         return sv->err;
     auto it = sv->reqs.find(id);
-    if (it == sv->reqs.end() || it->second->kind != 1 || it->second->state == DONE)
+    if (it == sv->reqs.end() || it->second->kind != 1 || it->second->state == DONE || it->second->cancel)
         return GF_EINVAL;
     Req *r = it->second;
     // keep the queue ordered by release time (stable for equal times)
@@ -514,6 +547,7 @@ int gf_serve_step(gf_server *sv, double now)
     int rc = collect(sv, now, true);
     if (rc)
         return fail(sv, rc);
+    free_ready(sv, retired_step(sv));
 
     // admission: FIFO, stop at the first request that does not fit
     std::vector<Req *> admitted;
@@ -553,6 +587,8 @@ int gf_serve_step(gf_server *sv, double now)
             f.enc.push_back(r);
             continue;
         }
+        if (r->cancel)
+            continue;
         uint32_t n = 0;
         const uint32_t first = (uint32_t)pk.size();
         while (!r->pkts.empty() && (int)n < sv->cfg.burst && r->pkts.front().release <= now) {
@@ -671,7 +707,7 @@ int gf_serve_poll(gf_server *sv, gf_serve_done *out, int max)
         gf_serve_done &d = out[n++];
         d.id = r->id;
         d.kind = r->kind;
-        d.status = GF_OK;
+        d.status = r->status;
         d.rank = r->kind == 1 ? r->rank : r->K;
         d.packets_seen = r->seen;
         d.packets_dropped = r->dropped;
@@ -694,7 +730,48 @@ int gf_serve_release(gf_server *sv, uint64_t id)
         return GF_EINVAL;
     it->second->release_asked = true;
     sv->to_free.push_back(it->second);
-    free_ready(sv, sv->inflight.empty() ? sv->next_step : sv->inflight.front().step - 1);
+    free_ready(sv, retired_step(sv));
+    return GF_OK;
+}
+
+int gf_serve_query(gf_server *sv, uint64_t id, gf_serve_status *out)
+{
+    if (!sv || !out)
+        return GF_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(id);
+    if (it == sv->reqs.end() || it->second->release_asked)
+        return GF_EINVAL;
+    const Req *r = it->second;
+    out->state = r->state;
+    out->rank = r->kind == 1 ? r->rank : (r->state == DONE ? r->K : 0);
+    out->packets_pending = (int)r->pkts.size();
+    out->packets_seen = r->seen;
+    out->packets_dropped = r->dropped;
+    return GF_OK;
+}
+
+int gf_serve_cancel(gf_server *sv, uint64_t id, double now)
+{
+    if (!sv)
+        return GF_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(id);
+    if (it == sv->reqs.end() || it->second->state == DONE || it->second->cancel)
+        return GF_EINVAL;
+    Req *r = it->second;
+    if (r->state == QUEUED) {
+        sv->queue.erase(std::remove(sv->queue.begin(), sv->queue.end(), r), sv->queue.end());
+        r->state = ACTIVE;   // finish() moves it to the completed list
+        finish(sv, r, now, GF_ECANCELED);
+        return GF_OK;
+    }
+    if (r->kind == 0)
+        return GF_EINVAL;    // an admitted encode is already in a step: it completes there
+    r->cancel = true;
+    r->pkts.clear();
+    if (r->last_step <= retired_step(sv))
+        finish(sv, r, now, GF_ECANCELED);   // no step in flight refers to it
     return GF_OK;
 }
 
@@ -704,19 +781,28 @@ int gf_serve_copy_out(gf_server *sv, uint64_t id, uint8_t *dst, size_t ld_dst, v
         return GF_EINVAL;
     std::lock_guard<std::mutex> lk(sv->mu);
     auto it = sv->reqs.find(id);
-    if (it == sv->reqs.end() || it->second->state != DONE || it->second->release_asked)
+    if (it == sv->reqs.end() || it->second->state != DONE || it->second->status != GF_OK ||
+        it->second->release_asked)
         return GF_EINVAL;
-    const Req *r = it->second;
+    Req *r = it->second;
     const size_t rows = (size_t)(r->kind == 0 ? r->K : r->N);
     if (rows > 1 && ld_dst < r->len)
         return GF_EINVAL;
     if (sv->cfg.dry_run)
         return GF_OK;
     // the step that produced the output has retired, so the copy only needs
-    // to follow the caller's own work
-    if (hipMemcpy2DAsync(dst, rows > 1 ? ld_dst : r->len, r->out, r->ld, r->len, rows, hipMemcpyDeviceToDevice,
-                         (hipStream_t)stream) != hipSuccess)
+    // to follow the caller's own work; the event after it keeps the memory
+    // from being reused (after gf_serve_release) until the copy has run
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
         return GF_EDEVICE;
+    if (hipMemcpy2DAsync(dst, rows > 1 ? ld_dst : r->len, r->out, r->ld, r->len, rows, hipMemcpyDeviceToDevice,
+                         (hipStream_t)stream) != hipSuccess ||
+        hipEventRecord(ev, (hipStream_t)stream) != hipSuccess) {
+        (void)hipEventDestroy(ev);
+        return GF_EDEVICE;
+    }
+    r->copies.push_back(ev);
     return GF_OK;
 }
 
@@ -732,6 +818,7 @@ int gf_serve_drain(gf_server *sv, double now)
             return fail(sv, GF_EDEVICE);
         retire(sv, now);
     }
+    free_ready(sv, retired_step(sv));
     return GF_OK;
 }
 

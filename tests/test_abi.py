@@ -124,10 +124,36 @@ def test_plan_argument_checks():
     assert L.gf_plan_encode(8, bad, 1, None, None) == gf.GF_EINVAL
     sysbad = (gf.gf_sys * 1)(gf.gf_sys(P1, P2, P3, 4, 1, 10, 10, 10))    # reserved != 0
     assert L.gf_plan_decode(8, sysbad, 1, None, C.byref(h)) == gf.GF_EINVAL
-    assert L.gf_encode_batched(None, None) == gf.GF_EINVAL
-    assert L.gf_decode_batched(None, None, None) == gf.GF_EINVAL
+    assert L.gf_encode_batched(8, P1, 1, None, None) == gf.GF_EINVAL      # no plan
+    assert L.gf_plan_launch(None, None, None) == gf.GF_EINVAL
     assert L.gf_plan_launch_graph(None, None, None) == gf.GF_EINVAL
+    assert L.gf_plan_errors(None, None) == gf.GF_EINVAL
+    # mixed descriptors: some with pointers, some shapes only
+    mixed = (gf.gf_gen * 2)(gf.gf_gen(P1, P2, P3, 2, 2, 10, 10, 10), gf.gf_gen(None, None, None, 2, 2, 10, 10, 10))
+    assert L.gf_plan_encode(8, mixed, 2, None, C.byref(h)) == gf.GF_EINVAL and not h.value
+    # a shape-only descriptor is still checked as a shape
+    shp = (gf.gf_gen * 1)(gf.gf_gen(None, None, None, 2, 3, 10, 5, 10))  # ld_s < len
+    assert L.gf_plan_encode(8, shp, 1, None, C.byref(h)) == gf.GF_EINVAL and not h.value
     L.gf_plan_destroy(None)
+
+
+def test_decode_batched_argument_checks():
+    """The descriptor-driven batched decode checks what the host can: field,
+    count, pointers, the workspace's size and alignment, and overlaps of the
+    workspace with the descriptor and rank arrays."""
+    L = gf.lib()
+    ws = L.gf_decode_workspace(8, 64, 10)
+    assert ws > 10 * 64 * 64
+    W = 0x5000_0000
+    assert L.gf_decode_batched(8, P1, 0, None, None, 0, None) == gf.GF_OK        # nothing to do
+    assert L.gf_decode_batched(3, P1, 10, None, W, ws, None) == gf.GF_EINVAL
+    assert L.gf_decode_batched(8, P1, -1, None, W, ws, None) == gf.GF_EINVAL
+    assert L.gf_decode_batched(8, None, 10, None, W, ws, None) == gf.GF_EINVAL
+    assert L.gf_decode_batched(8, P1, 10, None, None, ws, None) == gf.GF_EINVAL
+    assert L.gf_decode_batched(8, P1, 10, None, W + 16, ws, None) == gf.GF_EINVAL   # not 256-byte aligned
+    assert L.gf_decode_batched(8, P1, 10, None, W, 1000, None) == gf.GF_EINVAL      # far too small
+    assert L.gf_decode_batched(8, W + 512, 10, None, W, ws, None) == gf.GF_EINVAL   # descriptors inside ws
+    assert L.gf_decode_batched(8, P1, 10, W + 512, W, ws, None) == gf.GF_EINVAL     # ranks inside ws
 
 
 def test_recode_argument_checks():
@@ -209,3 +235,5 @@ def test_spans_that_fit_still_pass_validation():
     assert L.gf_decode(8, P1, P2, 10, 4, P3, 10, 10, P4, ws, None, None) == gf.GF_EDEVICE
     assert L.gf_decode_noalloc(8, P1, P2, 10, 4, P3, 10, 10, None, None) == gf.GF_EDEVICE
     assert L.gf_invert(8, P1, 4, P2, None, None) == gf.GF_EDEVICE
+    assert L.gf_decode_batched(8, P1, 10, None, 0x5000_0000, L.gf_decode_workspace(8, 64, 10),
+                               None) == gf.GF_EDEVICE

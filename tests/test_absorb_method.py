@@ -1,16 +1,21 @@
 """The serving runtime's progressive decode, checked on the CPU against the oracle.
 
 The device state of a decode request keeps R, the reduced row echelon form of
-the innovative coefficient vectors received so far, plus each accepted
-packet's raw coefficient row and payload.  A packet's vector is reduced
-against all rows of R in one pass (R is reduced, so no row reintroduces a
-pivot another row cleared); a zero result means the packet is not innovative
-and is dropped.  Otherwise it is scaled so its lowest nonzero column holds 1,
-that column is cleared from the other rows of R, and the raw row and payload
-are kept.  At rank N the sources are Csel^-1 * Bsel over the kept packets.
+the innovative coefficient vectors received so far, the transform T with
+R = T * Csel (Csel: the accepted packets' raw coefficient rows, in order of
+acceptance), and each accepted packet's payload.  A packet's vector is
+reduced against all rows of R in one pass (R is reduced, so no row
+reintroduces a pivot another row cleared), and its transform row is the same
+combination of T's rows plus its own unit weight; a zero vector means the
+packet is not innovative and is dropped.  Otherwise both are scaled so the
+vector's lowest nonzero column holds 1, that column is cleared from the other
+rows of R (T's rows take the same updates), and the payload is kept.  At rank
+N, R is the identity with its rows in pivot order, so row pivot(j) of
+Csel^-1 is row j of T, and the sources are Csel^-1 * Bsel with no inversion.
 These tests emulate that scheme and compare the innovative decisions, the
 rank and the decoded sources with the oracle's progressive decoder (which
-eliminates over [coefficients | payload] instead).
+eliminates over [coefficients | payload] instead), and the inverse with the
+oracle's inverse of Csel.
 """
 import numpy as np
 import pytest
@@ -23,24 +28,29 @@ class Absorb:
     def __init__(self, n: int, N: int):
         self.n, self.N = n, N
         self.M = oracle.mul_table(n)
-        self.R = []            # (pivot column, row) pairs, reduced
+        self.R = []            # (pivot column, row of R, row of T), reduced
         self.Csel, self.Bsel = [], []
 
     def add(self, c: np.ndarray, b: np.ndarray) -> bool:
-        M = self.M
+        M, N = self.M, self.N
         v = c.astype(np.int64).copy()
-        for p, row in self.R:
-            if v[p]:
-                v ^= M[int(v[p])][row]
+        f = [int(v[p]) for p, _, _ in self.R]   # factors from the vector as received
+        for (p, row, trow), fr in zip(self.R, f):
+            v ^= M[fr][row]
         nz = np.nonzero(v)[0]
         if len(nz) == 0:
             return False
+        t = np.zeros(N, dtype=np.int64)
+        t[len(self.R)] = 1                      # the new packet's own weight (innovative: rank < N)
+        for (p, row, trow), fr in zip(self.R, f):
+            t ^= M[fr][trow]
         p = int(nz[0])
-        v = M[oracle.inv(self.n, int(v[p]))][v]
-        for i, (q, row) in enumerate(self.R):
-            if row[p]:
-                self.R[i] = (q, row ^ M[int(row[p])][v])
-        self.R.append((p, v))
+        iv = oracle.inv(self.n, int(v[p]))
+        v, t = M[iv][v], M[iv][t]
+        for i, (q, row, trow) in enumerate(self.R):
+            g = int(row[p])
+            self.R[i] = (q, row ^ M[g][v], trow ^ M[g][t])
+        self.R.append((p, v, t))
         self.Csel.append(c.copy())
         self.Bsel.append(b.copy())
         return True
@@ -49,11 +59,17 @@ class Absorb:
     def rank(self) -> int:
         return len(self.R)
 
+    def inverse(self):
+        """Csel^-1 read off T: row pivot(j) is row j of T."""
+        Cinv = np.zeros((self.N, self.N), dtype=np.uint8)
+        for p, _, trow in self.R:
+            Cinv[p] = trow
+        return Cinv
+
     def solve(self):
         if self.rank < self.N:
             return None
-        Cinv = oracle.invert(self.n, np.array(self.Csel, dtype=np.uint8))
-        return oracle.encode(self.n, Cinv, np.array(self.Bsel, dtype=np.uint8))
+        return oracle.encode(self.n, self.inverse(), np.array(self.Bsel, dtype=np.uint8))
 
 
 @pytest.mark.parametrize("n", [1, 2, 4, 8])
@@ -72,14 +88,18 @@ def test_absorb_matches_the_oracle_progressive_decoder(n, N):
         assert a.add(c, b) == o.add(c, b), i
         assert a.rank == o.rank
         R = np.zeros((len(a.R), N), dtype=np.int64)
-        for j, (p, row) in enumerate(sorted(a.R, key=lambda t: t[0])):
+        for j, (p, row, trow) in enumerate(sorted(a.R, key=lambda t: t[0])):
             R[j] = row
-            assert row[p] == 1 and all(other[p] == 0 for q, other in a.R if q != p)
+            assert row[p] == 1 and all(other[p] == 0 for q, other, _ in a.R if q != p)
+            # R = T * Csel holds row by row
+            C = np.array(a.Csel, dtype=np.uint8)
+            assert np.array_equal(oracle.matmul(n, trow[:len(a.Csel)].astype(np.uint8).reshape(1, -1), C)[0], row)
     got, want = a.solve(), o.solve()
     if want is None:
         assert got is None
     else:
         assert np.array_equal(got, want) and np.array_equal(got, S)
+        assert np.array_equal(a.inverse(), oracle.invert(n, np.array(a.Csel, dtype=np.uint8)))
 
 
 def test_dependent_packets_never_raise_the_rank():

@@ -165,7 +165,8 @@ def test_decode_batch_full_size(gf):
     draws the oracle rejected, decoded as a batch of their own, get the oracle's
     rank from the device and leave their outputs untouched."""
     torch = torch_cuda()
-    _want("decode_2048")
+    if not os.path.exists(digests.path("decode_2048")):
+        pytest.skip("decode draws not written yet (tests/golden/make_digests.py decode_2048)")
     draws = _decode_draws()
     db = synth.decode_batch(2048, 1500)
     count = len(db.Ns)
@@ -187,7 +188,7 @@ def test_decode_batch_full_size(gf):
         encd[i] = gf.gf_gen(cp, sp, bp, Nn, Nn, L, ld, ld)
         sysd[i] = gf.gf_sys(cp, bp, rp, Nn, 0, L, ld, ld)
     eplan = gf.gf_plan_encode_desc(8, encd, count, tune={"form": 1}, keep=(C_dev, S_dev, B_dev))
-    gf.gf_encode_batched(eplan)
+    gf.gf_plan_launch(eplan)
     dplan = gf.gf_plan_decode_desc(8, sysd, count, keep=(C_dev, B_dev, R_dev))
     rank = torch.full((count,), -1, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
@@ -226,7 +227,7 @@ def test_decode_batch_full_size(gf):
         sysr[j] = gf.gf_sys(Cr.data_ptr() + int(offs[j]), bp, out[j].data_ptr(), Nn, 0, 16, int(db.lds[i]), 16)
     rplan = gf.gf_plan_decode_desc(8, sysr, len(rej), keep=(Cr, S_dev, out))
     rk = torch.full((len(rej),), -1, dtype=torch.int32, device="cuda")
-    gf.gf_decode_batched(rplan, rk)
+    gf.gf_plan_launch(rplan, rk)
     torch.cuda.synchronize()
     assert rk.cpu().numpy().tolist() == [r for _, _, r in rej]
     assert (out == 0x77).all()
@@ -257,40 +258,49 @@ def test_recode_relay_full_size(gf):
     rb["plan"].destroy()
 
 
-def test_serving_full_size(gf):
-    """The serving workload (4000 requests, 70% encode / 30% decode, GF(256), 10%
-    loss, random order) all arriving at once through a 4 GiB arena: every encode's
-    sampled bytes are the oracle's and every decode returns its sources exactly."""
+@pytest.mark.parametrize("count,budget_gib", [(4000, 4.0), (20000, 0.5)])
+def test_serving_full_size(gf, count, budget_gib):
+    """The serving workload (70% encode / 30% decode, GF(256), 10% loss, random order,
+    rateless senders) with every request arriving at once: 4000 requests through a
+    4 GiB arena, and the bench's 20,000 through the tight 512 MiB one.  Every decode
+    completes and returns its sources exactly; every encode's sampled bytes are the
+    oracle's."""
     from paper_1909_02871_amd.serving import replay
     torch = torch_cuda()
-    st = bench.serving_trace(gf, torch, 4000)
-    where, S_host, C_host, S_dev = st["where"], st["S_host"], st["C_host"], st["S_dev"]
-    rng = np.random.default_rng(synth.key(64))
-    srv = gf.Server(field=8, budget_bytes=4 << 30)
+    st = bench.serving_trace(gf, torch, count)
+    where, S_dev, C_dev = st["where"], st["S_dev"], st["C_dev"]
+    rng = np.random.default_rng(synth.key(64, count))
+    srv = gf.Server(field=8, budget_bytes=int(budget_gib * (1 << 30)))
     bad = []
 
     def check(d):
         w = where[d["id"]]
         N, L, ld, so = w["N"], w["length"], w["ld"], w["s_off"]
+        if d["status"] != 0:
+            bad.append(("status", d["id"], d["status"]))
+            return
         out = torch.empty((N, L), dtype=torch.uint8, device="cuda")
         srv.copy_out(d["id"], out)
         torch.cuda.synchronize()
+        Sg = S_dev[so:so + N * ld].view(N, ld)
         if w["kind"] == "decode":
-            if d["rank"] != N or not torch.equal(out, S_dev[so:so + N * ld].view(N, ld)[:, :L]):
-                bad.append(d["id"])
+            if d["rank"] != N or not torch.equal(out, Sg[:, :L]):
+                bad.append(("decode", d["id"]))
             return
         rows, cols = _sample_rows(rng, N), _sample_cols(rng, L)
-        Cm = C_host[w["c_off"]:w["c_off"] + N * N].reshape(N, N)
-        S = S_host[so:so + N * ld].reshape(N, ld)
-        want = oracle.encode(8, Cm[rows], np.ascontiguousarray(S[:, cols]))
-        got = out.cpu().numpy()[np.ix_(rows, cols)]
+        Cm = C_dev[w["c_off"]:w["c_off"] + N * N].view(N, N).cpu().numpy()
+        cidx = torch.tensor(cols, device="cuda")
+        want = oracle.encode(8, Cm[rows], Sg.index_select(1, cidx).cpu().numpy())
+        got = out.index_select(1, cidx).cpu().numpy()[rows]
         if not (got == want).all():
-            bad.append(d["id"])
+            bad.append(("encode", d["id"]))
 
     done = replay(srv, st["trace"], on_done=check, timeout_s=300)
+    peak = srv.stats()["arena_peak"]
     srv.close()
-    assert len(done) == 4000
+    assert len(done) == count
     assert not bad, bad[:10]
+    assert peak <= int(budget_gib * (1 << 30))
 
 
 @pytest.mark.parametrize("n,form", [(8, 1), (8, 2), (4, 3), (8, "single")])

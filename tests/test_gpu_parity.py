@@ -153,7 +153,7 @@ def test_encode_every_variant(gf, n, form, bpl, grid):
     for rep in range(2):      # the work counter resets itself between launches
         for _, _, Yd in keep:
             Yd.zero_()
-        gf.gf_encode_batched(plan)
+        gf.gf_plan_launch(plan)
         torch.cuda.synchronize()
         for (Cd, Sd, Yd), w in zip(keep, wants):
             assert (host(Yd) == w).all()
@@ -189,7 +189,7 @@ def test_batched_encode_odd_rows(gf, n, form, pitch, off):
     assert plan.tuning()["form"] == form if form else plan.tuning()["form"] in ((1, 2, 3) if n <= 4 else (1, 2))
     for _, _, Yd, _, _, _ in items:
         Yd.zero_()
-    gf.gf_encode_batched(plan)
+    gf.gf_plan_launch(plan)
     torch.cuda.synchronize()
     for (C, S, Yd, yb, K, L), w in zip(items, wants):
         assert (host(Yd) == w).all()
@@ -211,7 +211,7 @@ def test_encode_long_packet(gf, form):
     Cd, Sd = dev(g.C), dev(g.S)
     Yd = torch.zeros((20, L), dtype=torch.uint8, device="cuda")
     plan = gf.gf_plan_encode(8, [(Cd, Sd, Yd)], tune={"form": form})
-    gf.gf_encode_batched(plan)
+    gf.gf_plan_launch(plan)
     torch.cuda.synchronize()
     got = host(Yd)
     bad = np.argwhere(got != want)
@@ -321,7 +321,7 @@ def test_batched_encode_and_graph(gf, n):
     items = _uneven(n, 60, synth.key(30, n), maxN=96, maxL=3000)
     wants = [oracle.encode(n, g.C, g.S) for g, _, _, _ in items]
     plan = gf.gf_plan_encode(n, [(C, S, Y) for _, C, S, Y in items])
-    gf.gf_encode_batched(plan)
+    gf.gf_plan_launch(plan)
     torch.cuda.synchronize()
     for (g, _, _, Yd), w in zip(items, wants):
         assert (host(Yd) == w).all()
@@ -372,7 +372,7 @@ def test_batched_decode(gf, n, layout):
             out.fill_(0x3C)
         torch.cuda.synchronize()
         if mode == "eager":
-            gf.gf_decode_batched(plan, rank)
+            gf.gf_plan_launch(plan, rank)
         else:
             gf.gf_plan_launch_graph(plan, rank)
         torch.cuda.synchronize()
@@ -463,7 +463,7 @@ def test_batched_recode_and_graph(gf, n, form):
             it[4].fill_(0xC3)
         torch.cuda.synchronize()
         if mode == "eager":
-            gf.gf_encode_batched(plan)
+            gf.gf_plan_launch(plan)
         else:
             gf.gf_plan_launch_graph(plan)
         torch.cuda.synchronize()
@@ -537,7 +537,7 @@ def test_batched_recode_mixed_layouts(gf, n, form):
             it[4].fill_(0xE7)
         torch.cuda.synchronize()
         if mode == "eager":
-            gf.gf_encode_batched(plan)
+            gf.gf_plan_launch(plan)
         else:
             gf.gf_plan_launch_graph(plan)
         torch.cuda.synchronize()
@@ -567,9 +567,9 @@ def test_binding_rejects_host_and_short_buffers(gf):
         gf.gf_decode(8, Cm, B, S, ws=torch.empty(gf.gf_decode_workspace(8, N), dtype=torch.uint8))
     plan = gf.gf_plan_decode(8, [(Cm, B, S), (Cm, B, torch.empty_like(S))])
     with pytest.raises(ValueError):  # one rank slot for two systems
-        gf.gf_decode_batched(plan, d_rank=torch.zeros(1, dtype=torch.int32, device="cuda"))
+        gf.gf_plan_launch(plan, d_rank=torch.zeros(1, dtype=torch.int32, device="cuda"))
     rank = torch.zeros(2, dtype=torch.int32, device="cuda")
-    gf.gf_decode_batched(plan, d_rank=rank)
+    gf.gf_plan_launch(plan, d_rank=rank)
     torch.cuda.synchronize()
     assert host(rank).tolist() == [N, N]
     plan.destroy()
@@ -590,3 +590,43 @@ def test_binding_rejects_host_and_short_buffers(gf):
     assert (host(out) == oracle.encode(8, Ce, host(S))).all()
     srv.release(1)
     srv.close()
+
+
+@pytest.mark.parametrize("n", FIELDS)
+@pytest.mark.parametrize("smax", [1, 2, 3, 8])
+@pytest.mark.parametrize("aligned", [True, False])
+def test_stream_form_small_generations(gf, n, smax, aligned):
+    """Form 4 (small generations streamed through a software pipeline; the kernel
+    instance follows the batch's largest K or N): every byte equals the oracle's,
+    on generations of one to many 1 KiB strips, tiles of 64 strips and ragged
+    ends, 16-byte aligned rows and odd ones (byte path); padding untouched."""
+    torch = torch_cuda()
+    items, wants = [], []
+    for i in range(40):
+        N = int(synth.uniform_ints(synth.key(17, smax, i), 1, 1, smax)[0])
+        K = int(synth.uniform_ints(synth.key(18, smax, i), 1, 1, smax)[0])
+        L = [1, 15, 1023, 1024, 1025, 3000, 9000, 65536, 70001, 2049][i % 10]
+        g = synth.generation(synth.key(19, n, smax, i), n, N, K, L)
+        wants.append(oracle.encode(n, g.C, g.S))
+        ld = synth.padded(L) if aligned else L + 3
+        _, Sd = padded_rows(g.S, ld, 0 if aligned else 1)
+        yb, Yd = padded_rows(np.zeros((K, L), np.uint8), ld, fill=0x5A)
+        items.append((dev(g.C), Sd, Yd, yb, K, L, ld))
+    plan = gf.gf_plan_encode(n, [(C, S, Y) for C, S, Y, _, _, _, _ in items], tune={"form": 4})
+    assert plan.tuning()["form"] == 4
+    for rep in range(2):
+        for _, _, Yd, _, _, _, _ in items:
+            Yd.fill_(0x5A)
+        if rep == 0:
+            gf.gf_plan_launch(plan)
+        else:
+            gf.gf_plan_launch_graph(plan)
+        torch.cuda.synchronize()
+        for (C, S, Yd, yb, K, L, ld), w in zip(items, wants):
+            assert (host(Yd) == w).all(), (K, L)
+            raw = host(yb)[:K * ld].reshape(K, ld)
+            assert (raw[:, L:] == 0x5A).all()
+    plan.destroy()
+    big = [(dev(np.ones((9, 2), np.uint8)), dev(np.ones((2, 8), np.uint8)), dev(np.zeros((9, 8), np.uint8)))]
+    with pytest.raises(gf.GFError):      # K = 9: not a small generation
+        gf.gf_plan_encode(n, big, tune={"form": 4})

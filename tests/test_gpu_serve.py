@@ -7,6 +7,7 @@ random order, 10% lost, plus one repeated packet that must be recognised as
 not innovative; packets are released over time, so the echelon state lives on
 the device across several steps."""
 import math
+import time
 
 import numpy as np
 import pytest
@@ -113,3 +114,53 @@ def test_alone_equals_mix_equals_oracle(gf, n):
         if r.kind == "decode":
             assert d["rank"] == r.N
             assert d["packets_dropped"] >= 1 or d["packets_seen"] < len(r.packets)
+
+
+def test_copy_out_then_release_keeps_the_bytes_until_the_copy_ran(gf):
+    """copy_out on a busy side stream, release at once, then a new request that
+    would take the same arena memory: the copy still reads the first request's
+    bytes (the memory is reused only after the copy has run)."""
+    torch = torch_cuda()
+    N, L = 32, 4000
+    gA = synth.generation(synth.key(95, 1), 8, N, N, L)
+    gB = synth.generation(synth.key(95, 2), 8, N, N, L)
+    want = oracle.encode(8, gA.C, gA.S)
+    keep = [dev(gA.C), dev(gA.S), dev(gB.C), dev(gB.S)]
+    ld = (L + 15) // 16 * 16
+    srv = gf.Server(field=8, budget_bytes=N * ld + 256)      # room for one request only
+    srv.submit_encode(1, keep[0], keep[1], N, N, L, L, 0.0)
+    t = 0.0
+    done = []
+    while not done:
+        t += 0.001
+        srv.step(t)
+        done = srv.poll()
+    side = torch.cuda.Stream()
+    dst = torch.full((N, L), 0x11, dtype=torch.uint8, device="cuda")
+    a = torch.randn((4096, 4096), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        for _ in range(40):                # keeps the side stream busy before the copy (tens of ms)
+            a = torch.tanh(a @ a)
+    srv.copy_out(1, dst, stream=side)
+    srv.release(1)
+    srv.submit_encode(2, keep[2], keep[3], N, N, L, L, t)
+    out2 = None
+    t_end = time.perf_counter() + 20.0
+    while time.perf_counter() < t_end:
+        t += 0.001
+        srv.step(t)
+        got = srv.poll()
+        if got:
+            out2 = got[0]
+            break
+    assert out2 is not None and out2["id"] == 2
+    side.synchronize()
+    torch.cuda.synchronize()
+    assert (host(dst) == want).all()
+    o2 = torch.empty((N, L), dtype=torch.uint8, device="cuda")
+    srv.copy_out(2, o2)
+    torch.cuda.synchronize()
+    assert (host(o2) == oracle.encode(8, gB.C, gB.S)).all()
+    srv.release(2)
+    srv.close()

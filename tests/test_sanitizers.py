@@ -33,12 +33,13 @@ def test_host_runtime_under_sanitizers(tmp_path):
     if not rt:
         pytest.skip("clang sanitizer runtime not found")
     from paper_1909_02871_amd import build as hip_build
-    kernels = [os.path.join(hip_build.BUILD_DIR, s + ".o") for s in ("gf_kernels.hip", "gf_mfma.hip")]
+    # device-code files as built; the host-code files rebuilt with the sanitizers
+    kernels = [os.path.join(hip_build.BUILD_DIR, s + ".o") for s in hip_build.SOURCES if s.endswith(".hip")]
     if not all(os.path.exists(k) for k in kernels):
         hip_build.build()
     objs = []
     procs = []
-    for src in ("gf_tables.cpp", "gf_api.cpp", "gf_serve.cpp"):
+    for src in [s for s in hip_build.SOURCES if s.endswith(".cpp")]:
         obj = str(tmp_path / (src + ".o"))
         objs.append(obj)
         procs.append(subprocess.Popen(

@@ -186,3 +186,90 @@ def test_calls_from_several_threads_are_serialised():
             done += 1
         assert t < 1000
     assert s.stats()["arena_used"] == 0
+
+
+def test_starved_decode_is_cancelled_and_its_slot_reused():
+    """A decode whose sender stops short of rank N never completes by itself;
+    cancelling it completes it with GF_ECANCELED (no output), and releasing it
+    frees its slot and memory for the request queued behind it."""
+    s = gf.Server(budget_bytes=1 << 20, max_slots=1, dry_run=True)
+    s.submit_decode(1, 6, 500, 0.0)
+    for j in range(4):                       # only 4 of the 6 packets it needs
+        s.push_packet(1, FAKE + j, FAKE + 100 + j, 0.0)
+    s.submit_decode(2, 3, 500, 0.0)          # waits for the only slot
+    for t in (0.1, 0.2, 0.3):
+        s.step(t)
+        assert s.poll() == []
+    st = s.stats()
+    assert st["active"] == 1 and st["queued"] == 1
+    s.cancel(1, 0.35)
+    with pytest.raises(gf.GFError):
+        s.push_packet(1, FAKE, FAKE, 0.4)    # a completed request takes no packets
+    (d,) = s.poll()
+    assert d["id"] == 1 and d["status"] == gf.GF_ECANCELED and d["rank"] == 4
+    with pytest.raises(gf.GFError):
+        s.cancel(1, 0.4)                     # already completed
+    # a cancelled request has no output to copy
+    assert gf.lib().gf_serve_copy_out(s._h, 1, 0x1000, 500, None) == gf.GF_EINVAL
+    s.release(1)
+    for j in range(3):
+        s.push_packet(2, FAKE + j, FAKE + 100 + j, 0.4)
+    s.step(0.5)
+    s.step(0.6)
+    (d2,) = s.poll()
+    assert d2["id"] == 2 and d2["status"] == gf.GF_OK and d2["rank"] == 3
+    assert d2["t_admit"] >= 0.35
+
+
+def test_cancel_of_queued_requests_and_admitted_encodes():
+    s = gf.Server(budget_bytes=64 * 1024, dry_run=True)
+    s.submit_encode(1, FAKE, FAKE, 16, 16, 1500, 1500, 0.0)      # 24 KiB
+    s.submit_encode(2, FAKE, FAKE, 16, 16, 2000, 2000, 0.0)      # 32 KiB
+    s.submit_encode(3, FAKE, FAKE, 16, 16, 2000, 2000, 0.0)      # queued behind the budget
+    s.step(0.0)
+    assert s.stats()["queued"] == 1
+    with pytest.raises(gf.GFError):
+        s.cancel(1, 0.01)                     # admitted encode: completes in its step
+    s.cancel(3, 0.01)                         # queued: completes at once
+    done = {d["id"]: d for d in s.poll()}
+    assert done[3]["status"] == gf.GF_ECANCELED and s.stats()["queued"] == 0
+    s.step(0.1)
+    done.update({d["id"]: d for d in s.poll()})
+    assert done[1]["status"] == gf.GF_OK and done[2]["status"] == gf.GF_OK
+    with pytest.raises(gf.GFError):
+        s.cancel(99, 0.2)                     # unknown id
+
+
+def test_query_reports_state_and_pending_packets():
+    s = gf.Server(budget_bytes=1 << 20, burst=2, max_slots=1, dry_run=True)
+    s.submit_decode(1, 4, 100, 0.0)
+    s.submit_decode(2, 4, 100, 0.0)
+    for j in range(5):
+        s.push_packet(1, FAKE + j, FAKE + 100 + j, 0.0)
+    assert s.query(1)["state"] == 0 and s.query(1)["packets_pending"] == 5
+    s.step(0.1)                      # admitted; takes 2 packets
+    q = s.query(1)
+    assert q["state"] == 1 and q["packets_pending"] == 3
+    s.step(0.2)
+    s.step(0.3)
+    assert s.query(1)["state"] == 2 and s.query(1)["rank"] == 4
+    assert s.query(2)["state"] == 1      # admitted into the slot request 1 left
+    (d,) = s.poll()
+    s.release(1)
+    with pytest.raises(gf.GFError):
+        s.query(1)                   # released
+
+
+def test_replay_cancels_a_starved_decode_only_once_admitted_and_dry():
+    """The rateless replay: a decode whose sender runs out before rank N is
+    cancelled, but only after the server admitted it and took every packet;
+    requests queued behind it for a long time are not."""
+    from paper_1909_02871_amd.serving import TraceRequest, replay
+    s = gf.Server(budget_bytes=1 << 20, burst=4, max_slots=1, dry_run=True)
+    trace = [TraceRequest(0, 0.0, "decode", 6, 100, packets=[(FAKE + j, FAKE + 50 + j, 1e-6 * j) for j in range(3)])]
+    trace += [TraceRequest(i, 0.0, "decode", 3, 100, packets=[(FAKE + j, FAKE + 50 + j, 1e-6 * j) for j in range(5)])
+              for i in range(1, 4)]
+    done = replay(s, trace, timeout_s=20, starve_s=0.2)
+    by = {d["id"]: d for d in done}
+    assert by[0]["status"] == gf.GF_ECANCELED and by[0]["rank"] == 3
+    assert all(by[i]["status"] == gf.GF_OK and by[i]["rank"] == 3 for i in (1, 2, 3))
