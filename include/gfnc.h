@@ -184,9 +184,10 @@ typedef struct {
  *         3-input bit operation per row, source, plane and dword);
  *         GF_EINVAL for GF(256).
  * form 4: small generations streamed at 16 payload bytes per lane, every
- *         generation's K x N tables staged once per tile and the next strip's
- *         loads in flight during the current one's lookups; only when every
- *         generation has K <= 8 and N <= 8 (GF_EINVAL otherwise).
+ *         generation's K x N tables staged once per tile and the strips read
+ *         in bursts of about 8 KiB per wave; only when every generation has
+ *         K <= 8 and N <= 8 and its rows (S, Y, ld_s, ld_y) are 16-byte
+ *         aligned (GF_EINVAL otherwise).
  * form 0 on an encode plan made with pointers: every form that applies is
  * timed on the plan's own batch while the plan is created (which writes the
  * plan's outputs) and the fastest is kept (form 2 is skipped if a packet is

@@ -209,7 +209,7 @@ struct gf_plan {
     DevGen *d_bound = nullptr;      // the same shapes with the pointers of gf_encode_batched's descriptors
     unsigned *d_err = nullptr;      // [0] descriptors refused by that call, [1] = 1 (status of a refused one)
     bool shape_only = false;        // made from shapes alone (no pointers to run on)
-    bool small_ok = false;          // every generation has K, N <= STREAM_MAX (form 4 applies)
+    bool small_ok = false;          // every generation has K, N <= STREAM_MAX and 16-byte aligned rows (form 4 applies)
     int small_max = 0;              // the largest K or N of the batch
     DevTile *d_tiles = nullptr;
     unsigned *d_runs = nullptr;     // first tile of each run, then the queue bounds
@@ -943,12 +943,12 @@ static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, co
     bool mf_ok = true;   // the bit-matrix kernels count a tile's steps in 32 bits
     p->small_ok = true;  // every generation fits the streaming form
     for (DevGen &x : g) {
-        if (x.K > STREAM_MAX || x.N > STREAM_MAX)
-            p->small_ok = false;
         p->small_max = std::max<int>(p->small_max, (int)std::max(x.K, x.N));
         if (x.len > (1ull << 34))
             mf_ok = false;
         x.align = row_align(x.S, x.N > 1 ? x.ld_s : 0, x.Y, x.K > 1 ? x.ld_y : 0);
+        if (x.K > STREAM_MAX || x.N > STREAM_MAX || x.align < 16)   // the streaming form reads 16-byte blocks
+            p->small_ok = false;
         if ((((uintptr_t)x.S) | (x.N > 1 ? x.ld_s : 0)) % 4 != 0)
             p->src_aligned4 = false;
     }

@@ -71,18 +71,51 @@ __device__ __forceinline__ void gst(void *p, T v)
     *reinterpret_cast<__attribute__((address_space(1))) T *>(reinterpret_cast<uintptr_t>(p)) = v;
 }
 
-template <int D>
-__device__ __forceinline__ void load_row(const uint8_t *p, uint64_t avail, bool vec, uint32_t (&x)[D])
+// The same for data touched once (streamed sources and outputs): marked
+// non-temporal, so they pass through the caches without displacing what is
+// reused.
+template <class T>
+__device__ __forceinline__ T gld_nt(const void *p)
 {
-    if (vec && avail >= 4u * D) {
-        if constexpr (D == 4) {
-            const gf_u32x4 t = gld<gf_u32x4>(p);
+    return __builtin_nontemporal_load(
+        reinterpret_cast<const __attribute__((address_space(1))) T *>(reinterpret_cast<uintptr_t>(p)));
+}
+
+template <class T>
+__device__ __forceinline__ void gst_nt(void *p, T v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<__attribute__((address_space(1))) T *>(reinterpret_cast<uintptr_t>(p)));
+}
+
+// Bytes [q, q + 4D) of a row, as D dwords: q is the row's byte `off`, and
+// `avail` bytes of the row are left from there.  vec: the row starts 16-byte
+// aligned and off is a multiple of 4D.  Then the block is read with one
+// vector load, unconditionally, also when the row ends inside it: an aligned
+// block of at most 16 bytes lies inside the 4 KiB page of its first byte, so
+// the read stays in mapped memory; a block wholly past the end reads the
+// row's first block instead.  Either way the bytes past the row's end hold
+// other data.  Every caller multiplies byte positions independently and stores
+// only the first `avail` bytes of its results, so they never reach an output.
+// (Masking them here, or a branch around the load, would use the loaded value
+// at once, and a wave that uses a load waits for every load it has in flight,
+// which would empty the callers' software pipelines.)  Rows that are not
+// aligned go byte by byte, zero past the end.
+template <int D, bool NT = false>
+__device__ __forceinline__ void load_row(const uint8_t *q, uint64_t off, uint64_t avail, bool vec, uint32_t (&x)[D])
+{
+    if (vec) {
+        const uint8_t *a = avail > 0 ? q : q - off;
+        if constexpr (D == 4 && NT) {
+            const gf_u32x4 t = gld_nt<gf_u32x4>(a);
+            x[0] = t.x; x[1] = t.y; x[2] = t.z; x[3] = t.w;
+        } else if constexpr (D == 4) {
+            const gf_u32x4 t = gld<gf_u32x4>(a);
             x[0] = t.x; x[1] = t.y; x[2] = t.z; x[3] = t.w;
         } else if constexpr (D == 2) {
-            const gf_u32x2 t = gld<gf_u32x2>(p);
+            const gf_u32x2 t = gld<gf_u32x2>(a);
             x[0] = t.x; x[1] = t.y;
         } else {
-            x[0] = gld<uint32_t>(p);
+            x[0] = gld<uint32_t>(a);
         }
     } else {
 #pragma unroll
@@ -91,15 +124,17 @@ __device__ __forceinline__ void load_row(const uint8_t *p, uint64_t avail, bool 
 #pragma unroll
         for (int b = 0; b < 4 * D; b++)
             if ((uint64_t)b < avail)
-                x[b >> 2] |= (uint32_t)gld<uint8_t>(p + b) << (8 * (b & 3));
+                x[b >> 2] |= (uint32_t)gld<uint8_t>(q + b) << (8 * (b & 3));
     }
 }
 
-template <int D>
+template <int D, bool NT = false>
 __device__ __forceinline__ void store_row(uint8_t *p, uint64_t avail, bool vec, const uint32_t (&x)[D])
 {
     if (vec && avail >= 4u * D) {
-        if constexpr (D == 4) {
+        if constexpr (D == 4 && NT) {
+            gst_nt<gf_u32x4>(p, gf_u32x4{x[0], x[1], x[2], x[3]});
+        } else if constexpr (D == 4) {
             gst<gf_u32x4>(p, gf_u32x4{x[0], x[1], x[2], x[3]});
         } else if constexpr (D == 2) {
             gst<gf_u32x2>(p, gf_u32x2{x[0], x[1]});
@@ -185,62 +220,134 @@ struct RegionDesc {
     uint32_t reserved;
 };
 
-// One 16-byte piece of a batched region madd: piece v of region r.  Aligned
-// regions take one vector load of x and of y; others (and a region's last
-// partial piece) go byte by byte.
+// One 16-byte piece of a batched region madd: bytes [p, p + 16) of region d
+// (p < d.len, a multiple of 16).  When x and y are 16-byte aligned, both
+// pieces are read with one vector load each, also the region's last, partial
+// piece: an aligned 16-byte block lies inside the 4 KiB page of its first
+// byte, so reading it whole stays in mapped memory; only the bytes before
+// d.len are written back.  Unaligned regions load every byte first and then
+// store, so the wave waits for its loads once.
 __device__ __forceinline__ void region_piece(const RegionDesc &d, uint64_t p, const uint4 ta, uint32_t tb)
 {
-    const bool vec = ((((uintptr_t)d.y | (uintptr_t)d.x) & 15u) == 0) && p + 16 <= d.len;
-    if (vec) {
-        const uint4 a = *reinterpret_cast<const uint4 *>(d.x + p);
-        uint4 yv = *reinterpret_cast<const uint4 *>(d.y + p);
+    if ((((uintptr_t)d.y | (uintptr_t)d.x) & 15u) == 0) {
+        const gf_u32x4 a = gld_nt<gf_u32x4>(d.x + p);
+        gf_u32x4 yv = gld_nt<gf_u32x4>(d.y + p);
         yv.x ^= prod4(ta, tb, a.x);
         yv.y ^= prod4(ta, tb, a.y);
         yv.z ^= prod4(ta, tb, a.z);
         yv.w ^= prod4(ta, tb, a.w);
-        *reinterpret_cast<uint4 *>(d.y + p) = yv;
+        if (p + 16 <= d.len) {
+            gst_nt<gf_u32x4>(d.y + p, yv);
+        } else {
+            const int n = (int)(d.len - p);   // 1 .. 15 bytes left
+            const uint32_t w[4] = {yv.x, yv.y, yv.z, yv.w};
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+                if (4 * k + 4 <= n)
+                    gst<uint32_t>(d.y + p + 4 * k, w[k]);
+#pragma unroll
+            for (int b = 0; b < 16; b++)
+                if (b >= (n & ~3) && b < n)
+                    gst<uint8_t>(d.y + p + b, (uint8_t)(w[b >> 2] >> (8 * (b & 3))));
+        }
     } else {
-        const uint64_t end = min(d.len, p + 16);
-        for (uint64_t b = p; b < end; b++)
-            d.y[b] ^= (uint8_t)(prod4(ta, tb, (uint32_t)d.x[b]) & 0xFFu);
+        const int n = (int)(min(d.len, p + 16) - p);
+        uint32_t xb[16], yb[16];
+#pragma unroll
+        for (int b = 0; b < 16; b++) {
+            const uint64_t o = p + (uint64_t)(b < n ? b : n - 1);   // inside the region
+            xb[b] = gld<uint8_t>(d.x + o);
+            yb[b] = gld<uint8_t>(d.y + o);
+        }
+#pragma unroll
+        for (int b = 0; b < 16; b++)
+            if (b < n)
+                gst<uint8_t>(d.y + p + b, (uint8_t)(yb[b] ^ (prod4(ta, tb, xb[b]) & 0xFFu)));
     }
 }
 
-// Batched madd of regions shorter than 4 KiB over a flat index of 16-byte
-// pieces: piece f is piece f % vpr of region f / vpr, vpr = the pieces of the
-// longest region, so every lane of a wave has work while regions are about
-// that long (a 1500-byte region is 94 lanes, not a 256-thread block).  Each thread keeps two pieces in flight:
-// both descriptor loads, then both pieces' data.
-// f / d for f < 2^52 without an integer division: the double quotient is at
-// most one off, then corrected.
-__device__ __forceinline__ uint64_t div_small(uint64_t f, uint64_t d, double inv)
+// Batched madd of regions shorter than 4 KiB: one wave per region at a time
+// (regions dealt to the waves round robin), lane l taking the 16-byte pieces
+// l, l + 64, ..., M per lane (M = 1024-byte rounds of the longest region).
+// Descriptors and the coefficient's tables are wave-uniform scalar loads, the
+// next region's read while the current one's pieces are in flight.  For
+// 16-byte aligned regions the wave issues the loads of all its pieces of x
+// and y back to back (a piece past the region's end re-reads its first
+// piece), waits once, and stores the pieces inside the region; others go
+// piece by piece.
+constexpr int REGION_WAVES = 4;   // waves per workgroup of the region kernels
+
+__device__ __forceinline__ bool region_live(const RegionDesc &d, int q)
 {
-    uint64_t r = (uint64_t)((double)f * inv);
-    if (r * d > f)
-        r--;
-    else if ((r + 1) * d <= f)
-        r++;
-    return r;
+    return d.c != 0 && d.c < (uint32_t)q && d.len != 0;
 }
 
-__global__ __launch_bounds__(256) void k_region_batched(const RegionDesc *__restrict__ regs,
-                                                        const uint4 *__restrict__ ptab4, int q, uint64_t total,
-                                                        uint32_t vpr, double inv_vpr)
+template <int M>
+__global__ __launch_bounds__(256) void k_region_waves(const RegionDesc *__restrict__ regs,
+                                                      const uint4 *__restrict__ ptab4, int q, int count)
 {
-    const uint64_t stride = (uint64_t)gridDim.x * 256u;
-    for (uint64_t f0 = (uint64_t)blockIdx.x * 256u + threadIdx.x; f0 < total; f0 += 2 * stride) {
-        const uint64_t f1 = f0 + stride;
-        const bool two = f1 < total;
-        const uint64_t r0 = div_small(f0, vpr, inv_vpr), r1 = two ? div_small(f1, vpr, inv_vpr) : r0;
-        const RegionDesc d0 = regs[r0];
-        const RegionDesc d1 = regs[r1];
-        const uint64_t p0 = (f0 - r0 * vpr) * 16u, p1 = (f1 - r1 * vpr) * 16u;
-        const bool w0 = d0.c != 0 && d0.c < (uint32_t)q && p0 < d0.len;
-        const bool w1 = two && d1.c != 0 && d1.c < (uint32_t)q && p1 < d1.len;
-        if (w0)
-            region_piece(d0, p0, ptab4[d0.c * 2], ptab4[d0.c * 2 + 1].x);
-        if (w1)
-            region_piece(d1, p1, ptab4[d1.c * 2], ptab4[d1.c * 2 + 1].x);
+    const int lane = threadIdx.x & 63;
+    const int w0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * REGION_WAVES) + (int)(threadIdx.x >> 6));
+    const int nw = (int)(gridDim.x * REGION_WAVES);
+    if (w0 >= count)
+        return;
+    RegionDesc d = regs[w0];
+    uint4 ta = ptab4[d.c < 256 ? d.c * 2 : 0];
+    uint32_t tb = ptab4[d.c < 256 ? d.c * 2 + 1 : 1].x;
+    for (int r = w0; r < count; r += nw) {
+        const int rn = r + nw;
+        const RegionDesc dn = regs[min(rn, count - 1)];   // one scalar load, unconditional
+        const bool live = region_live(d, q);
+        if (live && ((((uintptr_t)d.y | (uintptr_t)d.x)) & 15u) == 0) {
+            gf_u32x4 xv[M], yv[M];
+#pragma unroll
+            for (int m = 0; m < M; m++) {
+                const uint64_t pc = (uint64_t)(lane + 64 * m) * 16u;
+                const uint64_t p = pc < d.len ? pc : 0;   // in the region, so in mapped memory
+                xv[m] = gld_nt<gf_u32x4>(d.x + p);
+                yv[m] = gld_nt<gf_u32x4>(d.y + p);
+            }
+#pragma unroll
+            for (int m = 0; m < M; m++) {
+                // every loaded register is read here, also for pieces past the
+                // end, so no load is left in flight for the next region's loads
+                // to wait on (they would wait for this region's stores too)
+                asm volatile("" ::"v"(xv[m].x), "v"(xv[m].y), "v"(xv[m].z), "v"(xv[m].w));
+                asm volatile("" ::"v"(yv[m].x), "v"(yv[m].y), "v"(yv[m].z), "v"(yv[m].w));
+                const uint64_t p = (uint64_t)(lane + 64 * m) * 16u;
+                gf_u32x4 v = yv[m];
+                v.x ^= prod4(ta, tb, xv[m].x);
+                v.y ^= prod4(ta, tb, xv[m].y);
+                v.z ^= prod4(ta, tb, xv[m].z);
+                v.w ^= prod4(ta, tb, xv[m].w);
+                if (p + 16 <= d.len) {
+                    gst_nt<gf_u32x4>(d.y + p, v);
+                } else if (p < d.len) {   // the region's last, partial piece
+                    const int n = (int)(d.len - p);
+                    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int k = 0; k < 4; k++)
+                        if (4 * k + 4 <= n)
+                            gst<uint32_t>(d.y + p + 4 * k, w[k]);
+#pragma unroll
+                    for (int b = 0; b < 16; b++)
+                        if (b >= (n & ~3) && b < n)
+                            gst<uint8_t>(d.y + p + b, (uint8_t)(w[b >> 2] >> (8 * (b & 3))));
+                }
+            }
+        } else if (live) {
+#pragma unroll
+            for (int m = 0; m < M; m++) {
+                const uint64_t p = (uint64_t)(lane + 64 * m) * 16u;
+                if (p < d.len)
+                    region_piece(d, p, ta, tb);
+            }
+        }
+        if (rn < count) {   // the next region's tables, read while its data are fetched
+            ta = ptab4[dn.c < 256 ? dn.c * 2 : 0];
+            tb = ptab4[dn.c < 256 ? dn.c * 2 + 1 : 1].x;
+        }
+        d = dn;
     }
 }
 
@@ -287,17 +394,6 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
-template <int D>
-__device__ __forceinline__ void load_lane(const uint8_t *p, uint64_t avail, bool vec, uint32_t (&x)[D])
-{
-    if (avail == 0) {
-#pragma unroll
-        for (int d = 0; d < D; d++)
-            x[d] = 0;
-    } else {
-        load_row<D>(p, avail, vec, x);
-    }
-}
 
 // One wave tile: coded rows k0 .. k0+min(KW, K-k0)-1 over the 256*D payload
 // bytes starting at p0 (4*D bytes per lane).  The N source rows stream
@@ -325,9 +421,9 @@ __device__ __forceinline__ void wave_tile(const uint8_t *__restrict__ C, int K, 
 
     const uint8_t *src = S + p;
     uint32_t xa[D], xb[D];
-    load_lane<D>(src + (uint64_t)nb * ld_s, avail, vec, xa);
+    load_row<D>(src + (uint64_t)nb * ld_s, p, avail, vec, xa);
     if (nb + 1 < ne)
-        load_lane<D>(src + (uint64_t)(nb + 1) * ld_s, avail, vec, xb);
+        load_row<D>(src + (uint64_t)(nb + 1) * ld_s, p, avail, vec, xb);
     else
 #pragma unroll
         for (int d = 0; d < D; d++)
@@ -355,9 +451,9 @@ __device__ __forceinline__ void wave_tile(const uint8_t *__restrict__ C, int K, 
         }
         const bool two = g + 1 < ne;
         if (g + 2 < ne)
-            load_lane<D>(src + (uint64_t)(g + 2) * ld_s, avail, vec, xa);
+            load_row<D>(src + (uint64_t)(g + 2) * ld_s, p, avail, vec, xa);
         if (g + 3 < ne)
-            load_lane<D>(src + (uint64_t)(g + 3) * ld_s, avail, vec, xb);
+            load_row<D>(src + (uint64_t)(g + 3) * ld_s, p, avail, vec, xb);
         if (two) {
 #pragma unroll
             for (int k8 = 0; k8 < KW; k8 += 8) {
@@ -433,42 +529,43 @@ __device__ __forceinline__ void wave_tile(const uint8_t *__restrict__ C, int K, 
 // latency and bandwidth, not by the lookups.  A wave here takes a tile of up
 // to STREAM_STRIPS strips of 1 KiB (16 bytes per lane) of one generation,
 // stages the generation's K x N product tables in its LDS once, and streams
-// the strips through a software pipeline DEPTH strips deep: the loads of
-// strip s + DEPTH - 1 are issued before strip s is multiplied.  SK (the batch's
-// largest K or N, rounded up to 1, 2, 4 or 8) sizes the registers, and DEPTH
-// grows as SK shrinks, so every wave keeps about the same bytes in flight.
+// the strips in bursts of B: the loads of B strips go out back to back, the
+// wave waits for them once, multiplies the B strips and stores them.  (On
+// this chip loads and stores share one completion counter that the compiler
+// must treat as unordered once both are in flight, so a wave cannot keep a
+// load in flight across the use of an earlier one while its stores drain;
+// what it can do is issue many loads before its first use.)  SK (the batch's
+// largest K or N, rounded up to 1, 2, 4 or 8) sizes the registers, and B
+// shrinks as SK grows, so every burst reads about 8 KiB; the small register
+// budget lets 8 waves share each SIMD, whose bursts overlap.
 
 template <int SK>
 struct SmallStage {
     uint4 t[SK][SK][2];   // [coded row][source][tables]
 };
 
-// The N source dwords x 4 of one strip (zero past the packet or past N).
+// The source rows x 16 bytes of one strip per lane; rows are 16-byte
+// aligned.  Rows past N re-read row N - 1 (their tables are zero), so every
+// load is unconditional: a wave whose loads all feed the next products never
+// has a stale load in flight when it reuses the registers.
 template <int SK>
-__device__ __forceinline__ void small_load(const uint8_t *S, uint64_t ld_s, int N, uint64_t p, uint64_t len, bool vec,
+__device__ __forceinline__ void small_load(const uint8_t *S, uint64_t ld_s, int N, uint64_t p, uint64_t len,
                                            uint32_t (&x)[SK][4])
 {
     const uint64_t avail = p < len ? len - p : 0;
 #pragma unroll
-    for (int i = 0; i < SK; i++) {
-        if (i < N)
-            load_lane<4>(S + (uint64_t)i * ld_s + p, avail, vec, x[i]);
-        else
-#pragma unroll
-            for (int d = 0; d < 4; d++)
-                x[i][d] = 0;
-    }
+    for (int i = 0; i < SK; i++)
+        load_row<4, true>(S + (uint64_t)min(i, N - 1) * ld_s + p, p, avail, true, x[i]);
 }
 
 // All K coded rows of one strip: the sources go two at a time (their byte
 // splits computed once), each pair multiplied into every row's accumulators.
 template <int SK>
 __device__ __forceinline__ void small_strip(const SmallStage<SK> &st, int K, int N, uint8_t *Y, uint64_t ld_y,
-                                            uint64_t p, uint64_t len, bool vec, const uint32_t (&x)[SK][4])
+                                            uint64_t p, uint64_t len, bool vec, const uint32_t (&x)[SK][4],
+                                            bool store = true)
 {
-    const uint64_t avail = p < len ? len - p : 0;
-    if (avail == 0)
-        return;
+    const uint64_t avail = p < len && store ? len - p : 0;
     uint32_t acc[SK][4];
 #pragma unroll
     for (int k = 0; k < SK; k++)
@@ -513,59 +610,172 @@ __device__ __forceinline__ void small_strip(const SmallStage<SK> &st, int K, int
 #pragma unroll
     for (int k = 0; k < SK; k++)
         if (k < K)
-            store_row<4>(Y + (uint64_t)k * ld_y + p, avail, vec, acc[k]);
+            store_row<4, true>(Y + (uint64_t)k * ld_y + p, avail, vec, acc[k]);
 }
 
-template <int SK, int DEPTH>
-__global__ __launch_bounds__(256) void k_encode_stream(const DevGen *__restrict__ gens,
+// queue_next_tile for a whole wave, every lane calling with the same cursor: lane 0
+// makes the claims, every other load is from a wave-uniform address, and the
+// result is wave-uniform.  While the current run lasts no memory is touched,
+// so a wave that claims its next tile early does not wait for the loads and
+// stores it has in flight.
+__device__ __forceinline__ int queue_next_tile_wave(unsigned *counters, const unsigned *__restrict__ runs,
+                                                    const unsigned *__restrict__ bounds, QueueCursor &c, int lane)
+{
+    const int home = (int)(blockIdx.x % MF_QUEUES);
+    while (c.next == c.end) {
+        if (c.q >= MF_QUEUES)
+            return -1;
+        const int qi = (home + c.q) % MF_QUEUES;
+        const unsigned lo = bounds[qi], hi = bounds[qi + 1];
+        unsigned t = ~0u;
+        if (lo < hi) {
+            unsigned v = 0;
+            if (lane == 0)
+                v = atomicAdd(&counters[MF_CTR_STRIDE * qi], 1u);
+            t = (unsigned)__builtin_amdgcn_readlane((int)v, 0);
+        }
+        if (lo < hi && t < hi - lo) {
+            const unsigned r = lo + t;
+            c.next = runs ? runs[r] : r;
+            c.end = runs ? runs[r + 1] : r + 1;
+        } else {
+            c.q++;
+        }
+    }
+    return (int)c.next++;
+}
+
+// A tile descriptor made wave-uniform (each field taken from lane 0), so that
+// loops and branches over its strips stay scalar.
+__device__ __forceinline__ DevTile uniform_tile(const DevTile &v)
+{
+    DevTile u;
+    u.gen = __builtin_amdgcn_readfirstlane(v.gen);
+    u.k0 = (uint16_t)__builtin_amdgcn_readfirstlane((uint32_t)v.k0);
+    u.D = (uint16_t)__builtin_amdgcn_readfirstlane((uint32_t)v.D);
+    u.p0 = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(v.p0 >> 32)) << 32) |
+           __builtin_amdgcn_readfirstlane((uint32_t)v.p0);
+    return u;
+}
+
+// Tile t, read as one 16-byte word from a wave-uniform address.
+__device__ __forceinline__ DevTile read_tile(const DevTile *__restrict__ tiles, int t)
+{
+    const uint4 w = reinterpret_cast<const uint4 *>(tiles)[t];
+    DevTile v;
+    v.gen = w.x;
+    v.k0 = (uint16_t)(w.y & 0xFFFFu);
+    v.D = (uint16_t)(w.y >> 16);
+    v.p0 = ((uint64_t)w.w << 32) | w.z;
+    return uniform_tile(v);
+}
+
+// Marks every loaded dword of a strip as read, on every path through the
+// products (rows past N skip them): the compiler then knows no load into these
+// registers is still in flight when the next burst reuses them, and does not
+// make that burst wait for the stores in flight as well.
+template <int SK>
+__device__ __forceinline__ void hold(const uint32_t (&x)[SK][4])
+{
+#pragma unroll
+    for (int i = 0; i < SK; i++)
+#pragma unroll
+        for (int d = 0; d < 4; d++)
+            asm volatile("" ::"v"(x[i][d]));
+}
+
+// One tile of the streaming form.  The claim of the wave's next tile comes
+// first (it touches memory only when the wave's run of tiles is used up),
+// then the K x N coefficient bytes and the first burst; the next tile's
+// descriptor is read while the burst is in flight, and the coefficients'
+// product tables are looked up in the block's LDS copy of the field table
+// and staged once the burst has arrived.  Returns the next tile (or -1) with
+// its descriptor in `next`.
+template <int SK, int B>
+__device__ __forceinline__ int stream_tile(const DevGen &g, const DevTile &tl, SmallStage<SK> &st,
+                                           const uint4 *field_tab, int lane, const DevTile *__restrict__ tiles,
+                                           const unsigned *__restrict__ runs, const unsigned *__restrict__ bounds,
+                                           unsigned *counters, QueueCursor &cursor, DevTile &next)
+{
+    const int tn = queue_next_tile_wave(counters, runs, bounds, cursor, lane);
+    const int K = (int)g.K, N = (int)g.N, last = tl.D >> 8;   // strips 0 .. last
+    const uint64_t p0 = tl.p0 + (uint64_t)lane * 16u;
+    const int k = lane / SK, i = lane % SK;
+    const bool has_c = lane < SK * SK && k < K && i < N;
+    // every lane reads a coefficient byte (lanes past K x N read C[0])
+    uint32_t c = gld<uint8_t>(g.C + (has_c ? (uint64_t)k * N + i : 0));
+    // a burst past the tile's last strip re-reads the last one, multiplies it
+    // and drops the products, so that every load feeds a product
+    uint32_t x[B][SK][4];
+#pragma unroll
+    for (int u = 0; u < B; u++)
+        small_load<SK>(g.S, g.ld_s, N, p0 + (uint64_t)min(u, last) * 1024u, g.len, x[u]);
+    if (tn >= 0)
+        next = read_tile(tiles, tn);
+    c = has_c ? c : 0u;
+    wave_sync();
+    if (lane < SK * SK) {   // one (row, source) pair per lane; zero tables past K or N
+        st.t[k][i][0] = field_tab[c * 2];
+        st.t[k][i][1] = field_tab[c * 2 + 1];
+    }
+    wave_sync();
+#pragma unroll
+    for (int u = 0; u < B; u++) {
+        small_strip<SK>(st, K, N, g.Y, g.ld_y, p0 + (uint64_t)min(u, last) * 1024u, g.len, true, x[u], u <= last);
+        hold<SK>(x[u]);
+    }
+    for (int s0 = B; s0 <= last; s0 += B) {
+#pragma unroll
+        for (int u = 0; u < B; u++)
+            small_load<SK>(g.S, g.ld_s, N, p0 + (uint64_t)min(s0 + u, last) * 1024u, g.len, x[u]);
+#pragma unroll
+        for (int u = 0; u < B; u++) {
+            small_strip<SK>(st, K, N, g.Y, g.ld_y, p0 + (uint64_t)min(s0 + u, last) * 1024u, g.len, true, x[u],
+                            s0 + u <= last);
+            hold<SK>(x[u]);
+        }
+    }
+    return tn;
+}
+
+// Waves per SIMD each instance is built for: every burst reads about 8 KiB,
+// and the more waves share a SIMD, the more bursts are in flight.
+constexpr int stream_waves(int sk) { return sk <= 1 ? 7 : sk <= 2 ? 4 : sk <= 4 ? 3 : 2; }
+
+template <int SK, int B>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stream_waves(SK)))) void k_encode_stream(const DevGen *__restrict__ gens,
                                                        const DevTile *__restrict__ tiles,
                                                        const unsigned *__restrict__ runs,
                                                        const unsigned *__restrict__ bounds, unsigned *counters,
                                                        const uint4 *__restrict__ ptab4)
 {
+    __shared__ uint4 field_tab[256 * 2];
     __shared__ SmallStage<SK> stage[WAVES];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    SmallStage<SK> &st = stage[wave];
+    for (int e = threadIdx.x; e < 256 * 2; e += 256)
+        field_tab[e] = ptab4[e];
+    __syncthreads();
     QueueCursor cursor;
-    for (;;) {
-        int t = 0;
-        if (lane == 0)
-            t = queue_next_tile(counters, runs, bounds, cursor);
-        t = __builtin_amdgcn_readlane(t, 0);
-        if (t < 0)
-            break;
-        const DevTile tl = tiles[t];
+    int t = queue_next_tile_wave(counters, runs, bounds, cursor, lane);
+    DevTile tl{};
+    if (t >= 0)
+        tl = read_tile(tiles, t);
+    while (t >= 0) {
         const DevGen g = gens[tl.gen];
-        if (g.status && *g.status != g.need)
-            continue;
-        const int K = (int)g.K, N = (int)g.N, strips = (tl.D >> 8) + 1;
-        wave_sync();
-        if (lane < SK * SK) {   // tables of the K x N coefficients, one (row, source) pair per lane
-            const int k = lane / SK, i = lane % SK;
-            const uint32_t c = (k < K && i < N) ? (uint32_t)gld<uint8_t>(g.C + (uint64_t)k * N + i) : 0u;
-            st.t[k][i][0] = ptab4[c * 2];
-            st.t[k][i][1] = ptab4[c * 2 + 1];
+        DevTile next{};
+        int tn;
+        const bool run = !g.status || __builtin_amdgcn_readfirstlane((uint32_t)*g.status) == (uint32_t)g.need;
+        if (!run) {   // a generation not to run: claim the next tile
+            tn = queue_next_tile_wave(counters, runs, bounds, cursor, lane);
+            if (tn >= 0)
+                next = read_tile(tiles, tn);
+        } else {
+            tn = stream_tile<SK, B>(g, tl, stage[wave], field_tab, lane, tiles, runs, bounds, counters, cursor,
+                                    next);
         }
-        wave_sync();
-        const bool vec = g.align >= 16;
-        const uint64_t p0 = tl.p0 + (uint64_t)lane * 16u;
-        uint32_t x[DEPTH][SK][4];
-#pragma unroll
-        for (int u = 0; u + 1 < DEPTH; u++)
-            if (u < strips)
-                small_load<SK>(g.S, g.ld_s, N, p0 + (uint64_t)u * 1024u, g.len, vec, x[u]);
-        for (int q = 0; q < strips; q += DEPTH) {
-#pragma unroll
-            for (int u = 0; u < DEPTH; u++) {
-                const int sidx = q + u;
-                if (sidx >= strips)
-                    break;
-                const int nxt = sidx + DEPTH - 1;
-                if (nxt < strips)
-                    small_load<SK>(g.S, g.ld_s, N, p0 + (uint64_t)nxt * 1024u, g.len, vec, x[(u + DEPTH - 1) % DEPTH]);
-                small_strip<SK>(st, K, N, g.Y, g.ld_y, p0 + (uint64_t)sidx * 1024u, g.len, vec, x[u]);
-            }
-        }
+        // the loop's control stays scalar: the next tile's index and descriptor as lane 0 has them
+        t = __builtin_amdgcn_readfirstlane(tn);
+        tl = uniform_tile(next);
     }
     if (lane == 0)
         queue_retire(counters, gridDim.x * WAVES);
@@ -739,9 +949,9 @@ __device__ __forceinline__ void wave_tile_planes(const uint8_t *__restrict__ C, 
     // the pair of sources in use; the next pair is loaded while it is used
     const uint8_t *src = S + p;
     uint32_t xa[D], xb[D];
-    load_lane<D>(src, avail, vec, xa);
+    load_row<D>(src, p, avail, vec, xa);
     if (N > 1)
-        load_lane<D>(src + ld_s, avail, vec, xb);
+        load_row<D>(src + ld_s, p, avail, vec, xb);
     else
 #pragma unroll
         for (int d = 0; d < D; d++)
@@ -776,9 +986,9 @@ __device__ __forceinline__ void wave_tile_planes(const uint8_t *__restrict__ C, 
         }
         // a missing source reads as zero (its masks are zero as well)
         if (g + 2 < N)
-            load_lane<D>(src + (uint64_t)(g + 2) * ld_s, avail, vec, xa);
+            load_row<D>(src + (uint64_t)(g + 2) * ld_s, p, avail, vec, xa);
         if (g + 3 < N)
-            load_lane<D>(src + (uint64_t)(g + 3) * ld_s, avail, vec, xb);
+            load_row<D>(src + (uint64_t)(g + 3) * ld_s, p, avail, vec, xb);
         else
 #pragma unroll
             for (int d = 0; d < D; d++)
@@ -1439,17 +1649,20 @@ hipError_t launch_region_batched(const void *d_regions, int count, uint64_t max_
         }
         return hipSuccess;
     }
-    const uint64_t vpr = (max_len + 15) / 16;
-    const uint64_t total = vpr * (uint64_t)count;
-    if (total >= (1ull << 52))
-        return hipErrorInvalidValue;
-    // enough workgroups to keep every CU's waves busy; each thread then walks
-    // its pieces two at a time
-    const uint64_t want = (total + 511) / 512;
-    const unsigned blocks = (unsigned)std::min<uint64_t>(std::max<uint64_t>(want, 1), 256ull * 32);
-    hipLaunchKernelGGL(k_region_batched, dim3(blocks), dim3(256), 0, s,
-                       reinterpret_cast<const RegionDesc *>(d_regions), reinterpret_cast<const uint4 *>(ptab_field), q,
-                       total, (uint32_t)vpr, 1.0 / (double)vpr);
+    // shorter regions: a wave each, M 1024-byte rounds per lane
+    const int M = (int)((max_len + 1023) / 1024);
+    const unsigned blocks = (unsigned)std::min<uint64_t>((uint64_t)(count + REGION_WAVES - 1) / REGION_WAVES,
+                                                         256ull * 8);
+    const RegionDesc *r = reinterpret_cast<const RegionDesc *>(d_regions);
+    const uint4 *pt = reinterpret_cast<const uint4 *>(ptab_field);
+    if (M <= 1)
+        hipLaunchKernelGGL(k_region_waves<1>, dim3(blocks), dim3(256), 0, s, r, pt, q, count);
+    else if (M == 2)
+        hipLaunchKernelGGL(k_region_waves<2>, dim3(blocks), dim3(256), 0, s, r, pt, q, count);
+    else if (M == 3)
+        hipLaunchKernelGGL(k_region_waves<3>, dim3(blocks), dim3(256), 0, s, r, pt, q, count);
+    else
+        hipLaunchKernelGGL(k_region_waves<4>, dim3(blocks), dim3(256), 0, s, r, pt, q, count);
     return hipGetLastError();
 }
 
@@ -1544,9 +1757,9 @@ hipError_t launch_encode_planes(int field, const DevGen *gens, const DevTile *ti
 static const void *stream_kernel(int sk)
 {
     return sk <= 1   ? reinterpret_cast<const void *>(&k_encode_stream<1, 8>)
-           : sk <= 2 ? reinterpret_cast<const void *>(&k_encode_stream<2, 6>)
-           : sk <= 4 ? reinterpret_cast<const void *>(&k_encode_stream<4, 4>)
-                     : reinterpret_cast<const void *>(&k_encode_stream<8, 2>);
+           : sk <= 2 ? reinterpret_cast<const void *>(&k_encode_stream<2, 4>)
+           : sk <= 4 ? reinterpret_cast<const void *>(&k_encode_stream<4, 2>)
+                     : reinterpret_cast<const void *>(&k_encode_stream<8, 1>);
 }
 
 hipError_t launch_encode_stream(int sk, const DevGen *gens, const DevTile *tiles, const unsigned *runs,
@@ -1559,11 +1772,11 @@ hipError_t launch_encode_stream(int sk, const DevGen *gens, const DevTile *tiles
     if (sk <= 1)
         hipLaunchKernelGGL((k_encode_stream<1, 8>), dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters, pt);
     else if (sk <= 2)
-        hipLaunchKernelGGL((k_encode_stream<2, 6>), dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters, pt);
+        hipLaunchKernelGGL((k_encode_stream<2, 4>), dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters, pt);
     else if (sk <= 4)
-        hipLaunchKernelGGL((k_encode_stream<4, 4>), dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters, pt);
+        hipLaunchKernelGGL((k_encode_stream<4, 2>), dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters, pt);
     else
-        hipLaunchKernelGGL((k_encode_stream<8, 2>), dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters, pt);
+        hipLaunchKernelGGL((k_encode_stream<8, 1>), dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters, pt);
     return hipGetLastError();
 }
 

@@ -596,10 +596,12 @@ def test_binding_rejects_host_and_short_buffers(gf):
 @pytest.mark.parametrize("smax", [1, 2, 3, 8])
 @pytest.mark.parametrize("aligned", [True, False])
 def test_stream_form_small_generations(gf, n, smax, aligned):
-    """Form 4 (small generations streamed through a software pipeline; the kernel
-    instance follows the batch's largest K or N): every byte equals the oracle's,
-    on generations of one to many 1 KiB strips, tiles of 64 strips and ragged
-    ends, 16-byte aligned rows and odd ones (byte path); padding untouched."""
+    """Form 4 (small generations streamed in bursts of strips; the kernel instance
+    follows the batch's largest K or N): every byte equals the oracle's, on
+    generations of one to many 1 KiB strips, tiles of 64 strips and ragged ends
+    (whose last 16-byte block is read whole and written only up to the row's
+    end); padding untouched.  Rows that are not 16-byte aligned are refused by
+    form 4, and the autotuned plan over them (another form) matches as well."""
     torch = torch_cuda()
     items, wants = [], []
     for i in range(40):
@@ -612,8 +614,15 @@ def test_stream_form_small_generations(gf, n, smax, aligned):
         _, Sd = padded_rows(g.S, ld, 0 if aligned else 1)
         yb, Yd = padded_rows(np.zeros((K, L), np.uint8), ld, fill=0x5A)
         items.append((dev(g.C), Sd, Yd, yb, K, L, ld))
-    plan = gf.gf_plan_encode(n, [(C, S, Y) for C, S, Y, _, _, _, _ in items], tune={"form": 4})
-    assert plan.tuning()["form"] == 4
+    gens = [(C, S, Y) for C, S, Y, _, _, _, _ in items]
+    if aligned:
+        plan = gf.gf_plan_encode(n, gens, tune={"form": 4})
+        assert plan.tuning()["form"] == 4
+    else:
+        with pytest.raises(gf.GFError):      # form 4 reads whole 16-byte blocks
+            gf.gf_plan_encode(n, gens, tune={"form": 4})
+        plan = gf.gf_plan_encode(n, gens)
+        assert plan.tuning()["form"] != 4
     for rep in range(2):
         for _, _, Yd, _, _, _, _ in items:
             Yd.fill_(0x5A)
