@@ -684,13 +684,55 @@ __device__ __forceinline__ void hold(const uint32_t (&x)[SK][4])
             asm volatile("" ::"v"(x[i][d]));
 }
 
+// One burst of R strips from strip s0: the R strips' loads go out back to
+// back, then (first burst of a tile) the coefficients' product tables are
+// looked up in the block's LDS copy of the field table and staged, then the
+// strips are multiplied and stored in order.
+template <int SK, int R>
+__device__ __forceinline__ void stream_burst(const DevGen &g, int K, int N, uint64_t p0, int s0, SmallStage<SK> &st,
+                                             const uint4 *field_tab, int lane, bool first, uint32_t c, bool has_c)
+{
+    uint32_t x[R][SK][4];
+#pragma unroll
+    for (int u = 0; u < R; u++)
+        small_load<SK>(g.S, g.ld_s, N, p0 + (uint64_t)(s0 + u) * 1024u, g.len, x[u]);
+    if (first) {
+        const int k = lane / SK, i = lane % SK;
+        const uint32_t cv = has_c ? c : 0u;
+        wave_sync();
+        if (lane < SK * SK) {   // one (row, source) pair per lane; zero tables past K or N
+            st.t[k][i][0] = field_tab[cv * 2];
+            st.t[k][i][1] = field_tab[cv * 2 + 1];
+        }
+        wave_sync();
+    }
+#pragma unroll
+    for (int u = 0; u < R; u++) {
+        small_strip<SK>(st, K, N, g.Y, g.ld_y, p0 + (uint64_t)(s0 + u) * 1024u, g.len, true, x[u]);
+        hold<SK>(x[u]);
+    }
+}
+
+// The strips s0 .. s0 + rem - 1 (rem < B) as one burst of exactly that many.
+template <int SK, int R>
+__device__ __forceinline__ void stream_rest(const DevGen &g, int K, int N, uint64_t p0, int s0, int rem,
+                                            SmallStage<SK> &st, const uint4 *field_tab, int lane, bool first,
+                                            uint32_t c, bool has_c)
+{
+    if constexpr (R >= 1) {
+        if (rem == R)
+            stream_burst<SK, R>(g, K, N, p0, s0, st, field_tab, lane, first, c, has_c);
+        else
+            stream_rest<SK, R - 1>(g, K, N, p0, s0, rem, st, field_tab, lane, first, c, has_c);
+    }
+}
+
 // One tile of the streaming form.  The claim of the wave's next tile comes
 // first (it touches memory only when the wave's run of tiles is used up),
 // then the K x N coefficient bytes and the first burst; the next tile's
-// descriptor is read while the burst is in flight, and the coefficients'
-// product tables are looked up in the block's LDS copy of the field table
-// and staged once the burst has arrived.  Returns the next tile (or -1) with
-// its descriptor in `next`.
+// descriptor is read while the burst is in flight.  Bursts are B strips, the
+// last one exactly the strips that are left.  Returns the next tile (or -1)
+// with its descriptor in `next`.
 template <int SK, int B>
 __device__ __forceinline__ int stream_tile(const DevGen &g, const DevTile &tl, SmallStage<SK> &st,
                                            const uint4 *field_tab, int lane, const DevTile *__restrict__ tiles,
@@ -698,49 +740,28 @@ __device__ __forceinline__ int stream_tile(const DevGen &g, const DevTile &tl, S
                                            unsigned *counters, QueueCursor &cursor, DevTile &next)
 {
     const int tn = queue_next_tile_wave(counters, runs, bounds, cursor, lane);
-    const int K = (int)g.K, N = (int)g.N, last = tl.D >> 8;   // strips 0 .. last
+    const int K = (int)g.K, N = (int)g.N, n = (tl.D >> 8) + 1;   // strips of the tile
     const uint64_t p0 = tl.p0 + (uint64_t)lane * 16u;
     const int k = lane / SK, i = lane % SK;
     const bool has_c = lane < SK * SK && k < K && i < N;
     // every lane reads a coefficient byte (lanes past K x N read C[0])
-    uint32_t c = gld<uint8_t>(g.C + (has_c ? (uint64_t)k * N + i : 0));
-    // a burst past the tile's last strip re-reads the last one, multiplies it
-    // and drops the products, so that every load feeds a product
-    uint32_t x[B][SK][4];
-#pragma unroll
-    for (int u = 0; u < B; u++)
-        small_load<SK>(g.S, g.ld_s, N, p0 + (uint64_t)min(u, last) * 1024u, g.len, x[u]);
+    const uint32_t c = gld<uint8_t>(g.C + (has_c ? (uint64_t)k * N + i : 0));
     if (tn >= 0)
         next = read_tile(tiles, tn);
-    c = has_c ? c : 0u;
-    wave_sync();
-    if (lane < SK * SK) {   // one (row, source) pair per lane; zero tables past K or N
-        st.t[k][i][0] = field_tab[c * 2];
-        st.t[k][i][1] = field_tab[c * 2 + 1];
+    int s0 = 0;
+    bool first = true;
+    for (; s0 + B <= n; s0 += B) {
+        stream_burst<SK, B>(g, K, N, p0, s0, st, field_tab, lane, first, c, has_c);
+        first = false;
     }
-    wave_sync();
-#pragma unroll
-    for (int u = 0; u < B; u++) {
-        small_strip<SK>(st, K, N, g.Y, g.ld_y, p0 + (uint64_t)min(u, last) * 1024u, g.len, true, x[u], u <= last);
-        hold<SK>(x[u]);
-    }
-    for (int s0 = B; s0 <= last; s0 += B) {
-#pragma unroll
-        for (int u = 0; u < B; u++)
-            small_load<SK>(g.S, g.ld_s, N, p0 + (uint64_t)min(s0 + u, last) * 1024u, g.len, x[u]);
-#pragma unroll
-        for (int u = 0; u < B; u++) {
-            small_strip<SK>(st, K, N, g.Y, g.ld_y, p0 + (uint64_t)min(s0 + u, last) * 1024u, g.len, true, x[u],
-                            s0 + u <= last);
-            hold<SK>(x[u]);
-        }
-    }
+    if (s0 < n)
+        stream_rest<SK, B - 1>(g, K, N, p0, s0, n - s0, st, field_tab, lane, first, c, has_c);
     return tn;
 }
 
 // Waves per SIMD each instance is built for: every burst reads about 8 KiB,
 // and the more waves share a SIMD, the more bursts are in flight.
-constexpr int stream_waves(int sk) { return sk <= 1 ? 7 : sk <= 2 ? 4 : sk <= 4 ? 3 : 2; }
+constexpr int stream_waves(int sk) { return sk <= 1 ? 6 : sk <= 2 ? 4 : sk <= 4 ? 3 : 2; }
 
 template <int SK, int B>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stream_waves(SK)))) void k_encode_stream(const DevGen *__restrict__ gens,
