@@ -141,6 +141,12 @@ def make_parser() -> argparse.ArgumentParser:
                     choices=[name for name, _ in EXTRA_PARTS] + ["serve"],
                     help="run just this one of the other workloads (or the serving runs), print its JSON "
                          "and exit (for profiling one workload's kernels)")
+    ap.add_argument("--sweep-fields", default="1,2,4,8",
+                    help="word widths n of the field/length sweep (comma-separated; for profiling one point)")
+    ap.add_argument("--sweep-lengths", default="1500,9000,65536",
+                    help="packet lengths of the field/length sweep (comma-separated)")
+    ap.add_argument("--k-list", default="1,2,4,8,16,32,64,128,256",
+                    help="K = N values of the K sweep (comma-separated)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (to calibrate HBM counters) and exit")
     return ap
@@ -472,8 +478,8 @@ def part_sweep(gf, torch, args) -> dict:
     # ---- plain sweep: 4096 generations, N = K = 64, every field and packet length
     sweep = []
     count = 4096
-    for n in (1, 2, 4, 8):
-        for L in (1500, 9000, 65536):
+    for n in [int(v) for v in args.sweep_fields.split(",")]:
+        for L in [int(v) for v in args.sweep_lengths.split(",")]:
             plan, S, Cm, Y, ld = uniform_plan(gf, torch, synth.sweep_batch(n, L, count))
             ms = time_ms(torch, lambda: gf.gf_plan_launch_graph(plan), reps=3, warm=1)
             src = count * 64 * L
@@ -615,7 +621,7 @@ def part_k_sweep(gf, torch, args) -> dict:
     out = {}
     # ---- K sweep at 9000 B: where encode meets the HBM roofline
     ks = []
-    for K in (1, 2, 4, 8, 16, 32, 64, 128, 256):
+    for K in [int(v) for v in args.k_list.split(",")]:
         count = int(np.ceil(1e9 / (K * 9000)))
         plan, S, Cm, Y, ld = uniform_plan(gf, torch, synth.uniform_batch(8, K, K, 9000, count,
                                                                      synth.key(synth.BASE_SEED + 5, K)))
@@ -624,7 +630,8 @@ def part_k_sweep(gf, torch, args) -> dict:
         hbm = HBM_PEAK_GBS * (K * 9000) / (2 * K * 9000 + K * K)
         ks.append({"K": K, "N": K, "generations": count, "gbs": round(src / ms / 1e6, 2),
                    "hbm_roofline_gbs": round(hbm, 1), "hbm_frac": round(src / ms / 1e6 / hbm, 4),
-                   "byte_madds_per_s": round(K * src / ms * 1e3, 1), "form": plan.tuning()["form"]})
+                   "byte_madds_per_s": round(K * src / ms * 1e3, 1), "form": plan.tuning()["form"],
+                   "grid_blocks": plan.tuning()["grid_blocks"]})
         log("K sweep K=%d: %.1f GB/s (%.0f%% of HBM roofline, form %d)"
             % (K, src / ms / 1e6, 100 * src / ms / 1e6 / hbm, plan.tuning()["form"]))
         plan.destroy()

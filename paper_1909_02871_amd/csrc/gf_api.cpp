@@ -907,10 +907,15 @@ static int autotune(gf_plan *p, DevState *d, const std::vector<DevGen> &g, const
     if (best.ms < 0)
         return GF_EDEVICE;
     if (!(tune && tune->grid_blocks > 0)) {
+        // smaller grids while they keep winning: memory-bound forms can run
+        // faster with fewer waves in flight; stop two steps past the best
         const TuneChoice top = best;
-        for (int pct : {75, 50})
+        for (int pct : {75, 50, 35, 25, 18}) {
             if ((rc = consider(top.form, top.fixed_D, pct)))
                 return rc;
+            if (3 * pct < 2 * best.grid_pct)
+                break;
+        }
     }
     p->fixed_D = best.fixed_D;
     if ((rc = make_schedule(p, d, g, best.form, tune, best.grid_pct)))

@@ -1186,17 +1186,33 @@ __device__ void invert_rows(uint32_t *A, RowOf row, int N, uint8_t *__restrict__
     load_matrix();
     sync();
 
+    // Two barriers per pivot in the usual case: (1) the pivot row is scaled
+    // while every thread reads the factors of its rows from column j into
+    // registers; (2) the rows are updated, their table lookups independent of
+    // one another.  The pivot is row j itself when its entry in column j is
+    // nonzero (a random matrix almost always has one); only otherwise is the
+    // column searched and a lower row swapped in.
+    constexpr int RPT = (MAXN + RS - 1) / RS;   // rows per thread
     bool singular = false;
     for (int j = 0; j < N; j++) {
-        const int pr = find_pivot(j, j);
-        if (pr >= N) {
-            singular = true;
-            break;
+        int pr = j;
+        if (__builtin_amdgcn_readfirstlane((uint32_t)Ab[j * (4 * PRW) + j]) == 0) {
+            pr = find_pivot(j, j + 1);
+            if (pr >= N) {
+                singular = true;
+                break;
+            }
+            swap_rows(pr, j);
+            sync();
         }
-        swap_rows(pr, j);
         if (tid == 0)
             piv[j] = pr;
-        sync();
+        uint32_t f[RPT];
+#pragma unroll
+        for (int m = 0; m < RPT; m++) {
+            const int i = r0 + m * RS;
+            f[m] = (i < N && i != j) ? (uint32_t)Ab[i * (4 * PRW) + j] : 0u;
+        }
         if (tid < NW) {   // wave 0 only: reads below happen before the write
             uint32_t a = A[j * PRW + tid];
             const uint32_t pinv = IV[Ab[j * (4 * PRW) + j]];
@@ -1204,24 +1220,23 @@ __device__ void invert_rows(uint32_t *A, RowOf row, int N, uint8_t *__restrict__
                 a = (a & ~(0xFFu << (8 * (j & 3)))) | (1u << (8 * (j & 3)));
             A[j * PRW + tid] = prod4(T[pinv][0], T[pinv][1].x, a);
         }
-        if (tid < N)
-            fcol[tid] = tid == j ? 0 : Ab[tid * (4 * PRW) + j];
         sync();
         if (cl < NW) {   // thread: column dword cl of rows r0, r0 + RS, ...
-            // branch-free: where fcol is 0 the row's byte j is 0 already and the
-            // product is 0 (row j itself, whose fcol is 0, keeps its leading 1)
+            // branch-free: where f is 0 the row's byte j is 0 already and the
+            // product is 0 (row j itself, whose f is 0, keeps its leading 1)
             const uint32_t pj = A[j * PRW + cl];
             const uint32_t keep = cl == (j >> 2) ? ~(0xFFu << (8 * (j & 3))) : 0xFFFFFFFFu;
-#pragma unroll 4
-            for (int i = r0; i < N; i += RS) {
-                const uint32_t f = fcol[i];
-                const uint32_t k = i == j ? 0xFFFFFFFFu : keep;
-                A[i * PRW + cl] = (A[i * PRW + cl] & k) ^ prod4(T[f][0], T[f][1].x, pj);
+#pragma unroll
+            for (int m = 0; m < RPT; m++) {
+                const int i = r0 + m * RS;
+                if (i < N) {
+                    const uint32_t k = i == j ? 0xFFFFFFFFu : keep;
+                    A[i * PRW + cl] = (A[i * PRW + cl] & k) ^ prod4(T[f[m]][0], T[f[m]][1].x, pj);
+                }
             }
         }
         sync();
     }
-
     if (!singular) {
         if (tid == 0) {
             for (int c = 0; c < N; c++)
@@ -1672,8 +1687,10 @@ hipError_t launch_region_batched(const void *d_regions, int count, uint64_t max_
     }
     // shorter regions: a wave each, M 1024-byte rounds per lane
     const int M = (int)((max_len + 1023) / 1024);
+    // four workgroups per CU: measured faster than eight (more waves add
+    // memory traffic in flight without adding bandwidth) and than two
     const unsigned blocks = (unsigned)std::min<uint64_t>((uint64_t)(count + REGION_WAVES - 1) / REGION_WAVES,
-                                                         256ull * 8);
+                                                         256ull * 4);
     const RegionDesc *r = reinterpret_cast<const RegionDesc *>(d_regions);
     const uint4 *pt = reinterpret_cast<const uint4 *>(ptab_field);
     if (M <= 1)
