@@ -61,12 +61,12 @@ def _profile_bench_commands():
         blocks = re.findall(r"```\n(.*?)```", text, flags=re.S)
         for line in "\n".join(blocks).splitlines():
             line = line.strip()
-            m = re.match(r'B="python3 <repo>/bench\.py([^"]*)"', line)
+            m = re.match(r'[A-Z][A-Z0-9_]*="python3 <repo>/bench\.py([^"]*)"', line)
             if m:
                 cmds.append((os.path.basename(path), shlex.split(m.group(1))))
             elif "bench.py" in line:
                 tail = line.split("bench.py", 1)[1]
-                cmds.append((os.path.basename(path), [t for t in shlex.split(tail) if t != "$B"]))
+                cmds.append((os.path.basename(path), [t for t in shlex.split(tail) if not t.startswith("$")]))
     return cmds
 
 
