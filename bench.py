@@ -305,7 +305,7 @@ def main():
     ceil = measure_ceilings(gf, torch)
     ceil["torch_copy_gbs"] = round(stream_copy_gbs(torch), 1)
     roofline["measured_ceilings"] = ceil
-    roofline["frac_of_measured_copy"] = round(achieved / ceil["copy_gbs"], 4)
+    roofline["frac_of_measured_copy"] = round(achieved / max(ceil["copy_gbs"], ceil["copy_chunks_gbs"]), 4)
     if tuning["form"] == 2:
         roofline["compute"]["frac_of_measured_fp4"] = round(roofline["compute"]["achieved"] / ceil["fp4_mfma_tflops"], 4)
     log("roofline: %.1f GB/s of algorithmic HBM bytes = %.3f of 8 TB/s; measured ceilings %s"
@@ -695,6 +695,8 @@ def measure_ceilings(gf, torch) -> dict:
     buf = torch.empty(4 << 30, dtype=torch.uint8, device="cuda")
     t = min(timed(0, buf, cus * 32, 0) for _ in range(3))
     out["copy_gbs"] = round(buf.numel() / t / 1e9, 1)                  # half read + half written
+    t = min(timed(4, buf, 1, 0) for _ in range(3))
+    out["copy_chunks_gbs"] = round(buf.numel() / t / 1e9, 1)           # the same, a workgroup per 16 KiB
     small = torch.empty(cus * 64 * 1024, dtype=torch.uint8, device="cuda")
     blocks, iters = cus * 8, 4000
     t = timed(1, small, blocks, iters)

@@ -188,13 +188,18 @@ typedef struct {
  *         in bursts of about 8 KiB per wave; only when every generation has
  *         K <= 8 and N <= 8 and its rows (S, Y, ld_s, ld_y) are 16-byte
  *         aligned (GF_EINVAL otherwise).
+ * form 5: form 4's generations without work queues: one wave per run of
+ *         at most about 8 KiB of one generation's strips, one workgroup per
+ *         four runs, as many workgroups as runs need (grid_blocks ignored);
+ *         the same conditions as form 4.
  * form 0 on an encode plan made with pointers: every form that applies is
  * timed on the plan's own batch while the plan is created (which writes the
  * plan's outputs) and the fastest is kept (form 2 is skipped if a packet is
  * too long for it); on a plan made from shapes alone, or a decode plan, form 0
  * means form 2 when every source row starts 4-byte aligned, else 1. */
 typedef struct {
-    int form;           /* 0 auto, 1 table, 2 bit-matrix, 3 bit-plane, 4 small-generation stream */
+    int form;           /* 0 auto, 1 table, 2 bit-matrix, 3 bit-plane, 4 small-generation stream,
+                           5 small-generation chunks */
     int bytes_per_lane; /* 0 = per tile; else 4, 8 or 16 payload bytes per lane everywhere */
     int grid_blocks;    /* persistent workgroups; 0 = as many as fit on the GPU at once */
     int reserved;       /* must be 0 */
@@ -271,7 +276,9 @@ void gf_plan_destroy(gf_plan *plan);
  * and iteration), 2 back-to-back FP4 32x32x64 MFMAs (8 per wave and
  * iteration), 3 the bit-plane form's step (64 three-input bit operations per
  * thread and iteration), each on blocks x 256 threads for `iters` iterations,
- * writing one word per thread to d_buf (bytes >= blocks * 1024).  Time it on
+ * writing one word per thread to d_buf (bytes >= blocks * 1024); what 4
+ * makes what 0's copy with one workgroup per 16 KiB instead of a grid-stride
+ * loop (blocks must be >= 1 and is otherwise unused, as is iters).  Time it on
  * `stream` with events. */
 int gf_ceiling(int what, void *d_buf, size_t bytes, int blocks, int iters, void *stream);
 

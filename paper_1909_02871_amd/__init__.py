@@ -429,8 +429,8 @@ def gf_plan_launch_graph(plan: Plan, d_rank=None, stream=None):
 
 
 def gf_ceiling(what: int, buf, blocks: int, iters: int, stream=None):
-    """Diagnostic microbenchmark (0 copy, 1 table step, 2 FP4 MFMA, 3 bit-plane step) on the CUDA
-    uint8 tensor ``buf`` (enqueued; time it with events)."""
+    """Diagnostic microbenchmark (0 copy, 1 table step, 2 FP4 MFMA, 3 bit-plane step, 4 copy by
+    16 KiB chunks) on the CUDA uint8 tensor ``buf`` (enqueued; time it with events)."""
     _dev_u8(buf, "buf")
     _check(lib().gf_ceiling(what, buf.data_ptr(), buf.numel(), blocks, iters, _stream(stream)), "gf_ceiling")
 

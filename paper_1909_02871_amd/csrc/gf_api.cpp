@@ -209,7 +209,7 @@ struct gf_plan {
     DevGen *d_bound = nullptr;      // the same shapes with the pointers of gf_encode_batched's descriptors
     unsigned *d_err = nullptr;      // [0] descriptors refused by that call, [1] = 1 (status of a refused one)
     bool shape_only = false;        // made from shapes alone (no pointers to run on)
-    bool small_ok = false;          // every generation has K, N <= STREAM_MAX and 16-byte aligned rows (form 4 applies)
+    bool small_ok = false;          // every generation has K, N <= STREAM_MAX and 16-byte aligned rows (forms 4 and 5 apply)
     int small_max = 0;              // the largest K or N of the batch
     DevTile *d_tiles = nullptr;
     unsigned *d_runs = nullptr;     // first tile of each run, then the queue bounds
@@ -708,6 +708,23 @@ void build_tiles_stream(const DevGen *g, size_t n, TileQueues &q)
     build_queues(tiles, 262144.0, q);
 }
 
+// Chunked streaming form: each generation's strips of 1 KiB in runs of equal
+// length (at most `burst` strips), in generation order.
+void build_tiles_chunks(const DevGen *g, size_t n, int burst, std::vector<DevTile> &tiles)
+{
+    for (size_t i = 0; i < n; i++) {
+        const DevGen &x = g[i];
+        if (x.K == 0 || x.len == 0)
+            continue;
+        const uint64_t ns = (x.len + 1023) / 1024;
+        const uint64_t runs = (ns + burst - 1) / burst;
+        for (uint64_t r = 0; r < runs; r++) {
+            const uint64_t s0 = r * ns / runs, s1 = (r + 1) * ns / runs;
+            tiles.push_back(DevTile{(uint32_t)i, 0, (uint16_t)(4 | ((s1 - s0 - 1) << 8)), s0 * 1024});
+        }
+    }
+}
+
 }  // namespace gfnc
 
 // One launch of the plan's persistent kernel over the generation table
@@ -726,6 +743,8 @@ static int launch_schedule(gf_plan *p, DevState *d, hipStream_t s, const DevGen 
     else if (p->form == 4)
         e = launch_encode_stream(p->small_max, gens, p->d_tiles, p->d_runs, p->d_bounds, p->ntiles, p->d_ctr,
                                  p->grid, field_ptab(d, f), s);
+    else if (p->form == 5)
+        e = launch_encode_chunks(p->small_max, gens, p->d_tiles, p->ntiles, field_ptab(d, f), s);
     else
         e = launch_encode_persistent(gens, p->d_tiles, p->d_runs, p->d_bounds, p->ntiles, p->d_ctr, p->grid,
                                      field_ptab(d, f), s);
@@ -751,6 +770,8 @@ static int make_schedule(gf_plan *p, DevState *d, const std::vector<DevGen> &g, 
         build_tiles_mfma(g.data(), g.size(), tq);
     else if (form == 4)
         build_tiles_stream(g.data(), g.size(), tq);
+    else if (form == 5)
+        build_tiles_chunks(g.data(), g.size(), encode_chunks_strips(p->small_max), tq.tiles);
     else
         build_tiles(g.data(), g.size(), p->fixed_D, tq);
     (void)hipFree(p->d_tiles);
@@ -772,6 +793,8 @@ static int make_schedule(gf_plan *p, DevState *d, const std::vector<DevGen> &g, 
         grid = tune->grid_blocks;
     const int per_block = form == 2 ? 1 : 4;
     p->grid = std::max(1, std::min(grid, std::max(1, (p->ntiles + per_block - 1) / per_block)));
+    if (form == 5)   // not persistent: a workgroup per four tiles
+        p->grid = std::max(1, (p->ntiles + 3) / 4);
     return GF_OK;
 }
 
@@ -862,7 +885,7 @@ static int autotune(gf_plan *p, DevState *d, const std::vector<DevGen> &g, const
     const std::string key = tune_key(p->field, g, p->src_aligned4, 0, tune ? tune->bytes_per_lane : 0,
                                      tune ? tune->grid_blocks : 0);
     TuneChoice c;
-    if (tune_cache_get(key, &c) && (c.form != 3 || p->field <= 4) && (c.form != 4 || p->small_ok)) {
+    if (tune_cache_get(key, &c) && (c.form != 3 || p->field <= 4) && (c.form < 4 || p->small_ok)) {
         p->tuned_from_cache = true;
         p->fixed_D = (tune && tune->bytes_per_lane) ? tune->bytes_per_lane / 4 : c.fixed_D;
         return make_schedule(p, d, g, c.form, tune, c.grid_pct);
@@ -881,8 +904,10 @@ static int autotune(gf_plan *p, DevState *d, const std::vector<DevGen> &g, const
     for (int D : fixed_bpl ? std::vector<int>{D0} : std::vector<int>{0, 4, 2, 1})
         cands.push_back({1, D});
     cands.push_back({2, 0});
-    if (p->small_ok)
+    if (p->small_ok) {
         cands.push_back({4, 0});
+        cands.push_back({5, 0});
+    }
     if (p->field <= 4)
         for (int D : fixed_bpl ? std::vector<int>{D0} : std::vector<int>{0, 4})
             cands.push_back({3, D});
@@ -906,7 +931,7 @@ static int autotune(gf_plan *p, DevState *d, const std::vector<DevGen> &g, const
             return rc;
     if (best.ms < 0)
         return GF_EDEVICE;
-    if (!(tune && tune->grid_blocks > 0)) {
+    if (!(tune && tune->grid_blocks > 0) && best.form != 5) {
         // smaller grids while they keep winning: memory-bound forms can run
         // faster with fewer waves in flight; stop two steps past the best
         const TuneChoice top = best;
@@ -926,7 +951,8 @@ static int autotune(gf_plan *p, DevState *d, const std::vector<DevGen> &g, const
     return GF_OK;
 }
 
-// form: 1 table, 2 bit-matrix, 3 bit-plane (n <= 4); 0 = time each on the
+// form: 1 table, 2 bit-matrix, 3 bit-plane (n <= 4), 4 and 5 the small-generation
+// streaming forms (queued, chunked); 0 = time each on the
 // plan's own data and keep the fastest (only when `may_run` allows launching
 // before the caller asks).
 static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, const gf_tuning *tune, bool may_run)
@@ -941,7 +967,7 @@ static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, co
         p->fixed_D = tune->bytes_per_lane / 4;
     }
     int form = tune ? tune->form : 0;
-    if (form < 0 || form > 4 || (form == 3 && p->field > 4))
+    if (form < 0 || form > 5 || (form == 3 && p->field > 4))
         return GF_EINVAL;
     std::vector<DevGen> g = gens;
     p->src_aligned4 = true;
@@ -977,7 +1003,7 @@ static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, co
         return GF_EDEVICE;
     if (form == 2 && !mf_ok)
         return GF_ERANGE;
-    if (form == 4 && !p->small_ok)
+    if (form >= 4 && !p->small_ok)
         return GF_EINVAL;
     if (form == 0 && (!may_run || !mf_ok))   // no trial launches: the bit-matrix form when its DMA path applies
         form = p->src_aligned4 && mf_ok ? 2 : 1;
@@ -1415,9 +1441,9 @@ int gf_plan_launch_graph(gf_plan *p, int *d_rank, void *stream)
 
 int gf_ceiling(int what, void *d_buf, size_t bytes, int blocks, int iters, void *stream)
 {
-    if (what < 0 || what > 3 || !d_buf || blocks < 1 || iters < 0)
+    if (what < 0 || what > 4 || !d_buf || blocks < 1 || iters < 0)
         return GF_EINVAL;
-    if (what == 0 ? bytes < 64 : bytes < (size_t)blocks * 256 * sizeof(uint32_t))
+    if (what == 0 || what == 4 ? bytes < 64 : bytes < (size_t)blocks * 256 * sizeof(uint32_t))
         return GF_EINVAL;
     DevState *d;
     int rc = current_state(&d);

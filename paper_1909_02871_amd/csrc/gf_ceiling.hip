@@ -31,6 +31,27 @@ __global__ __launch_bounds__(256) void k_ceil_copy(const gf_u32x4 *__restrict__ 
         __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
+// The same copy with a workgroup per 16 KiB: thread t of workgroup b moves the
+// words b * 1024 + t + 256 u (u < 4), all four loads before the stores, and
+// no workgroup loops (the dispatcher hands out the next one as one retires).
+__global__ __launch_bounds__(256) void k_ceil_copy_chunks(const gf_u32x4 *__restrict__ src,
+                                                          gf_u32x4 *__restrict__ dst, uint64_t n16)
+{
+    const uint64_t i0 = (uint64_t)blockIdx.x * 1024u + threadIdx.x;
+    gf_u32x4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        const uint64_t i = i0 + 256u * u;
+        v[u] = __builtin_nontemporal_load(src + (i < n16 ? i : 0));
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        const uint64_t i = i0 + 256u * u;
+        if (i < n16)
+            __builtin_nontemporal_store(v[u], dst + i);
+    }
+}
+
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
 {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
@@ -121,7 +142,8 @@ __global__ __launch_bounds__(256) void k_ceil_planes(uint32_t *out, int iters, u
 }  // namespace
 
 // what: 0 copy (the first half of buf to the second), 1 table-form step,
-// 2 FP4 MFMA, 3 bit-plane step; blocks x 256 threads, `iters` steps each.
+// 2 FP4 MFMA, 3 bit-plane step; blocks x 256 threads, `iters` steps each;
+// 4 the copy by 16 KiB chunks (blocks and iters unused).
 hipError_t launch_ceiling(int what, void *buf, uint64_t bytes, int blocks, int iters, hipStream_t s)
 {
     const uint32_t seed = 0x2545F491u;
@@ -130,6 +152,15 @@ hipError_t launch_ceiling(int what, void *buf, uint64_t bytes, int blocks, int i
         const uint64_t n16 = bytes / 32;
         hipLaunchKernelGGL(k_ceil_copy, dim3(blocks), dim3(256), 0, s, static_cast<const gf_u32x4 *>(buf),
                            static_cast<gf_u32x4 *>(buf) + n16, n16);
+        break;
+    }
+    case 4: {
+        const uint64_t n16 = bytes / 32;
+        const uint64_t grid = (n16 + 1023) / 1024;
+        if (grid > 0x7FFFFFFFull)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_ceil_copy_chunks, dim3((unsigned)grid), dim3(256), 0, s,
+                           static_cast<const gf_u32x4 *>(buf), static_cast<gf_u32x4 *>(buf) + n16, n16);
         break;
     }
     case 1:

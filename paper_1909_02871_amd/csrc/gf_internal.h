@@ -153,6 +153,12 @@ hipError_t launch_encode_stream(int sk, const DevGen *gens, const DevTile *tiles
                                 const unsigned *bounds, int ntiles, unsigned *counters, int grid,
                                 const uint32_t *ptab_field, hipStream_t s);
 int encode_stream_blocks_per_cu(int sk);
+// The same generations without queues: one wave per tile of at most
+// encode_chunks_strips(sk) strips, a workgroup per four tiles.
+int encode_chunks_strips(int sk);
+void build_tiles_chunks(const DevGen *g, size_t n, int burst, std::vector<DevTile> &tiles);
+hipError_t launch_encode_chunks(int sk, const DevGen *gens, const DevTile *tiles, int ntiles,
+                                const uint32_t *ptab_field, hipStream_t s);
 // One matrix (sys == nullptr: C, N, Cinv, rank) or `count` systems of one size
 // class (N <= 32, 64, 128 or 256; N names the class), one workgroup each.
 hipError_t launch_invert(const DevSys *sys, int count, const uint8_t *C, int N, uint8_t *Cinv, int *rank,

@@ -227,29 +227,38 @@ struct RegionDesc {
 // byte, so reading it whole stays in mapped memory; only the bytes before
 // d.len are written back.  Unaligned regions load every byte first and then
 // store, so the wave waits for its loads once.
+// y[p .. p + 16) ^= c x[p .. p + 16) from loaded 16-byte pieces of an
+// aligned region, stored whole or (the region's last piece) by words and bytes
+// up to its end; nothing is stored for a piece at or past the end.
+__device__ __forceinline__ void region_store(uint8_t *y, uint64_t p, uint64_t len, const uint4 ta, uint32_t tb,
+                                             const gf_u32x4 &xv, gf_u32x4 v)
+{
+    v.x ^= prod4(ta, tb, xv.x);
+    v.y ^= prod4(ta, tb, xv.y);
+    v.z ^= prod4(ta, tb, xv.z);
+    v.w ^= prod4(ta, tb, xv.w);
+    if (p + 16 <= len) {
+        gst_nt<gf_u32x4>(y + p, v);
+    } else if (p < len) {
+        const int n = (int)(len - p);   // 1 .. 15 bytes left
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (4 * k + 4 <= n)
+                gst<uint32_t>(y + p + 4 * k, w[k]);
+#pragma unroll
+        for (int b = 0; b < 16; b++)
+            if (b >= (n & ~3) && b < n)
+                gst<uint8_t>(y + p + b, (uint8_t)(w[b >> 2] >> (8 * (b & 3))));
+    }
+}
+
 __device__ __forceinline__ void region_piece(const RegionDesc &d, uint64_t p, const uint4 ta, uint32_t tb)
 {
     if ((((uintptr_t)d.y | (uintptr_t)d.x) & 15u) == 0) {
         const gf_u32x4 a = gld_nt<gf_u32x4>(d.x + p);
-        gf_u32x4 yv = gld_nt<gf_u32x4>(d.y + p);
-        yv.x ^= prod4(ta, tb, a.x);
-        yv.y ^= prod4(ta, tb, a.y);
-        yv.z ^= prod4(ta, tb, a.z);
-        yv.w ^= prod4(ta, tb, a.w);
-        if (p + 16 <= d.len) {
-            gst_nt<gf_u32x4>(d.y + p, yv);
-        } else {
-            const int n = (int)(d.len - p);   // 1 .. 15 bytes left
-            const uint32_t w[4] = {yv.x, yv.y, yv.z, yv.w};
-#pragma unroll
-            for (int k = 0; k < 4; k++)
-                if (4 * k + 4 <= n)
-                    gst<uint32_t>(d.y + p + 4 * k, w[k]);
-#pragma unroll
-            for (int b = 0; b < 16; b++)
-                if (b >= (n & ~3) && b < n)
-                    gst<uint8_t>(d.y + p + b, (uint8_t)(w[b >> 2] >> (8 * (b & 3))));
-        }
+        const gf_u32x4 yv = gld_nt<gf_u32x4>(d.y + p);
+        region_store(d.y, p, d.len, ta, tb, a, yv);
     } else {
         const int n = (int)(min(d.len, p + 16) - p);
         uint32_t xb[16], yb[16];
@@ -267,7 +276,8 @@ __device__ __forceinline__ void region_piece(const RegionDesc &d, uint64_t p, co
 }
 
 // Batched madd of regions shorter than 4 KiB: one wave per region at a time
-// (regions dealt to the waves round robin), lane l taking the 16-byte pieces
+// (regions dealt to the waves round robin; the launcher starts a wave for
+// every region, so each takes one), lane l taking the 16-byte pieces
 // l, l + 64, ..., M per lane (M = 1024-byte rounds of the longest region).
 // Descriptors and the coefficient's tables are wave-uniform scalar loads, the
 // next region's read while the current one's pieces are in flight.  For
@@ -314,26 +324,7 @@ __global__ __launch_bounds__(256) void k_region_waves(const RegionDesc *__restri
                 // to wait on (they would wait for this region's stores too)
                 asm volatile("" ::"v"(xv[m].x), "v"(xv[m].y), "v"(xv[m].z), "v"(xv[m].w));
                 asm volatile("" ::"v"(yv[m].x), "v"(yv[m].y), "v"(yv[m].z), "v"(yv[m].w));
-                const uint64_t p = (uint64_t)(lane + 64 * m) * 16u;
-                gf_u32x4 v = yv[m];
-                v.x ^= prod4(ta, tb, xv[m].x);
-                v.y ^= prod4(ta, tb, xv[m].y);
-                v.z ^= prod4(ta, tb, xv[m].z);
-                v.w ^= prod4(ta, tb, xv[m].w);
-                if (p + 16 <= d.len) {
-                    gst_nt<gf_u32x4>(d.y + p, v);
-                } else if (p < d.len) {   // the region's last, partial piece
-                    const int n = (int)(d.len - p);
-                    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                    for (int k = 0; k < 4; k++)
-                        if (4 * k + 4 <= n)
-                            gst<uint32_t>(d.y + p + 4 * k, w[k]);
-#pragma unroll
-                    for (int b = 0; b < 16; b++)
-                        if (b >= (n & ~3) && b < n)
-                            gst<uint8_t>(d.y + p + b, (uint8_t)(w[b >> 2] >> (8 * (b & 3))));
-                }
+                region_store(d.y, (uint64_t)(lane + 64 * m) * 16u, d.len, ta, tb, xv[m], yv[m]);
             }
         } else if (live) {
 #pragma unroll
@@ -353,6 +344,8 @@ __global__ __launch_bounds__(256) void k_region_waves(const RegionDesc *__restri
 
 // Regions of 4 KiB and more: block (bx, r) handles bytes [bx*REGION_CHUNK, ...)
 // of region r, with the region's descriptor and tables loaded once per block.
+// (Two or four pieces per thread, loads first, measured slower at 9000 B and
+// 64 KiB.)
 constexpr int REGION_CHUNK = 256 * 16;   // bytes per block per region
 
 __global__ __launch_bounds__(256) void k_region_chunks(const RegionDesc *__restrict__ regs,
@@ -800,6 +793,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stream_wave
     }
     if (lane == 0)
         queue_retire(counters, gridDim.x * WAVES);
+}
+
+// The same small generations dealt out by the hardware instead of queues:
+// wave w of workgroup b takes tile 4b + w, a run of at most B strips of one
+// generation (its strips split into runs of equal length), as one burst, and
+// the launch has a workgroup per four tiles.  No wave outlives its burst, so
+// no loads wait behind a previous burst's stores; the coefficients' tables
+// come straight from the field table in global memory (a few L2 hits per
+// wave) instead of a per-workgroup LDS copy.
+template <int SK, int B>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stream_waves(SK)))) void k_encode_chunks(
+    const DevGen *__restrict__ gens, const DevTile *__restrict__ tiles, int ntiles, const uint4 *__restrict__ ptab4)
+{
+    __shared__ SmallStage<SK> stage[WAVES];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int t = __builtin_amdgcn_readfirstlane((int)blockIdx.x * WAVES + wave);
+    if (t >= ntiles)
+        return;
+    const DevTile tl = read_tile(tiles, t);
+    const DevGen g = gens[tl.gen];
+    if (g.status && __builtin_amdgcn_readfirstlane((uint32_t)*g.status) != (uint32_t)g.need)
+        return;
+    const int K = (int)g.K, N = (int)g.N, n = (tl.D >> 8) + 1;
+    const int k = lane / SK, i = lane % SK;
+    const bool has_c = lane < SK * SK && k < K && i < N;
+    const uint32_t c = gld<uint8_t>(g.C + (has_c ? (uint64_t)k * N + i : 0));
+    stream_rest<SK, B>(g, K, N, tl.p0 + (uint64_t)lane * 16u, 0, n, stage[wave], ptab4, lane, true, c, has_c);
 }
 
 // Single generation: wave w of block b takes tile b*WAVES + w; tiles run
@@ -1687,10 +1707,10 @@ hipError_t launch_region_batched(const void *d_regions, int count, uint64_t max_
     }
     // shorter regions: a wave each, M 1024-byte rounds per lane
     const int M = (int)((max_len + 1023) / 1024);
-    // four workgroups per CU: measured faster than eight (more waves add
-    // memory traffic in flight without adding bandwidth) and than two
-    const unsigned blocks = (unsigned)std::min<uint64_t>((uint64_t)(count + REGION_WAVES - 1) / REGION_WAVES,
-                                                         256ull * 4);
+    // a wave per region, all at once: measured faster than a persistent
+    // grid of two, four or eight workgroups per CU (the dispatcher keeps the
+    // CUs fed, and no wave's loads queue behind its previous region's stores)
+    const unsigned blocks = (unsigned)(((uint64_t)count + REGION_WAVES - 1) / REGION_WAVES);
     const RegionDesc *r = reinterpret_cast<const RegionDesc *>(d_regions);
     const uint4 *pt = reinterpret_cast<const uint4 *>(ptab_field);
     if (M <= 1)
@@ -1815,6 +1835,29 @@ hipError_t launch_encode_stream(int sk, const DevGen *gens, const DevTile *tiles
         hipLaunchKernelGGL((k_encode_stream<4, 2>), dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters, pt);
     else
         hipLaunchKernelGGL((k_encode_stream<8, 1>), dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters, pt);
+    return hipGetLastError();
+}
+
+int encode_chunks_strips(int sk)
+{
+    return sk <= 1 ? 8 : sk <= 2 ? 4 : sk <= 4 ? 2 : 1;
+}
+
+hipError_t launch_encode_chunks(int sk, const DevGen *gens, const DevTile *tiles, int ntiles,
+                                const uint32_t *ptab_field, hipStream_t s)
+{
+    if (ntiles <= 0)
+        return hipSuccess;
+    const uint4 *pt = reinterpret_cast<const uint4 *>(ptab_field);
+    const dim3 grid((unsigned)((ntiles + WAVES - 1) / WAVES));
+    if (sk <= 1)
+        hipLaunchKernelGGL((k_encode_chunks<1, 8>), grid, dim3(256), 0, s, gens, tiles, ntiles, pt);
+    else if (sk <= 2)
+        hipLaunchKernelGGL((k_encode_chunks<2, 4>), grid, dim3(256), 0, s, gens, tiles, ntiles, pt);
+    else if (sk <= 4)
+        hipLaunchKernelGGL((k_encode_chunks<4, 2>), grid, dim3(256), 0, s, gens, tiles, ntiles, pt);
+    else
+        hipLaunchKernelGGL((k_encode_chunks<8, 1>), grid, dim3(256), 0, s, gens, tiles, ntiles, pt);
     return hipGetLastError();
 }
 

@@ -288,3 +288,22 @@ def test_autotuner_trials_leave_outputs_and_repeat_through_the_cache(gf):
         _check(keep, wants)
     p1.destroy()
     p2.destroy()
+
+
+@pytest.mark.parametrize("what", [0, 4])
+@pytest.mark.parametrize("nbytes", [64, 32 * 1000 + 48, 1 << 22])
+def test_ceiling_copies(gf, what, nbytes):
+    """The two copy microbenchmarks that the roofline report times (grid-stride and one
+    workgroup per 16 KiB) move the first bytes // 32 words of 16 bytes to just after them,
+    whole and in place, ragged counts of words included; the tail is untouched."""
+    torch = torch_cuda()
+    src = synth.random_bytes(synth.key(90, what, nbytes), nbytes)
+    buf = dev(src)
+    gf.gf_ceiling(what, buf, 3, 0)
+    torch.cuda.synchronize()
+    half = nbytes // 32 * 16
+    got = host(buf)
+    assert (got[half:2 * half] == src[:half]).all()
+    assert (got[:half] == src[:half]).all() and (got[2 * half:] == src[2 * half:]).all()
+    with pytest.raises(gf.GFError):
+        gf.gf_ceiling(5, buf, 3, 0)

@@ -595,13 +595,15 @@ def test_binding_rejects_host_and_short_buffers(gf):
 @pytest.mark.parametrize("n", FIELDS)
 @pytest.mark.parametrize("smax", [1, 2, 3, 8])
 @pytest.mark.parametrize("aligned", [True, False])
-def test_stream_form_small_generations(gf, n, smax, aligned):
-    """Form 4 (small generations streamed in bursts of strips; the kernel instance
-    follows the batch's largest K or N): every byte equals the oracle's, on
-    generations of one to many 1 KiB strips, tiles of 64 strips and ragged ends
+@pytest.mark.parametrize("form", [4, 5])
+def test_stream_form_small_generations(gf, n, smax, aligned, form):
+    """Forms 4 and 5 (small generations streamed in bursts of strips, from work
+    queues or one burst per wave; the kernel instance follows the batch's
+    largest K or N): every byte equals the oracle's, on generations of one to
+    many 1 KiB strips, tiles of 64 strips, runs split evenly and ragged ends
     (whose last 16-byte block is read whole and written only up to the row's
     end); padding untouched.  Rows that are not 16-byte aligned are refused by
-    form 4, and the autotuned plan over them (another form) matches as well."""
+    both, and the autotuned plan over them (another form) matches as well."""
     torch = torch_cuda()
     items, wants = [], []
     for i in range(40):
@@ -616,13 +618,13 @@ def test_stream_form_small_generations(gf, n, smax, aligned):
         items.append((dev(g.C), Sd, Yd, yb, K, L, ld))
     gens = [(C, S, Y) for C, S, Y, _, _, _, _ in items]
     if aligned:
-        plan = gf.gf_plan_encode(n, gens, tune={"form": 4})
-        assert plan.tuning()["form"] == 4
+        plan = gf.gf_plan_encode(n, gens, tune={"form": form})
+        assert plan.tuning()["form"] == form
     else:
-        with pytest.raises(gf.GFError):      # form 4 reads whole 16-byte blocks
-            gf.gf_plan_encode(n, gens, tune={"form": 4})
+        with pytest.raises(gf.GFError):      # forms 4 and 5 read whole 16-byte blocks
+            gf.gf_plan_encode(n, gens, tune={"form": form})
         plan = gf.gf_plan_encode(n, gens)
-        assert plan.tuning()["form"] != 4
+        assert plan.tuning()["form"] not in (4, 5)
     for rep in range(2):
         for _, _, Yd, _, _, _, _ in items:
             Yd.fill_(0x5A)
@@ -638,4 +640,4 @@ def test_stream_form_small_generations(gf, n, smax, aligned):
     plan.destroy()
     big = [(dev(np.ones((9, 2), np.uint8)), dev(np.ones((2, 8), np.uint8)), dev(np.zeros((9, 8), np.uint8)))]
     with pytest.raises(gf.GFError):      # K = 9: not a small generation
-        gf.gf_plan_encode(n, big, tune={"form": 4})
+        gf.gf_plan_encode(n, big, tune={"form": form})
