@@ -231,7 +231,9 @@ struct gf_plan {
     std::vector<gf_gen> gens;
     // recode: the encode plan of the coefficient headers, launched first
     gf_plan *head = nullptr;
-    // decode: streams and events that let the size classes' eliminations overlap
+    // decode: the product S = Cinv B of each size class (an encode plan each),
+    // and streams and events that let the size classes' work overlap
+    gf_plan *prod[4] = {nullptr, nullptr, nullptr, nullptr};
     hipStream_t aux[3] = {nullptr, nullptr, nullptr};
     hipEvent_t ev_fork = nullptr;
     hipEvent_t ev_done[3] = {nullptr, nullptr, nullptr};
@@ -552,6 +554,13 @@ static void plan_free_device(gf_plan *p)
         plan_free_device(p->head);
         delete p->head;
         p->head = nullptr;
+    }
+    for (gf_plan *&q : p->prod) {
+        if (q) {
+            plan_free_device(q);
+            delete q;
+            q = nullptr;
+        }
     }
     for (int i = 0; i < 3; i++) {
         if (p->aux[i])
@@ -1242,8 +1251,32 @@ int gf_plan_decode(int field, const gf_sys *sys, int count, const gf_tuning *tun
         const gf_sys &s = sys[i];
         g[i] = DevGen{p->d_cinv + off[i], s.B, s.S, s.len, s.ld_b, s.ld_s, s.N, s.N, p->d_rank + i, (int)s.N, 1};
     }
-    if (!rc)
-        rc = build_encode_schedule(p, g, tune, false);
+    // one product schedule per size class, so that a class's product can follow
+    // its own elimination while larger classes are still being eliminated; the
+    // plan reports the schedule of its largest class
+    for (int c = 0; c < 4 && !rc; c++) {
+        if (p->class_count[c] == 0)
+            continue;
+        std::vector<DevGen> gc;
+        for (int j = p->class_begin[c]; j < p->class_begin[c] + p->class_count[c]; j++)
+            gc.push_back(g[order[j]]);
+        gf_plan *q = new (std::nothrow) gf_plan;
+        if (!q) {
+            rc = GF_ENOMEM;
+            break;
+        }
+        q->field = field;
+        q->dev = p->dev;
+        q->count = (int)gc.size();
+        p->prod[c] = q;
+        if (!(rc = build_encode_schedule(q, gc, tune, false))) {
+            p->form = q->form;
+            p->grid = q->grid;
+            p->fixed_D = q->fixed_D;
+        }
+    }
+    if (!rc && hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
+        rc = GF_EDEVICE;
     if (rc) {
         plan_free_device(p);
         delete p;
@@ -1273,8 +1306,9 @@ static int run_plan(gf_plan *p, int *d_rank, hipStream_t s)
     if (p->head && (rc = run_plan(p->head, nullptr, s)))
         return rc;
     if (p->kind == 1) {
-        // the size classes' eliminations run side by side: the largest on `s`,
-        // the others on the plan's own streams, forked from and joined back to `s`
+        // the size classes run side by side, each its elimination and then its
+        // product: the largest on `s`, the others on the plan's own streams,
+        // forked from and joined back to `s`
         static const int kClassN[4] = {32, 64, 128, 256};
         int classes = 0;
         for (int c = 0; c < 4; c++)
@@ -1292,14 +1326,16 @@ static int run_plan(gf_plan *p, int *d_rank, hipStream_t s)
                                          nullptr, field_ptab(d, f), field_inv(d, f), on);
             if (e != hipSuccess)
                 return GF_EDEVICE;
+            if ((rc = launch_schedule(p->prod[c], d, on)))
+                return rc;
             if (used > 0 && (hipEventRecord(p->ev_done[used - 1], on) != hipSuccess ||
                              hipStreamWaitEvent(s, p->ev_done[used - 1], 0) != hipSuccess))
                 return GF_EDEVICE;
             used++;
         }
-    }
-    if ((rc = launch_schedule(p, d, s)))
+    } else if ((rc = launch_schedule(p, d, s))) {
         return rc;
+    }
     if (p->kind == 1 && d_rank && p->count > 0)
         if (hipMemcpyAsync(d_rank, p->d_rank, sizeof(int) * p->count, hipMemcpyDeviceToDevice, s) != hipSuccess)
             return GF_EDEVICE;
@@ -1342,6 +1378,10 @@ int gf_plan_errors(gf_plan *p, uint64_t *out)
         return rc;
     unsigned v = 0;
     const unsigned zero = 0;
+    if (!p->d_err) {   // a decode plan: no descriptors are bound to it
+        *out = 0;
+        return GF_OK;
+    }
     if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(&v, p->d_err, sizeof v, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(p->d_err, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess)
         return GF_EDEVICE;

@@ -1146,8 +1146,8 @@ __device__ void invert_rows(uint32_t *A, RowOf row, int N, uint8_t *__restrict__
     // NT threads take part: the whole workgroup (256 or 1024, barriers between
     // the phases) or its first wave alone (64, which needs no workgroup barrier:
     // a wave's LDS accesses complete in order).
-    static_assert(NT == 256 || NT == 1024 || (NT == 64 && MAXN <= 64),
-                  "invert_rows runs on 256 or 1024 threads, or on 64 for N <= 64");
+    static_assert(NT == 256 || NT == 512 || NT == 1024 || (NT == 64 && MAXN <= 64),
+                  "invert_rows runs on 256, 512 or 1024 threads, or on 64 for N <= 64");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     auto sync = [&]() {
         if constexpr (NT >= 256)
@@ -1345,18 +1345,19 @@ __global__ __launch_bounds__(256) void k_invert_one(const uint8_t *__restrict__ 
 
 // d_count (if not null): the number of systems in `sys`, known only on the
 // device; workgroups past it have nothing to do.
-template <int MAXN>
-__global__ __launch_bounds__(256) void k_invert_batched(const DevSys *__restrict__ sys,
-                                                        const uint4 *__restrict__ ptab4,
-                                                        const uint8_t *__restrict__ invg,
-                                                        const unsigned *__restrict__ d_count)
+template <int MAXN, int NT = 256>
+__global__ __launch_bounds__(NT) void k_invert_batched(const DevSys *__restrict__ sys,
+                                                       const uint4 *__restrict__ ptab4,
+                                                       const uint8_t *__restrict__ invg,
+                                                       const unsigned *__restrict__ d_count)
 {
     if (d_count && blockIdx.x >= *d_count)
         return;
     const DevSys s = sys[blockIdx.x];
     if ((int)s.N > MAXN || (MAXN > 32 && (int)s.N <= MAXN / 2))
         return;   // handled by the launch of another size class
-    invert_body<MAXN>(s.C, (int)s.N, s.Cinv, s.rank, ptab4, invg);
+    __shared__ uint32_t A[MAXN * (MAXN / 4 + 1)];
+    invert_rows<MAXN, NT>(A, [&](int r) { return s.C + (uint64_t)r * s.N; }, (int)s.N, s.Cinv, s.rank, ptab4, invg);
 }
 
 // ------------------------------------------------- one small generation
