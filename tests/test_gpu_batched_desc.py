@@ -122,6 +122,47 @@ def test_plan_with_pointers_runs_other_descriptors_and_skips_mismatches(gf):
     plan.destroy()
 
 
+@pytest.mark.parametrize("n", [8, 1])
+@pytest.mark.parametrize("form", [4, 5])
+def test_streaming_forms_over_descriptors(gf, n, form):
+    """The two small-generation streaming forms (K, N <= 8) on a plan of shapes: two
+    descriptor arrays give the oracle's bytes, and a descriptor whose K differs from
+    the plan's is skipped (its output untouched) and counted."""
+    torch = torch_cuda()
+    shapes = []
+    for i in range(24):
+        K = [1, 8, 3, 5, 2, 7, 4, 6][i % 8]
+        N = [8, 1, 5, 2, 7, 3, 6, 4][i % 8]
+        L = [1, 15, 16, 1023, 1025, 9000, 8192, 20000][(3 * i) % 8]
+        shapes.append((K, N, L))
+    ld = [synth.padded(L) for _, _, L in shapes]
+    plan_descs = (gf.gf_gen * len(shapes))(*[gf.gf_gen(None, None, None, K, N, L, l, l)
+                                              for (K, N, L), l in zip(shapes, ld)])
+    plan = gf.gf_plan_encode_desc(n, plan_descs, len(shapes), tune={"form": form})
+    assert plan.tuning()["form"] == form
+    for seed in (71, 72):
+        keep, d_gens, wants = _buffers(gf, torch, n, shapes, seed)
+        torch.cuda.synchronize()
+        gf.gf_encode_batched(n, d_gens, len(shapes), plan)
+        torch.cuda.synchronize()
+        _check(keep, wants)
+        assert plan.errors() == 0
+    bad = (gf.gf_gen * len(shapes)).from_buffer_copy(bytes(host(d_gens)))
+    bad[5].K = bad[5].K - 1
+    for _, _, Y, _ in keep:
+        Y.fill_(0x5A)
+    torch.cuda.synchronize()
+    gf.gf_encode_batched(n, gf.make_gens(bad), len(shapes), plan)
+    torch.cuda.synchronize()
+    assert plan.errors() == 1
+    for i, ((C, S, Y, yb), w) in enumerate(zip(keep, wants)):
+        if i == 5:
+            assert (host(Y) == 0x5A).all()
+        else:
+            assert (host(Y) == w).all(), i
+    plan.destroy()
+
+
 def test_encode_batched_in_a_captured_graph(gf):
     """gf_encode_batched allocates nothing, so it can be captured; replays with
     other work between them give the oracle's bytes every time."""
