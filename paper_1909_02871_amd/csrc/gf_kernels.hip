@@ -1450,9 +1450,9 @@ __global__ __launch_bounds__(256) void k_small(const uint8_t *__restrict__ C, in
     }
     const uint8_t *coef = C;
     if (decode) {
-        __shared__ uint32_t A[SMALL_MAX * (SMALL_MAX / 4 + 1)];
+        __shared__ __align__(16) uint32_t A[SMALL_MAX * inv_pitch<SMALL_MAX, 4>()];
         if (threadIdx.x < 64)   // one wave: no workgroup barrier per pivot
-            invert_rows<SMALL_MAX, 64>(A, [&](int r) { return C + (uint64_t)r * N; }, N, Ci, &rk, ptab4, invg);
+            invert_rows<SMALL_MAX, 64, 4>(A, [&](int r) { return C + (uint64_t)r * N; }, N, Ci, &rk, ptab4, invg);
         __syncthreads();
         if (blockIdx.x == 0 && threadIdx.x == 0 && rank)
             *rank = rk;
