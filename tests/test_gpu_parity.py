@@ -95,6 +95,40 @@ def test_region_batched(gf, n):
         assert (host(yd[i]) == oracle.region_madd(n, ys[i], xs[i], int(cs[i]))).all(), i
 
 
+@pytest.mark.parametrize("n", FIELDS)
+@pytest.mark.parametrize("max_len", [16, 600, 1500, 2048, 3000])
+def test_region_batched_short(gf, n, max_len):
+    """Short regions (the kernels that give a region half a wave or a wave):
+    lengths from 0 to max_len, zero coefficients, an odd count, and every
+    seventh region off the 16-byte grid (its pair then goes piece by piece);
+    bytes around every region untouched."""
+    torch = torch_cuda()
+    cnt = 301
+    Ls = synth.uniform_ints(synth.key(60, n, max_len), cnt, 0, max_len)
+    Ls[:4] = [0, 1, max_len, max_len - 1]
+    cs = synth.uniform_field(synth.key(61, n, max_len), cnt, n)
+    cs[5::9] = 0
+    xs = [synth.random_bytes(synth.key(62, n, i), int(L)) for i, L in enumerate(Ls)]
+    ys = [synth.random_bytes(synth.key(63, n, i), int(L)) for i, L in enumerate(Ls)]
+    bufs, regs = [], []
+    for i, L in enumerate(Ls):
+        off = 3 if i % 7 == 6 else 0
+        xb = torch.full((int(L) + 48,), 0x77, dtype=torch.uint8, device="cuda")
+        yb = torch.full((int(L) + 48,), 0x66, dtype=torch.uint8, device="cuda")
+        if L:
+            xb[off:off + L] = dev(xs[i])
+            yb[off:off + L] = dev(ys[i])
+        bufs.append((xb, yb, off))
+        regs.append((yb.data_ptr() + off, xb.data_ptr() + off, int(L), int(cs[i])))
+    gf.gf_region_madd_batched(n, gf.make_regions(regs), cnt, int(Ls.max()))
+    torch.cuda.synchronize()
+    for i, (xb, yb, off) in enumerate(bufs):
+        L = int(Ls[i])
+        out = host(yb)
+        assert (out[off:off + L] == oracle.region_madd(n, ys[i], xs[i], int(cs[i]))).all(), (i, L)
+        assert (out[:off] == 0x66).all() and (out[off + L:] == 0x66).all(), i
+
+
 # ------------------------------------------------------------------ encode
 
 SHAPES = [(1, 1, 1), (3, 7, 33), (16, 16, 1500), (64, 64, 1500), (40, 200, 513), (255, 256, 77),
