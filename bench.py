@@ -500,10 +500,11 @@ def part_sweep(gf, torch, args) -> dict:
             sweep.append({"field": "GF(2^%d)" % n, "packet_bytes": L, "generations": count,
                           "encode_gbs": round(src / ms / 1e6, 2), "encode_ms": round(ms, 3),
                           "encode_hbm_frac": round(src / ms / 1e6 / hbm_enc, 4), "form": t["form"],
+                          "grid_blocks": t["grid_blocks"],
                           "madd_gbs": round(src / mms / 1e6, 2), "madd_ms": round(mms, 3),
                           "madd_hbm_frac": round(3 * src / mms / 1e6 / HBM_PEAK_GBS, 4)})
-            log("sweep GF(2^%d) L=%d: encode %.1f GB/s (form %d), region madd %.1f GB/s"
-                % (n, L, src / ms / 1e6, t["form"], src / mms / 1e6))
+            log("sweep GF(2^%d) L=%d: encode %.1f GB/s (form %d, %d workgroups), region madd %.1f GB/s"
+                % (n, L, src / ms / 1e6, t["form"], t["grid_blocks"], src / mms / 1e6))
             plan.destroy()
             del plan, S, Cm, Y, R, d_regs
             torch.cuda.empty_cache()

@@ -192,16 +192,20 @@ typedef struct {
  *         at most about 8 KiB of one generation's strips, one workgroup per
  *         four runs, as many workgroups as runs need (grid_blocks ignored);
  *         the same conditions as form 4.
- * form 0 on an encode plan made with pointers: every form that applies is
- * timed on the plan's own batch while the plan is created (which writes the
- * plan's outputs) and the fastest is kept (form 2 is skipped if a packet is
- * too long for it); on a plan made from shapes alone, or a decode plan, form 0
- * means form 2 when every source row starts 4-byte aligned, else 1. */
+ * form 0 on an encode plan: every form that applies is timed while the plan
+ * is created, on the plan's own sources (a plan of shapes: on scratch inputs
+ * of its shapes) into scratch outputs, so the caller's outputs are not
+ * written; the fastest is kept (form 2 is skipped if a packet is too long for
+ * it), then tried without persistence (forms 1 and 3) and on smaller
+ * persistent grids.  The choice is cached per class of batch.  On a decode
+ * plan form 0 means form 2 when every coded row starts 4-byte aligned, else 1. */
 typedef struct {
     int form;           /* 0 auto, 1 table, 2 bit-matrix, 3 bit-plane, 4 small-generation stream,
                            5 small-generation chunks */
     int bytes_per_lane; /* 0 = per tile; else 4, 8 or 16 payload bytes per lane everywhere */
-    int grid_blocks;    /* persistent workgroups; 0 = as many as fit on the GPU at once */
+    int grid_blocks;    /* persistent workgroups; 0 = as many as fit on the GPU at once (or, with form
+                           0, what the autotuner picks); -1 = forms 1 and 3 not persistent: a
+                           workgroup per four wave tiles (GF_EINVAL for forms 2 and 4) */
     int reserved;       /* must be 0 */
 } gf_tuning;
 

@@ -204,6 +204,7 @@ struct gf_plan {
     std::vector<TuneChoice> trials;     // the autotuner's timed candidates
     bool tuned_from_cache = false;
     int grid = 0;
+    bool direct = false;   // forms 1 and 3: a workgroup per four wave tiles, not persistent
     int ntiles = 0;
     DevGen *d_gens = nullptr;       // the generations as described when the plan was made
     DevGen *d_bound = nullptr;      // the same shapes with the pointers of gf_encode_batched's descriptors
@@ -748,7 +749,8 @@ static int launch_schedule(gf_plan *p, DevState *d, hipStream_t s, const DevGen 
         e = launch_encode_mfma(gens, p->d_tiles, p->d_runs, p->d_bounds, p->ntiles, p->d_ctr, p->grid,
                                field_rows(d, f), p->src_aligned4, s);
     else if (p->form == 3)
-        e = launch_encode_planes(f, gens, p->d_tiles, p->d_runs, p->d_bounds, p->ntiles, p->d_ctr, p->grid, s);
+        e = launch_encode_planes(f, gens, p->d_tiles, p->d_runs, p->d_bounds, p->ntiles, p->d_ctr, p->grid, s,
+                                 p->direct);
     else if (p->form == 4)
         e = launch_encode_stream(p->small_max, gens, p->d_tiles, p->d_runs, p->d_bounds, p->ntiles, p->d_ctr,
                                  p->grid, field_ptab(d, f), s);
@@ -756,7 +758,7 @@ static int launch_schedule(gf_plan *p, DevState *d, hipStream_t s, const DevGen 
         e = launch_encode_chunks(p->small_max, gens, p->d_tiles, p->ntiles, field_ptab(d, f), s);
     else
         e = launch_encode_persistent(gens, p->d_tiles, p->d_runs, p->d_bounds, p->ntiles, p->d_ctr, p->grid,
-                                     field_ptab(d, f), s);
+                                     field_ptab(d, f), s, p->direct);
     return dev_err(e);
 }
 
@@ -770,7 +772,8 @@ static int full_grid(const gf_plan *p, const DevState *d, int form)
                                  : encode_blocks_per_cu());
 }
 
-// grid_pct: share of the full grid (100 unless the tuner tries less).
+// grid_pct: share of the full grid (100 unless the tuner tries less); 0 for
+// forms 1 and 3: not persistent, a workgroup per four wave tiles.
 static int make_schedule(gf_plan *p, DevState *d, const std::vector<DevGen> &g, int form, const gf_tuning *tune,
                          int grid_pct = 100)
 {
@@ -797,12 +800,13 @@ static int make_schedule(gf_plan *p, DevState *d, const std::vector<DevGen> &g, 
     if (rc)
         return rc;
     p->d_bounds = p->d_runs + tq.runs.size();
-    int grid = std::max(1, full_grid(p, d, form) * grid_pct / 100);
+    int grid = std::max(1, full_grid(p, d, form) * std::max(grid_pct, 1) / 100);
     if (tune && tune->grid_blocks > 0)
         grid = tune->grid_blocks;
     const int per_block = form == 2 ? 1 : 4;
     p->grid = std::max(1, std::min(grid, std::max(1, (p->ntiles + per_block - 1) / per_block)));
-    if (form == 5)   // not persistent: a workgroup per four tiles
+    p->direct = (form == 1 || form == 3) && (grid_pct == 0 || (tune && tune->grid_blocks == -1));
+    if (form == 5 || p->direct)   // not persistent: a workgroup per four tiles
         p->grid = std::max(1, (p->ntiles + 3) / 4);
     return GF_OK;
 }
@@ -940,15 +944,20 @@ static int autotune(gf_plan *p, DevState *d, const std::vector<DevGen> &g, const
             return rc;
     if (best.ms < 0)
         return GF_EDEVICE;
-    if (!(tune && tune->grid_blocks > 0) && best.form != 5) {
+    if (!(tune && tune->grid_blocks != 0) && best.form != 5) {
+        const TuneChoice top = best;
+        // the vector-ALU forms also without persistence: a wave per tile
+        if ((top.form == 1 || top.form == 3) && (rc = consider(top.form, top.fixed_D, 0)))
+            return rc;
         // smaller grids while they keep winning: memory-bound forms can run
         // faster with fewer waves in flight; stop two steps past the best
-        const TuneChoice top = best;
-        for (int pct : {75, 50, 35, 25, 18}) {
-            if ((rc = consider(top.form, top.fixed_D, pct)))
-                return rc;
-            if (3 * pct < 2 * best.grid_pct)
-                break;
+        if (best.grid_pct != 0) {
+            for (int pct : {75, 50, 35, 25, 18}) {
+                if ((rc = consider(top.form, top.fixed_D, pct)))
+                    return rc;
+                if (3 * pct < 2 * best.grid_pct)
+                    break;
+            }
         }
     }
     p->fixed_D = best.fixed_D;
@@ -977,6 +986,9 @@ static int build_encode_schedule(gf_plan *p, const std::vector<DevGen> &gens, co
     }
     int form = tune ? tune->form : 0;
     if (form < 0 || form > 5 || (form == 3 && p->field > 4))
+        return GF_EINVAL;
+    // grid_blocks -1: a workgroup per four wave tiles, for the forms that have it
+    if (tune && (tune->grid_blocks < -1 || (tune->grid_blocks == -1 && form != 1 && form != 3 && form != 5)))
         return GF_EINVAL;
     std::vector<DevGen> g = gens;
     p->src_aligned4 = true;

@@ -131,9 +131,10 @@ void build_tiles(const DevGen *g, size_t n, int fixed_D, TileQueues &q);
 // over the whole packet length in strips of MF_STRIP bytes (DevTile.D unused).
 void build_tiles_mfma(const DevGen *g, size_t n, TileQueues &q);
 
+// direct: not persistent, a workgroup per four wave tiles (grid unused).
 hipError_t launch_encode_persistent(const DevGen *gens, const DevTile *tiles, const unsigned *runs,
                                     const unsigned *bounds, int ntiles, unsigned *counters, int grid,
-                                    const uint32_t *ptab_field, hipStream_t s);
+                                    const uint32_t *ptab_field, hipStream_t s, bool direct = false);
 // aligned4: every generation's source rows start 4-byte aligned.
 hipError_t launch_encode_mfma(const DevGen *gens, const DevTile *tiles, const unsigned *runs, const unsigned *bounds,
                               int ntiles, unsigned *counters, int grid, const uint8_t *rows_field, bool aligned4,
@@ -141,7 +142,8 @@ hipError_t launch_encode_mfma(const DevGen *gens, const DevTile *tiles, const un
 int encode_mfma_blocks_per_cu(bool aligned4);
 // Bit-plane form (fields with n <= 4) over the table form's wave tiles.
 hipError_t launch_encode_planes(int field, const DevGen *gens, const DevTile *tiles, const unsigned *runs,
-                                const unsigned *bounds, int ntiles, unsigned *counters, int grid, hipStream_t s);
+                                const unsigned *bounds, int ntiles, unsigned *counters, int grid, hipStream_t s,
+                                bool direct = false);
 int encode_planes_blocks_per_cu(int field);
 // Small-generation streaming form (every generation K <= 8 and N <= 8): wave
 // tiles of up to STREAM_STRIPS strips of 1 KiB, tables staged once per tile.

@@ -891,22 +891,29 @@ __global__ __launch_bounds__(256) void k_zero_rows(uint8_t *Y, uint64_t ld_y, ui
 }
 
 // Persistent encode over the work queues; every wave claims tiles on its own.
+template <bool DIRECT = false>
 __global__ __launch_bounds__(256, GF_ENC_WAVES_PER_SIMD) void k_encode_waves(const DevGen *__restrict__ gens,
                                                       const DevTile *__restrict__ tiles,
                                                       const unsigned *__restrict__ runs,
                                                       const unsigned *__restrict__ bounds, unsigned *counters,
-                                                      const uint4 *__restrict__ ptab4)
+                                                      const uint4 *__restrict__ ptab4, int ntiles)
 {
     __shared__ WaveStage stage[WAVES];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     QueueCursor cursor;
-    for (;;) {
+    for (int pass = 0;; pass++) {
         int t = 0;
-        if (lane == 0)
-            t = queue_next_tile(counters, runs, bounds, cursor);
-        t = __builtin_amdgcn_readlane(t, 0);
-        if (t < 0)
-            break;
+        if constexpr (DIRECT) {   // not persistent: wave w of workgroup b takes tile 4b + w only
+            t = __builtin_amdgcn_readfirstlane((int)blockIdx.x * WAVES + wave);
+            if (pass > 0 || t >= ntiles)
+                break;
+        } else {
+            if (lane == 0)
+                t = queue_next_tile(counters, runs, bounds, cursor);
+            t = __builtin_amdgcn_readlane(t, 0);
+            if (t < 0)
+                break;
+        }
         const DevTile tl = tiles[t];
         const DevGen g = gens[tl.gen];
         if (g.status && *g.status != g.need)
@@ -927,7 +934,7 @@ __global__ __launch_bounds__(256, GF_ENC_WAVES_PER_SIMD) void k_encode_waves(con
                              g.align >= 4, ptab4, stage[wave], lane, 0, (int)g.N, false, staged);
         }
     }
-    if (lane == 0)
+    if (!DIRECT && lane == 0)
         queue_retire(counters, gridDim.x * WAVES);
 }
 
@@ -1075,25 +1082,32 @@ __device__ __forceinline__ void wave_tile_planes(const uint8_t *__restrict__ C, 
 }
 
 // Persistent bit-plane encode over the same wave tiles and queues as the
-// table form.
-template <int NB>
+// table form.  DIRECT: not persistent; wave w of workgroup b takes tile 4b + w
+// of the list and nothing else (a workgroup per four tiles).
+template <int NB, bool DIRECT = false>
 __global__ __launch_bounds__(256, NB <= 2 ? GF_PLANE_WAVES_PER_SIMD : 2) void k_encode_planes(const DevGen *__restrict__ gens,
                                                                              const DevTile *__restrict__ tiles,
                                                                              const unsigned *__restrict__ runs,
                                                                              const unsigned *__restrict__ bounds,
-                                                                             unsigned *counters)
+                                                                             unsigned *counters, int ntiles)
 {
     __shared__ WaveStage stage[WAVES];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t *mk = reinterpret_cast<uint32_t *>(&stage[wave]);
     QueueCursor cursor;
-    for (;;) {
+    for (int pass = 0;; pass++) {
         int t = 0;
-        if (lane == 0)
-            t = queue_next_tile(counters, runs, bounds, cursor);
-        t = __builtin_amdgcn_readlane(t, 0);
-        if (t < 0)
-            break;
+        if constexpr (DIRECT) {
+            t = __builtin_amdgcn_readfirstlane((int)blockIdx.x * WAVES + wave);
+            if (pass > 0 || t >= ntiles)
+                break;
+        } else {
+            if (lane == 0)
+                t = queue_next_tile(counters, runs, bounds, cursor);
+            t = __builtin_amdgcn_readlane(t, 0);
+            if (t < 0)
+                break;
+        }
         const DevTile tl = tiles[t];
         const DevGen g = gens[tl.gen];
         if (g.status && *g.status != g.need)
@@ -1113,7 +1127,7 @@ __global__ __launch_bounds__(256, NB <= 2 ? GF_PLANE_WAVES_PER_SIMD : 2) void k_
                                         g.align >= 4, mk, lane, staged);
         }
     }
-    if (lane == 0)
+    if (!DIRECT && lane == 0)
         queue_retire(counters, gridDim.x * WAVES);
 }
 
@@ -1827,26 +1841,44 @@ hipError_t launch_small(const uint8_t *C, int K, int N, const uint8_t *S, uint64
 
 hipError_t launch_encode_persistent(const DevGen *gens, const DevTile *tiles, const unsigned *runs,
                                     const unsigned *bounds, int ntiles, unsigned *counters, int grid,
-                                    const uint32_t *ptab_field, hipStream_t s)
+                                    const uint32_t *ptab_field, hipStream_t s, bool direct)
 {
     if (ntiles <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_encode_waves, dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters,
-                       reinterpret_cast<const uint4 *>(ptab_field));
+    const uint4 *pt = reinterpret_cast<const uint4 *>(ptab_field);
+    if (direct)
+        hipLaunchKernelGGL(k_encode_waves<true>, dim3((unsigned)((ntiles + WAVES - 1) / WAVES)), dim3(256), 0, s,
+                           gens, tiles, runs, bounds, counters, pt, ntiles);
+    else
+        hipLaunchKernelGGL(k_encode_waves<false>, dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters,
+                           pt, ntiles);
     return hipGetLastError();
 }
 
+template <int NB>
+static void launch_planes_nb(const DevGen *gens, const DevTile *tiles, const unsigned *runs, const unsigned *bounds,
+                             int ntiles, unsigned *counters, int grid, hipStream_t s, bool direct)
+{
+    if (direct)
+        hipLaunchKernelGGL((k_encode_planes<NB, true>), dim3((unsigned)((ntiles + WAVES - 1) / WAVES)), dim3(256), 0,
+                           s, gens, tiles, runs, bounds, counters, ntiles);
+    else
+        hipLaunchKernelGGL((k_encode_planes<NB, false>), dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds,
+                           counters, ntiles);
+}
+
 hipError_t launch_encode_planes(int field, const DevGen *gens, const DevTile *tiles, const unsigned *runs,
-                                const unsigned *bounds, int ntiles, unsigned *counters, int grid, hipStream_t s)
+                                const unsigned *bounds, int ntiles, unsigned *counters, int grid, hipStream_t s,
+                                bool direct)
 {
     if (ntiles <= 0)
         return hipSuccess;
     if (field == 1)
-        hipLaunchKernelGGL(k_encode_planes<1>, dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters);
+        launch_planes_nb<1>(gens, tiles, runs, bounds, ntiles, counters, grid, s, direct);
     else if (field == 2)
-        hipLaunchKernelGGL(k_encode_planes<2>, dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters);
+        launch_planes_nb<2>(gens, tiles, runs, bounds, ntiles, counters, grid, s, direct);
     else if (field == 4)
-        hipLaunchKernelGGL(k_encode_planes<4>, dim3(grid), dim3(256), 0, s, gens, tiles, runs, bounds, counters);
+        launch_planes_nb<4>(gens, tiles, runs, bounds, ntiles, counters, grid, s, direct);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -1917,9 +1949,9 @@ int encode_stream_blocks_per_cu(int sk)
 
 int encode_planes_blocks_per_cu(int field)
 {
-    const void *k = field == 1   ? reinterpret_cast<const void *>(&k_encode_planes<1>)
-                    : field == 2 ? reinterpret_cast<const void *>(&k_encode_planes<2>)
-                                 : reinterpret_cast<const void *>(&k_encode_planes<4>);
+    const void *k = field == 1   ? reinterpret_cast<const void *>(&k_encode_planes<1, false>)
+                    : field == 2 ? reinterpret_cast<const void *>(&k_encode_planes<2, false>)
+                                 : reinterpret_cast<const void *>(&k_encode_planes<4, false>);
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, 0) != hipSuccess || nb < 1)
         return 1;
@@ -1929,7 +1961,7 @@ int encode_planes_blocks_per_cu(int field)
 int encode_blocks_per_cu()
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_encode_waves), 256, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_encode_waves<false>), 256, 0) !=
             hipSuccess ||
         nb < 1)
         return 1;

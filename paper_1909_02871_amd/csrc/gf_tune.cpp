@@ -82,7 +82,7 @@ void load_locked()
         double form = 0, bpl = 0, pct = 0, ms = 0;
         if (field_num(s, k1, end, "form", &form) && field_num(s, k1, end, "bytes_per_lane", &bpl) &&
             field_num(s, k1, end, "grid_pct", &pct) && field_num(s, k1, end, "ms", &ms) && form >= 1 &&
-            form <= 5 && (bpl == 0 || bpl == 4 || bpl == 8 || bpl == 16) && pct >= 1 && pct <= 100)
+            form <= 5 && (bpl == 0 || bpl == 4 || bpl == 8 || bpl == 16) && pct >= 0 && pct <= 100 && (pct > 0 || form == 1 || form == 3))
             g_cache[s.substr(k0, k1 - k0)] = TuneChoice{(int)form, (int)bpl / 4, (int)pct, ms};
         pos = end;
     }

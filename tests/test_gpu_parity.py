@@ -160,10 +160,12 @@ def test_encode(gf, n, K, N, L):
 
 @pytest.mark.parametrize("n", FIELDS)
 @pytest.mark.parametrize("form,bpl", [(1, 0), (1, 4), (1, 8), (1, 16), (2, 0), (3, 0), (3, 4), (3, 8), (3, 16)])
-@pytest.mark.parametrize("grid", [0, 1, 7])
+@pytest.mark.parametrize("grid", [0, 1, 7, -1])
 def test_encode_every_variant(gf, n, form, bpl, grid):
     """Every schedule of every kernel form gives the same bytes (batched path, 30
-    generations; N up to 80 spans several mask stages of the bit-plane form)."""
+    generations; N up to 80 spans several mask stages of the bit-plane form);
+    grid -1 is the non-persistent dispatch of the vector-ALU forms (a workgroup
+    per four wave tiles), which the bit-matrix form refuses."""
     torch = torch_cuda()
     if form == 3 and n == 8:
         C1, S1, Y1 = dev(np.ones((2, 2), np.uint8)), dev(np.ones((2, 8), np.uint8)), dev(np.zeros((2, 8), np.uint8))
@@ -181,9 +183,14 @@ def test_encode_every_variant(gf, n, form, bpl, grid):
         _, Sd = padded_rows(g.S, synth.padded(L))
         _, Yd = padded_rows(np.zeros((K, L), np.uint8), synth.padded(L))
         keep.append((Cd, Sd, Yd))
+    if grid == -1 and form == 2:
+        with pytest.raises(gf.GFError):
+            gf.gf_plan_encode(n, keep, tune={"form": form, "bytes_per_lane": bpl, "grid_blocks": grid})
+        return
     plan = gf.gf_plan_encode(n, keep, tune={"form": form, "bytes_per_lane": bpl, "grid_blocks": grid})
     assert plan.tuning()["bytes_per_lane"] == bpl and plan.tuning()["form"] == form
-    assert grid == 0 or plan.tuning()["grid_blocks"] == grid
+    assert grid == 0 or plan.tuning()["grid_blocks"] == (grid if grid > 0 else plan.tuning()["grid_blocks"])
+    assert plan.tuning()["grid_blocks"] > 0
     for rep in range(2):      # the work counter resets itself between launches
         for _, _, Yd in keep:
             Yd.zero_()
