@@ -426,6 +426,40 @@ def extra_workloads(gf, torch, args, only=None) -> dict:
     return out
 
 
+def part_region(gf, torch, args) -> dict:
+    """The paper's primitive on its own: one gf_region_madd call y ^= c x over a region of 1500 B
+    to 1 GiB, GF(256) with c = 0x53 and GF(2) with c = 1, back to back through the C ABI; GB/s of
+    x and the share of the HBM roofline (3 bytes of traffic per byte of x; the 64 MiB point's x
+    and y fit the 256 MB last-level cache, so its repeated calls read partly from there).  Checked by a property that holds at any size
+    (the parity tests compare the bytes with the oracle): two calls give y back, since the
+    field's addition is XOR."""
+    out = []
+    lib = gf.lib()
+    st = torch.cuda.current_stream().cuda_stream
+    for L in (1500, 65536, 1 << 20, 64 << 20, 1 << 30):
+        x = device_bytes(torch, L, synth.key(synth.BASE_SEED + 7, L, 1))
+        y = device_bytes(torch, L, synth.key(synth.BASE_SEED + 7, L, 2))
+        for n, c in ((8, 0x53), (1, 1)):
+            y0 = y.clone()
+            gf.gf_region_madd(n, y, x, c)
+            changed = not torch.equal(y, y0)
+            gf.gf_region_madd(n, y, x, c)
+            ok = changed and torch.equal(y, y0)
+            del y0
+            reps = 20 if L >= (64 << 20) else 200
+            # C-ABI calls, arguments marshalled once (the binding's checks are not the library's latency)
+            yp, xp = y.data_ptr(), x.data_ptr()
+            ms = time_ms(torch, lambda: lib.gf_region_madd(n, yp, xp, c, L, st), reps=reps, warm=3)
+            out.append({"field": "GF(2^%d)" % n, "c": c, "bytes": L, "gbs": round(L / ms / 1e6, 2),
+                        "us": round(ms * 1e3, 2), "hbm_frac": round(3 * L / ms / 1e6 / HBM_PEAK_GBS, 4),
+                        "twice_is_identity": ok})
+            log("region madd GF(2^%d) %d B: %.1f GB/s of x (%.0f%% of HBM roofline), %.2f us"
+                % (n, L, L / ms / 1e6, 100 * 3 * L / ms / 1e6 / HBM_PEAK_GBS, ms * 1e3))
+        del x, y
+        torch.cuda.empty_cache()
+    return {"region_madd_single": out}
+
+
 def part_single_generation(gf, torch, args) -> dict:
     out = {}
     # ---- one generation: GF(256), 16 x 16 x 1500 B, encode and decode back (latency, one launch each)
@@ -653,7 +687,7 @@ def part_host_alg1(gf, torch, args) -> dict:
     return out
 
 
-EXTRA_PARTS = (("single_generation", part_single_generation), ("sweep", part_sweep),
+EXTRA_PARTS = (("single_generation", part_single_generation), ("region", part_region), ("sweep", part_sweep),
                ("uneven_gf16", part_uneven_gf16), ("recode", part_recode), ("decode", part_decode),
                ("k_sweep", part_k_sweep), ("host_alg1", part_host_alg1))
 

@@ -51,6 +51,26 @@ def test_region_madd_mul(gf, n, length):
         assert (host(yd) == oracle.region_mul(n, x, c)).all()
 
 
+@pytest.mark.parametrize("n,c", [(8, 0x53), (1, 1)])
+@pytest.mark.parametrize("offset", [0, 5])
+def test_region_madd_large(gf, n, c, offset):
+    """A region past 32 MiB (a launch of 5,121 workgroups of 8 KiB, where the grid
+    was once capped and looped), with a 13-byte tail, and one off the 16-byte grid
+    (the byte path): every byte equals the oracle's, the bytes around untouched."""
+    torch = torch_cuda()
+    L = (40 << 20) + 13
+    x = synth.random_bytes(synth.key(64, n, offset), L)
+    y = synth.random_bytes(synth.key(65, n, offset), L)
+    xb = torch.zeros(L + 32, dtype=torch.uint8, device="cuda")
+    yb = torch.full((L + 32,), 0x2D, dtype=torch.uint8, device="cuda")
+    xb[offset:offset + L] = dev(x)
+    yb[offset:offset + L] = dev(y)
+    gf.gf_region_madd(n, yb[offset:offset + L], xb[offset:offset + L], c)
+    out = host(yb)
+    assert (out[offset:offset + L] == oracle.region_madd(n, y, x, c)).all()
+    assert (out[:offset] == 0x2D).all() and (out[offset + L:] == 0x2D).all()
+
+
 @pytest.mark.parametrize("n", FIELDS)
 @pytest.mark.parametrize("xo,yo", [(1, 1), (3, 0), (0, 5), (7, 9)])
 def test_region_unaligned(gf, n, xo, yo):
