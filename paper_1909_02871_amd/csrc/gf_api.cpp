@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <mutex>
 #include <numeric>
+#include <cstring>
 #include <vector>
 
 #include "../../include/gfnc.h"
@@ -61,14 +62,20 @@ int current_state(DevState **out)
     if (!d.ready) {
         const HostTables &h = host_tables();
         void *pt = nullptr, *iv = nullptr, *rw = nullptr;
-        if (hipMalloc(&pt, sizeof h.ptab) != hipSuccess)
+        // the product tables, then those of every element's inverse (the same layout)
+        std::vector<uint32_t> tabs(2 * sizeof h.ptab / sizeof(uint32_t));
+        std::memcpy(tabs.data(), h.ptab, sizeof h.ptab);
+        for (int f = 0; f < 4; f++)
+            for (int c = 0; c < 256; c++)
+                std::memcpy(&tabs[((size_t)(4 + f) * 256 + c) * 8], h.ptab[f][h.inv[f][c]], 8 * sizeof(uint32_t));
+        if (hipMalloc(&pt, 2 * sizeof h.ptab) != hipSuccess)
             return GF_EDEVICE;
         if (hipMalloc(&iv, sizeof h.inv) != hipSuccess || hipMalloc(&rw, sizeof h.rows) != hipSuccess) {
             (void)hipFree(pt);
             (void)hipFree(iv);
             return GF_EDEVICE;
         }
-        if (hipMemcpy(pt, h.ptab, sizeof h.ptab, hipMemcpyHostToDevice) != hipSuccess ||
+        if (hipMemcpy(pt, tabs.data(), 2 * sizeof h.ptab, hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(iv, h.inv, sizeof h.inv, hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(rw, h.rows, sizeof h.rows, hipMemcpyHostToDevice) != hipSuccess) {
             (void)hipFree(pt);
@@ -117,6 +124,10 @@ bool valid_field(int f) { return f == 1 || f == 2 || f == 4 || f == 8; }
 const uint32_t *field_ptab(const DevState *d, int field)
 {
     return d->t.ptab + (size_t)field_index(field) * 256 * 8;
+}
+const uint32_t *field_ptab_inv(const DevState *d, int field)
+{
+    return d->t.ptab + (size_t)(4 + field_index(field)) * 256 * 8;
 }
 const uint8_t *field_inv(const DevState *d, int field) { return d->t.inv + (size_t)field_index(field) * 256; }
 const uint8_t *field_rows(const DevState *d, int field) { return d->t.rows + (size_t)field_index(field) * 256 * 8; }
@@ -361,7 +372,8 @@ static int encode_impl(int field, const uint8_t *C, int K, int N, const uint8_t 
         return rc;
     const uint32_t al = row_align(S, N > 1 ? ld_s : 0, Y, K > 1 ? ld_y : 0);
     if (!status && !(tune && tune->bytes_per_lane) && small_ok(K, N, len, al))
-        return dev_err(launch_small(C, K, N, S, ld_s, Y, ld_y, len, field_ptab(d, field), field_inv(d, field), nullptr,
+        return dev_err(launch_small(C, K, N, S, ld_s, Y, ld_y, len, field_ptab(d, field), field_ptab_inv(d, field),
+                                    field_inv(d, field), nullptr,
                                     false, (hipStream_t)stream));
     Single sc = pick_single(K, N, len, al, d->cus);
     if (tune && tune->bytes_per_lane) {
@@ -486,7 +498,8 @@ static int decode_impl(DevState *d, int field, const uint8_t *C, const uint8_t *
                        size_t ld_s, size_t len, uint8_t *cinv, int *rank, void *stream)
 {
     if (small_ok(N, N, len, row_align(B, N > 1 ? ld_b : 0, S, N > 1 ? ld_s : 0)))
-        return dev_err(launch_small(C, N, N, B, ld_b, S, ld_s, len, field_ptab(d, field), field_inv(d, field), rank,
+        return dev_err(launch_small(C, N, N, B, ld_b, S, ld_s, len, field_ptab(d, field), field_ptab_inv(d, field),
+                                    field_inv(d, field), rank,
                                     true, (hipStream_t)stream));
     hipError_t e = launch_invert(nullptr, 0, C, N, cinv, rank, field_ptab(d, field), field_inv(d, field),
                                  (hipStream_t)stream);

@@ -27,7 +27,7 @@ inline int field_index(int n) { return n == 1 ? 0 : n == 2 ? 1 : n == 4 ? 2 : n 
 //   rows[f][c][i]: row i of the 8 x 8 bit matrix of "multiply a byte by c":
 //     bit j is bit i of c * (1 << j)  (the product is GF(2)-linear in the byte).
 struct DevTables {
-    uint32_t *ptab;   // [4][256][8]
+    uint32_t *ptab;   // [8][256][8]: [f] the product tables, [4 + f] those of c's inverse at c
     uint8_t *inv;     // [4][256]
     uint8_t *rows;    // [4][256][8]
 };
@@ -177,7 +177,8 @@ int encode_blocks_per_cu();
 // null) and no output for a singular C.
 bool small_ok(int K, int N, uint64_t len, uint32_t align);
 hipError_t launch_small(const uint8_t *C, int K, int N, const uint8_t *S, uint64_t ld_s, uint8_t *Y, uint64_t ld_y,
-                        uint64_t len, const uint32_t *ptab_field, const uint8_t *inv_field, int *rank, bool decode,
+                        uint64_t len, const uint32_t *ptab_field, const uint32_t *ptab_inv_field,
+                        const uint8_t *inv_field, int *rank, bool decode,
                         hipStream_t s);
 uint32_t row_align(const void *S, uint64_t ld_s, const void *Y, uint64_t ld_y);
 // Device tables of `field` on the current device (initialising it if needed).

@@ -1428,11 +1428,72 @@ __global__ __launch_bounds__(NT) void k_invert_batched(const DevSys *__restrict_
 // workgroup 0 reports the rank, and a singular C writes no output.
 
 constexpr int SMALL_MAX = 32;   // largest N and K of the small path
+constexpr int REG_INV_MAX = 16;  // largest N inverted in one wave's registers
+
+// Gauss-Jordan inversion of an N x N matrix, N <= 16, in one wave's registers:
+// lane 4r + q holds bytes 4q .. 4q + 3 of row r.  At pivot step j a ballot
+// over the lanes that hold column j finds the lowest usable row, a cross-lane
+// permute swaps it up, the pivot row (its pivot replaced by 1) is multiplied
+// by the pivot's inverse (TI: the field's product tables indexed by the
+// element whose inverse they multiply by), and every other row takes its
+// factor (its byte j) and the pivot row's dword from the lanes that hold them
+// (cross-lane permutes) and clears column j.  (Taking them with a DPP quad
+// broadcast and four scalar lane reads instead measured slower.)  The row swaps are undone as column swaps when the inverse is
+// written to Ci (N x N, row-major, LDS).  W (64 dwords) and P (16 ints) are LDS
+// scratch.  Returns N, or -1 when C is singular (Ci then unspecified).
+__device__ int invert_wave_regs(const uint8_t *__restrict__ C, int N, uint8_t *Ci, const uint4 (*T)[2],
+                                const uint4 (*TI)[2], uint32_t *W, int *P)
+{
+    const int lane = threadIdx.x & 63, r = lane >> 2, q = lane & 3;
+    uint32_t v = 0;
+#pragma unroll
+    for (int b = 0; b < 4; b++) {   // clamped into the matrix, masked past it
+        const int c = 4 * q + b;
+        const uint32_t x = C[min(r, N - 1) * N + min(c, N - 1)];
+        v |= (r < N && c < N ? x : 0u) << (8 * b);
+    }
+#pragma unroll
+    for (int j = 0; j < REG_INV_MAX; j++) {
+        if (j >= N)
+            break;
+        const int qj = j >> 2, sh = 8 * (j & 3);
+        const uint64_t cand = __ballot(q == qj && r >= j && r < N && ((v >> sh) & 0xFFu) != 0);
+        if (cand == 0)
+            return -1;
+        const int pr = __builtin_amdgcn_readfirstlane((int)(__builtin_ctzll(cand) >> 2));
+        if (pr != j) {
+            const int src = r == j ? pr * 4 + q : r == pr ? j * 4 + q : lane;
+            v = (uint32_t)__shfl((int)v, src);
+        }
+        if (lane == 0)
+            P[j] = pr;
+        const uint32_t p = ((uint32_t)__builtin_amdgcn_readlane((int)v, j * 4 + qj) >> sh) & 0xFFu;
+        const uint32_t f = ((uint32_t)__shfl((int)v, r * 4 + qj) >> sh) & 0xFFu;   // this row's factor
+        uint32_t vj = q == qj ? ((v & ~(0xFFu << sh)) | (1u << sh)) : v;
+        vj = prod4(TI[p][0], TI[p][1].x, vj);
+        const uint32_t pj = (uint32_t)__shfl((int)vj, j * 4 + q);   // the scaled pivot row's dword q
+        const uint32_t keep = q == qj ? ~(0xFFu << sh) : 0xFFFFFFFFu;
+        v = r == j ? vj : ((v & keep) ^ prod4(T[f][0], T[f][1].x, pj));
+    }
+    W[lane] = v;
+    wave_sync();
+    for (int e = lane; e < N * N; e += 64) {
+        const int i = e / N, c = e - i * N;
+        int x = c;   // the column of the eliminated matrix that holds column c of the inverse
+        for (int l = 0; l < N; l++) {
+            const int pl = P[l];
+            x = x == l ? pl : x == pl ? l : x;
+        }
+        Ci[e] = (uint8_t)(W[i * 4 + (x >> 2)] >> (8 * (x & 3)));
+    }
+    return N;
+}
 
 __global__ __launch_bounds__(256) void k_small(const uint8_t *__restrict__ C, int K, int N,
                                                const uint8_t *__restrict__ S, uint64_t ld_s, uint8_t *__restrict__ Y,
                                                uint64_t ld_y, uint64_t len, const uint4 *__restrict__ ptab4,
-                                               const uint8_t *__restrict__ invg, int *rank, int decode)
+                                               const uint4 *__restrict__ ptabinv4, const uint8_t *__restrict__ invg,
+                                               int *rank, int decode)
 {
     __shared__ uint4 T[SMALL_MAX * SMALL_MAX][2];
     __shared__ uint8_t Ci[SMALL_MAX * SMALL_MAX];
@@ -1463,10 +1524,29 @@ __global__ __launch_bounds__(256) void k_small(const uint8_t *__restrict__ C, in
         }
     }
     const uint8_t *coef = C;
+    __shared__ uint4 FT[256][2], FTI[256][2];   // the field's product tables, and those of the inverses
+    const bool regs = decode && N <= REG_INV_MAX;
+    if (regs) {   // every thread fetches two of each
+        for (int e = threadIdx.x; e < 512; e += 256) {
+            FT[e >> 1][e & 1] = ptab4[e];
+            FTI[e >> 1][e & 1] = ptabinv4[e];
+        }
+        __syncthreads();
+    }
     if (decode) {
         __shared__ __align__(16) uint32_t A[SMALL_MAX * inv_pitch<SMALL_MAX, 4>()];
-        if (threadIdx.x < 64)   // one wave: no workgroup barrier per pivot
-            invert_rows<SMALL_MAX, 64, 4>(A, [&](int r) { return C + (uint64_t)r * N; }, N, Ci, &rk, ptab4, invg);
+        __shared__ uint32_t W[64];
+        __shared__ int P[REG_INV_MAX];
+        if (threadIdx.x < 64) {   // one wave: no workgroup barrier per pivot
+            int got = -1;
+            if (regs)
+                got = invert_wave_regs(C, N, Ci, FT, FTI, W, P);
+            if (got < 0)   // larger, or singular: the LDS elimination, which also finds the rank
+                invert_rows<SMALL_MAX, 64, 4>(A, [&](int r) { return C + (uint64_t)r * N; }, N, Ci, &rk, ptab4,
+                                              invg);
+            else if (threadIdx.x == 0)
+                rk = got;
+        }
         __syncthreads();
         if (blockIdx.x == 0 && threadIdx.x == 0 && rank)
             *rank = rk;
@@ -1476,8 +1556,8 @@ __global__ __launch_bounds__(256) void k_small(const uint8_t *__restrict__ C, in
     }
     for (int e = threadIdx.x; e < K * N; e += 256) {
         const uint32_t c = coef[e];
-        T[e][0] = ptab4[c * 2];
-        T[e][1] = ptab4[c * 2 + 1];
+        T[e][0] = regs ? FT[c][0] : ptab4[c * 2];   // from the LDS copy when there is one
+        T[e][1] = regs ? FT[c][1] : ptab4[c * 2 + 1];
     }
     __syncthreads();
     if (avail == 0)
@@ -1831,14 +1911,15 @@ bool small_ok(int K, int N, uint64_t len, uint32_t align)
 }
 
 hipError_t launch_small(const uint8_t *C, int K, int N, const uint8_t *S, uint64_t ld_s, uint8_t *Y, uint64_t ld_y,
-                        uint64_t len, const uint32_t *ptab_field, const uint8_t *inv_field, int *rank, bool decode,
-                        hipStream_t s)
+                        uint64_t len, const uint32_t *ptab_field, const uint32_t *ptab_inv_field,
+                        const uint8_t *inv_field, int *rank, bool decode, hipStream_t s)
 {
     if (!small_ok(K, N, len, 4))
         return hipErrorInvalidValue;
     const uint64_t threads = (len + 3) / 4 * (uint64_t)K;
     hipLaunchKernelGGL(k_small, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, C, K, N, S, ld_s, Y, ld_y,
-                       len, reinterpret_cast<const uint4 *>(ptab_field), inv_field, rank, decode ? 1 : 0);
+                       len, reinterpret_cast<const uint4 *>(ptab_field), reinterpret_cast<const uint4 *>(ptab_inv_field),
+                       inv_field, rank, decode ? 1 : 0);
     return hipGetLastError();
 }
 

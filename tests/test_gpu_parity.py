@@ -339,6 +339,45 @@ def test_decode(gf, n, N, L):
 
 
 @pytest.mark.parametrize("n", FIELDS)
+def test_decode_small_every_N(gf, n):
+    """The one-launch decode for N = 1 .. 17 (N <= 16 inverts in one wave's
+    registers, 17 in LDS): matrices with a zero leading entry (so a lower pivot
+    row is swapped up, and the inverse's columns swapped back) decode to the
+    sources; singular ones leave the output untouched and report the oracle's
+    rank."""
+    torch = torch_cuda()
+    for N in range(1, 18):
+        L = 4 * (50 + N)   # rows 4-byte aligned: the one-launch path
+        S = synth.random_bytes(synth.key(71, n, N), N * L).reshape(N, L)
+        cases = []
+        if N > 1:
+            for t in range(50):   # a zero in the top-left corner, still invertible
+                Cm = synth.uniform_field(synth.key(72, n, N, t), N * N, n).reshape(N, N)
+                Cm[0, 0] = 0
+                if oracle.rank(n, Cm) == N:
+                    cases.append(Cm)
+                    break
+        Cs = synth.uniform_field(synth.key(73, n, N), N * N, n).reshape(N, N)
+        if N > 1:
+            Cs[N - 1] = Cs[0]
+        else:
+            Cs[0, 0] = 0
+        cases.append(Cs)
+        for Cm in cases:
+            r = oracle.rank(n, Cm)
+            B = oracle.encode(n, Cm, S)
+            out = torch.full((N, L), 0x77, dtype=torch.uint8, device="cuda")
+            rank = torch.zeros(1, dtype=torch.int32, device="cuda")
+            gf.gf_decode(n, dev(Cm), dev(B), out, d_rank=rank)
+            torch.cuda.synchronize()
+            assert int(rank.item()) == r, (N, r)
+            if r == N:
+                assert (host(out) == S).all(), N
+            else:
+                assert (host(out) == 0x77).all(), N
+
+
+@pytest.mark.parametrize("n", FIELDS)
 @pytest.mark.parametrize("N", [2, 9, 64, 130])
 def test_decode_singular(gf, n, N):
     torch = torch_cuda()
