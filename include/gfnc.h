@@ -268,7 +268,9 @@ int gf_plan_launch(gf_plan *plan, int *d_rank, void *stream);
 /* Same work as gf_plan_launch, replayed from a HIP graph captured on first
  * use (d_rank must be the same pointer on every replay of a decode plan). */
 int gf_plan_launch_graph(gf_plan *plan, int *d_rank, void *stream);
-/* The schedule the plan uses (after autotuning). */
+/* The schedule the plan uses (after autotuning); grid_blocks is the number of
+ * workgroups a launch starts (for the non-persistent dispatches, one per four
+ * wave tiles or runs). */
 int gf_plan_tuning(const gf_plan *plan, gf_tuning *out);
 void gf_plan_destroy(gf_plan *plan);
 
@@ -326,7 +328,7 @@ typedef struct {
  * gf_plan_launch or gf_plan_launch_graph: one persistent launch over the
  * headers that are not stored in front of their payloads (if any), then one
  * over the payloads (with the headers that are), each autotuned like
- * gf_plan_encode (form 0 runs trials that write the outputs).
+ * gf_plan_encode (form 0 times its trials on scratch outputs).
  * gf_plan_tuning reports the payload launch's schedule. */
 int gf_plan_recode(int field, const gf_recode_desc *descs, int count, const gf_tuning *tune, gf_plan **out);
 
