@@ -1592,11 +1592,17 @@ __global__ __launch_bounds__(256) void k_small(const uint8_t *__restrict__ C, in
 // row pivot(j) of Csel^-1 is row j of T: the kernel writes Csel^-1 directly and
 // the step's payload product S = Csel^-1 * Bsel needs no separate inversion.
 //
-// During a step R and T live in LDS; packet descriptors are cached 64 at a time and the next packet's
-// coefficients are fetched while the current one is reduced, so the loop over
-// packets touches device memory only for those prefetches.  The innovative
-// packets' payloads are copied out after the loop.
-constexpr int ABSORB_PKC = 64;
+// During a step R and T live in LDS; the packets are taken ABSORB_PKC at a
+// time, their descriptors and coefficient vectors loaded into LDS together, so
+// the loop over packets touches device memory only at those refills.  A
+// packet costs three workgroup barriers (two when it is dropped): every wave
+// reduces the vector against its share of R's rows and XORs its partial sums
+// into one LDS accumulator with atomics; wave 0 alone finds the leading entry,
+// scales the row and, while the other waves clear the new pivot column from
+// R, sets up the next packet's accumulator.  The innovative packets' payloads
+// are copied out after the loop.
+constexpr int ABSORB_PKC = 32;
+
 // One workgroup per generation of 16 waves: the passes over R of each packet
 // split its rows 16 ways (a step has at most a few dozen such workgroups, so
 // each has a CU to itself).
@@ -1608,15 +1614,15 @@ __global__ __launch_bounds__(ABSORB_THREADS) void k_absorb(const DevAbsorb *__re
 {
     __shared__ uint32_t Rl[256 * 65];   // row r at Rl + 65 r (odd stride)
     __shared__ uint32_t Tl[256 * 65];   // transform rows, the same layout
-    __shared__ uint32_t cw[64], tw[64];
-    __shared__ uint32_t part[ABSORB_WAVES][64], tpart[ABSORB_WAVES][64];
+    __shared__ uint32_t cw[64], tw[64];   // the accepted packet's scaled vector and transform row
+    __shared__ uint32_t xacc[64], tacc[64];   // the current packet's reduction, summed by atomics
+    __shared__ uint32_t coefs[ABSORB_PKC][64];   // coefficient dwords of the cached packets
     __shared__ uint4 TB[256][2];
     __shared__ uint8_t IV[256];
-    __shared__ uint8_t fcol[256];
     __shared__ int pivc[256];
     __shared__ const uint8_t *row_pay[256];   // payloads of the rows added in this step
-    __shared__ DevPacket pkc[ABSORB_PKC];
-    __shared__ int cand[4];
+    __shared__ const uint8_t *pay_c[ABSORB_PKC];
+    __shared__ int s_lead;
     const DevAbsorb it = items[blockIdx.x];
     const DevDecSlot &s = it.s;
     const int N = (int)s.N, NW = (N + 3) >> 2;
@@ -1639,90 +1645,100 @@ __global__ __launch_bounds__(ABSORB_THREADS) void k_absorb(const DevAbsorb *__re
         Rl[r * 65 + w] = reinterpret_cast<const uint32_t *>(s.R + (uint64_t)r * s.rs)[w];
         Tl[r * 65 + w] = reinterpret_cast<const uint32_t *>(s.T + (uint64_t)r * s.rs)[w];
     }
-    // coefficient dword tid of a packet (lanes tid < NW)
-    auto coef_dword = [&](const uint8_t *c) {
-        uint32_t v = 0;
-        for (int b = 0; b < 4; b++)
-            if (4 * tid + b < N)
-                v |= (uint32_t)c[4 * tid + b] << (8 * b);
-        return v;
+    // descriptors and coefficient vectors of packets q0 .. q0 + ABSORB_PKC - 1 (dword w of
+    // packet p at coefs[p][w], bytes past N zero); ends with a barrier
+    auto refill = [&](uint32_t q0) {
+        for (int e = tid; e < ABSORB_PKC * 64; e += ABSORB_THREADS) {
+            const int p = e >> 6, w = e & 63;
+            uint32_t v = 0;
+            if (q0 + p < it.npk && w < NW) {
+                const uint8_t *c = pkts[it.pk0 + q0 + p].coef;
+#pragma unroll
+                for (int b = 0; b < 4; b++)
+                    if (4 * w + b < N)
+                        v |= (uint32_t)c[4 * w + b] << (8 * b);
+            }
+            coefs[p][w] = v;
+        }
+        if (tid < ABSORB_PKC && q0 + tid < it.npk)
+            pay_c[tid] = pkts[it.pk0 + q0 + tid].payload;
+        __syncthreads();
+    };
+    // wave 0: the reduction of packet slot p starts from its own vector and,
+    // in the transform, its unit weight at the next row's index
+    auto start_packet = [&](int p) {
+        if (wave == 0) {
+            xacc[lane] = coefs[p][lane];
+            tacc[lane] = lane == (rank >> 2) ? 1u << (8 * (rank & 3)) : 0u;
+        }
     };
     int seen = 0, dropped = 0;
-    uint32_t nextv = 0;
-    bool have_next = false;
+    if (it.npk > 0) {
+        refill(0);
+        start_packet(0);
+        __syncthreads();
+    }
 
     for (uint32_t q = 0; q < it.npk && rank < N; q++) {
         const int slot = (int)(q % ABSORB_PKC);
-        if (slot == 0) {
-            __syncthreads();   // every lane is done with the previous descriptors
-            if (tid < ABSORB_PKC && q + tid < it.npk)
-                pkc[tid] = pkts[it.pk0 + q + tid];
-            __syncthreads();
-        }
-        const DevPacket pk = pkc[slot];
-        if (tid < NW)
-            cw[tid] = have_next ? nextv : coef_dword(pk.coef);
-        // the next packet's coefficients, if its descriptor is cached, land during this one
-        have_next = slot + 1 < ABSORB_PKC && q + 1 < it.npk;
-        if (have_next && tid < NW)
-            nextv = coef_dword(pkc[slot + 1].coef);
-        __syncthreads();
-        for (int r = tid; r < rank; r += ABSORB_THREADS) {   // the vector's entry in each row's pivot column
-            const int pc = pivc[r];
-            fcol[r] = (uint8_t)(cw[pc >> 2] >> (8 * (pc & 3)));
-        }
-        __syncthreads();
-        if (lane < NW) {   // wave w sums rows w, w + W, ... of column dword `lane`, in R and in T
-            uint32_t acc = 0, tacc = 0;
+        // wave w sums rows w, w + W, ... of column dword `lane`, in R and in T; the
+        // factor of a row is the vector's entry in the row's pivot column (zero
+        // factors add zero products)
+        if (lane < NW) {
+            uint32_t acc = 0, tac = 0;
 #pragma unroll 4
-            for (int r = wave; r < rank; r += ABSORB_WAVES) {   // a zero factor adds a zero product
-                const uint32_t f = fcol[r];
+            for (int r = wave; r < rank; r += ABSORB_WAVES) {
+                const int pc = pivc[r];
+                const uint32_t f = (coefs[slot][pc >> 2] >> (8 * (pc & 3))) & 0xFFu;
                 acc ^= prod4(TB[f][0], TB[f][1].x, Rl[r * 65 + lane]);
-                tacc ^= prod4(TB[f][0], TB[f][1].x, Tl[r * 65 + lane]);
+                tac ^= prod4(TB[f][0], TB[f][1].x, Tl[r * 65 + lane]);
             }
-            part[wave][lane] = acc;
-            tpart[wave][lane] = tacc;
+            if (acc)
+                atomicXor(&xacc[lane], acc);
+            if (tac)
+                atomicXor(&tacc[lane], tac);
         }
         __syncthreads();
-        if (tid < NW) {
-            uint32_t x = cw[tid], t = 0;
-#pragma unroll
-            for (int w = 0; w < ABSORB_WAVES; w++) {
-                x ^= part[w][tid];
-                t ^= tpart[w][tid];
+        if (wave == 0) {   // leading entry, then the row scaled to a leading 1
+            uint32_t x = lane < NW ? xacc[lane] : 0u, t = lane < NW ? tacc[lane] : 0u;
+            const uint64_t m = __ballot(x != 0);
+            int lead = N;
+            if (m) {
+                const int l0 = (int)__builtin_ctzll(m);
+                const uint32_t x0 = (uint32_t)__builtin_amdgcn_readlane((int)x, l0);
+                lead = 4 * l0 + (int)(__builtin_ctz(x0) >> 3);
+                const uint32_t iv = IV[(x0 >> (8 * (lead & 3))) & 0xFFu];
+                x = prod4(TB[iv][0], TB[iv][1].x, x);
+                t = prod4(TB[iv][0], TB[iv][1].x, t);
+                if (lane < NW) {
+                    cw[lane] = x;
+                    tw[lane] = t;
+                }
             }
-            if (tid == (rank >> 2))
-                t ^= 1u << (8 * (rank & 3));   // the new packet's own unit weight
-            cw[tid] = x;
-            tw[tid] = t;
+            if (lane == 0)
+                s_lead = lead;
         }
         __syncthreads();
-        const bool nz = tid < N && ((cw[tid >> 2] >> (8 * (tid & 3))) & 0xFFu) != 0;
-        const uint64_t m = __ballot(nz);
-        if (lane == 0 && wave < 4)   // entries < 256 sit in the first four waves
-            cand[wave] = m ? wave * 64 + __builtin_ctzll(m) : (1 << 30);
-        __syncthreads();
-        const int lead = min(min(cand[0], cand[1]), min(cand[2], cand[3]));
+        const int lead = s_lead;
         seen++;
-        if (lead >= N) {
+        const bool next_cached = slot + 1 < ABSORB_PKC && q + 1 < it.npk;
+        if (lead >= N) {   // nothing new in this packet
             dropped++;
-            __syncthreads();
+            if (next_cached) {
+                start_packet(slot + 1);
+                __syncthreads();
+            } else if (q + 1 < it.npk) {
+                refill(q + 1);
+                start_packet(0);
+                __syncthreads();
+            }
             continue;
         }
-        if (tid < NW) {   // wave 0 reads the leading entry before any lane rewrites it
-            const uint32_t lv = (cw[lead >> 2] >> (8 * (lead & 3))) & 0xFFu;
-            const uint32_t iv = IV[lv];
-            cw[tid] = prod4(TB[iv][0], TB[iv][1].x, cw[tid]);
-            tw[tid] = prod4(TB[iv][0], TB[iv][1].x, tw[tid]);
-        }
-        for (int r = tid; r < rank; r += ABSORB_THREADS)
-            fcol[r] = Rb[r * 260 + lead];
-        __syncthreads();
         if (lane < NW) {   // wave w clears the new pivot column from rows w, w + W, ... (T alike)
             const uint32_t c = cw[lane], t = tw[lane];
 #pragma unroll 4
             for (int r = wave; r < rank; r += ABSORB_WAVES) {
-                const uint32_t f = fcol[r];
+                const uint32_t f = Rb[r * 260 + lead];   // read by the whole wave before its row changes
                 Rl[r * 65 + lane] ^= prod4(TB[f][0], TB[f][1].x, c);
                 Tl[r * 65 + lane] ^= prod4(TB[f][0], TB[f][1].x, t);
             }
@@ -1733,10 +1749,17 @@ __global__ __launch_bounds__(ABSORB_THREADS) void k_absorb(const DevAbsorb *__re
         }
         if (tid == 0) {
             pivc[rank] = lead;
-            row_pay[rank] = pk.payload;
+            row_pay[rank] = pay_c[slot];
         }
         rank++;
+        if (next_cached)
+            start_packet(slot + 1);
         __syncthreads();
+        if (!next_cached && q + 1 < it.npk && rank < N) {
+            refill(q + 1);
+            start_packet(0);
+            __syncthreads();
+        }
     }
     // R and T back to device memory; the new rows' payloads
     for (int i = tid; i < rank * NW; i += ABSORB_THREADS) {
