@@ -1438,9 +1438,10 @@ constexpr int REG_INV_MAX = 16;  // largest N inverted in one wave's registers
 // element whose inverse they multiply by), and every other row takes its
 // factor (its byte j) and the pivot row's dword from the lanes that hold them
 // (cross-lane permutes) and clears column j.  (Taking them with a DPP quad
-// broadcast and four scalar lane reads instead measured slower.)  The row swaps are undone as column swaps when the inverse is
-// written to Ci (N x N, row-major, LDS).  W (64 dwords) and P (16 ints) are LDS
-// scratch.  Returns N, or -1 when C is singular (Ci then unspecified).
+// broadcast and four scalar lane reads instead measured slower.)  The row
+// swaps are undone as column swaps when the inverse is written to Ci (N x N,
+// row-major, LDS).  W (64 dwords) and P (16 ints) are LDS scratch.  Returns N,
+// or -1 when C is singular (Ci then unspecified).
 __device__ int invert_wave_regs(const uint8_t *__restrict__ C, int N, uint8_t *Ci, const uint4 (*T)[2],
                                 const uint4 (*TI)[2], uint32_t *W, int *P)
 {
@@ -1597,10 +1598,10 @@ __global__ __launch_bounds__(256) void k_small(const uint8_t *__restrict__ C, in
 // the loop over packets touches device memory only at those refills.  A
 // packet costs three workgroup barriers (two when it is dropped): every wave
 // reduces the vector against its share of R's rows and XORs its partial sums
-// into one LDS accumulator with atomics; wave 0 alone finds the leading entry,
-// scales the row and, while the other waves clear the new pivot column from
-// R, sets up the next packet's accumulator.  The innovative packets' payloads
-// are copied out after the loop.
+// into one LDS accumulator with atomics; wave 0 alone finds the leading entry
+// and scales the row, and after its share of clearing the new pivot column
+// from R sets up the next packet's accumulator.  The innovative packets'
+// payloads are copied out after the loop.
 constexpr int ABSORB_PKC = 32;
 
 // One workgroup per generation of 16 waves: the passes over R of each packet
