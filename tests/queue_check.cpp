@@ -7,8 +7,13 @@
 //     rows and payload appears exactly once, nothing else appears;
 //   * table form: for every generation and 24-row block the tiles' strips
 //     cover [0, len) exactly once, in order, with the declared lane widths;
-//   * all tiles of one generation sit in one queue.
+//   * all tiles of one generation sit in one queue;
+//   * small-generation streaming form (queued) and its chunked form (one wave
+//     per tile, no queues): every generation's strips of 1 KiB covered once,
+//     in order, within the per-tile strip limit; the chunked runs of a
+//     generation differ in length by at most one strip.
 #include <cstdio>
+#include <algorithm>
 #include <cstdlib>
 #include <map>
 #include <random>
@@ -54,6 +59,47 @@ static void check_structure(const TileQueues &q, size_t ngen, const char *what)
                 else
                     CHECK(it->second == i, "%s: generation %u spans queues %d and %d", what, g, it->second, i);
             }
+}
+
+// Strips [p0, p0 + strips * 1 KiB) of each generation must cover [0, len)
+// once, in order, and every strip must start inside the row.
+static void check_strip_cover(const std::vector<DevTile> &tiles, const std::vector<DevGen> &g, int max_strips,
+                              bool equal_runs, const char *what)
+{
+    std::map<uint32_t, std::vector<std::pair<uint64_t, int>>> cover;
+    for (const DevTile &t : tiles) {
+        const int strips = (t.D >> 8) + 1;
+        CHECK((t.D & 0xFF) == 4, "%s: lane width %d", what, t.D & 0xFF);
+        CHECK(t.k0 == 0, "%s: tile starts at row %u", what, t.k0);
+        CHECK(strips <= max_strips, "%s: %d strips in a tile, at most %d", what, strips, max_strips);
+        CHECK(t.gen < g.size(), "%s: tile names generation %u of %zu", what, t.gen, g.size());
+        if (t.gen < g.size())
+            cover[t.gen].push_back({t.p0, strips});
+    }
+    for (size_t i = 0; i < g.size(); i++) {
+        auto it = cover.find((uint32_t)i);
+        if (!g[i].K || !g[i].len) {
+            CHECK(it == cover.end(), "%s: generation %zu has no work but has tiles", what, i);
+            continue;
+        }
+        CHECK(it != cover.end(), "%s: generation %zu not covered", what, i);
+        if (it == cover.end())
+            continue;
+        const auto &v = it->second;   // in the builders' order, which must be the row order
+        uint64_t at = 0;
+        int lo = 1 << 30, hi = 0;
+        for (const auto &s : v) {
+            CHECK(s.first == at, "%s: gen %zu gap, overlap or disorder at %llu", what, i, (unsigned long long)at);
+            CHECK(s.first < g[i].len, "%s: gen %zu has a tile past the end", what, i);
+            at = s.first + 1024ull * (uint64_t)s.second;
+            lo = std::min(lo, s.second);
+            hi = std::max(hi, s.second);
+        }
+        CHECK(at >= g[i].len && at < g[i].len + 1024, "%s: gen %zu ends at %llu for %llu bytes", what, i,
+              (unsigned long long)at, (unsigned long long)g[i].len);
+        if (equal_runs)
+            CHECK(hi - lo <= 1, "%s: gen %zu runs of %d to %d strips", what, i, lo, hi);
+    }
 }
 
 int main()
@@ -120,6 +166,29 @@ int main()
                           (unsigned long long)at, (unsigned long long)g[i].len);
                     CHECK(v.back().first < g[i].len, "table: gen %zu rows %u has a tile past the end", i, k0);
                 }
+            }
+        }
+        // small-generation streaming form, queued and chunked
+        {
+            std::vector<DevGen> sg = g;
+            for (DevGen &x : sg) {
+                x.K = x.K ? 1 + x.K % STREAM_MAX : 0;
+                x.N = 1 + x.N % STREAM_MAX;
+                if (rng() % 8 == 0)
+                    x.len = 1024 * (1 + rng() % 200) + rng() % 3;   // lengths near whole strips
+            }
+            TileQueues q;
+            build_tiles_stream(sg.data(), n, q);
+            check_structure(q, n, "stream");
+            check_strip_cover(q.tiles, sg, STREAM_STRIPS, false, "stream");
+            for (int sk : {1, 2, 4, 8}) {
+                const int burst = encode_chunks_strips(sk);
+                CHECK(burst >= 1, "chunks: %d strips per tile for K %d", burst, sk);
+                std::vector<DevTile> tiles;
+                build_tiles_chunks(sg.data(), n, burst, tiles);
+                check_strip_cover(tiles, sg, burst, true, "chunks");
+                for (size_t t = 1; t < tiles.size(); t++)
+                    CHECK(tiles[t - 1].gen <= tiles[t].gen, "chunks: tiles out of generation order at %zu", t);
             }
         }
     }
